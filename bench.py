@@ -1,0 +1,203 @@
+"""Benchmark of the UV-decomposition ADMM sweep on one MI355X.
+
+Workload (default ``lp_large``): random sparse standard-form LP, m = 1e6,
+n = 2e6, 10 nonzeros per column at distinct uniform rows, N(0,1) values, rows
+scaled to unit 2-norm, b = A x0 and c = A'y0 + s0 from a complementary pair
+(seeded synthetic data).  A step is one ADMM iteration (column pass + row
+pass, with the FP64 residual check every ``check_every`` iterations).
+
+Printed: one JSON line with iterations/s of the FP64 solver (``value``), the
+time to a 1e-4 relative KKT residual, the same for the mixed-precision form,
+the roofline of the dominant kernel (algorithmic bytes / measured duration,
+timed with HIP events on the solver's stream) and the CPU oracle's rate on a
+bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def alg_bytes(m, n, nnz, precision):
+    """Algorithmic bytes per launch of the row and column passes: every array
+    counted once, gathered vectors at their compulsory size, int32 indices."""
+    if precision == "fp64":
+        row = 12 * nnz + 4 * (m + 1) + 8 * n + 8 * m + 8 * m + 16 * m + 8 * m
+        col = 12 * nnz + 4 * (n + 1) + 8 * m + 8 * n + 24 * n + 24 * n
+    else:  # FP32 A, x, z, u, b, c, F_U; FP64 lambda, delta
+        row = 8 * nnz + 4 * (m + 1) + 4 * n + 4 * m + 4 * m + 16 * m + 4 * m
+        col = 8 * nnz + 4 * (n + 1) + 4 * m + 4 * n + 4 * n + 8 * n + 4 * n + 4 * n + 4 * n + 8 * n
+    return row, col
+
+
+def measure(inst, precision, steps, warmup, check_every, ttk_cap, mu, ttk=True):
+    import torch
+    from paper_2203_05027_amd.solver import Solver
+
+    out = {}
+    t0 = time.time()
+    s = Solver.from_instance(inst, mu=mu, precision=precision, eps=0.0,
+                             check_every=check_every)
+    out["create_s"] = time.time() - t0
+    lr, lc = s.launch_shape()
+    out["lanes_row"], out["lanes_col"] = lr, lc
+    s.iterate(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.iterate(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["ms_per_step"] = dt * 1e3 / steps
+    out["iters_per_s"] = steps / dt
+    out["kkt_after"] = s.residuals()["kkt"]
+    ms_col, ms_row = s.time_kernels(min(200, max(steps // 5, 20)))
+    out["ms_col"], out["ms_row"] = ms_col, ms_row
+    s.close()
+    if not ttk:
+        out.update(ttk_s=None, ttk_iters=None, ttk_status="skipped", ttk_kkt=None, ttk_pobj=None)
+        return out
+
+    # time to 1e-4 relative KKT from the zero start
+    s = Solver.from_instance(inst, mu=mu, precision=precision, eps=1e-4,
+                             check_every=check_every, max_iter=ttk_cap)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chunk = 2000
+    while not s.iterate(chunk):
+        pass
+    torch.cuda.synchronize()
+    r = s.residuals()
+    out["ttk_s"] = time.perf_counter() - t0
+    out["ttk_iters"] = r["iter"]
+    out["ttk_status"] = r["status"]
+    out["ttk_kkt"] = r["kkt"]
+    out["ttk_pobj"] = r["pobj"]
+    s.close()
+    return out
+
+
+def cpu_baseline(inst, mu, seconds):
+    import oracle
+
+    orc = oracle.Oracle.from_instance(inst, mu=mu)
+    orc.iterate(1)                       # first touch of the o-space arrays
+    t0 = time.perf_counter()
+    k = 0
+    while time.perf_counter() - t0 < seconds:
+        orc.iterate(1)
+        k += 1
+    dt = time.perf_counter() - t0
+    return {"value": k / dt, "unit": "iter/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{k} FP64 iterations of the literal Algorithm 1 oracle on the full "
+                      f"workload (timed {dt:.1f} s after one untimed iteration)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="lp_large")
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--check-every", type=int, default=10)
+    ap.add_argument("--mu", type=float, default=1.0)
+    ap.add_argument("--ttk-cap", type=int, default=200_000)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-ttk", action="store_true", help="skip the time-to-1e-4 runs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this solver runs on one GPU; multi-GPU runs are not part of this "
+              "build (see DESIGN.md for how the sweep would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2203_05027_amd import instances as I
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    t0 = time.time()
+    inst = I.config_instance(args.workload, scale=args.scale)
+    m, n, nnz = inst["m"], inst["n"], inst["nnz"]
+    log(f"workload {args.workload} m={m} n={n} nnz={nnz} generated in {time.time() - t0:.1f} s")
+
+    res = {}
+    for prec in (["fp64"] if args.no_mixed else ["fp64", "mixed"]):
+        log(f"measuring {prec}")
+        res[prec] = measure(inst, prec, args.steps, args.warmup, args.check_every,
+                            args.ttk_cap, args.mu, ttk=not args.no_ttk)
+        log(f"{prec}: {json.dumps(res[prec])}")
+
+    main_r = res["fp64"]
+    row_b, col_b = alg_bytes(m, n, nnz, "fp64")
+    kern = {"col": (col_b, main_r["ms_col"]), "row": (row_b, main_r["ms_row"])}
+    dom = max(kern, key=lambda k: kern[k][1])
+    achieved = kern[dom][0] / (kern[dom][1] * 1e-3) / 1e9
+    sweep_gbs = (row_b + col_b) / ((main_r["ms_col"] + main_r["ms_row"]) * 1e-3) / 1e9
+
+    cpu = None
+    if not args.no_cpu:
+        log("timing the CPU oracle")
+        cpu = cpu_baseline(inst, args.mu, args.cpu_seconds)
+
+    extra = {}
+    if "mixed" in res:
+        mr = res["mixed"]
+        rb, cb = alg_bytes(m, n, nnz, "mixed")
+        extra = {
+            "iters_per_s": mr["iters_per_s"], "ms_per_step": mr["ms_per_step"],
+            "time_to_1e-4_s": mr["ttk_s"], "iters_to_1e-4": mr["ttk_iters"],
+            "status": mr["ttk_status"], "pobj": mr["ttk_pobj"],
+            "ms_col": mr["ms_col"], "ms_row": mr["ms_row"],
+            "sweep_GBs": (rb + cb) / ((mr["ms_col"] + mr["ms_row"]) * 1e-3) / 1e9,
+        }
+    line = {
+        "metric": "iters/s of the FP64 ADMM sweep (time-to-1e-4 KKT and HBM GB/s alongside)",
+        "value": main_r["iters_per_s"],
+        "unit": "iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: LP m={m} n={n} nnz={nnz}, unit-norm rows, "
+                               f"orthant cone, mu={args.mu}, check_every={args.check_every}",
+                   "lanes_row": main_r["lanes_row"], "lanes_col": main_r["lanes_col"]},
+        "time_to_1e-4_s": main_r["ttk_s"],
+        "iters_to_1e-4": main_r["ttk_iters"],
+        "ttk_status": main_r["ttk_status"],
+        "ttk_pobj": main_r["ttk_pobj"],
+        "p_star": inst.get("p_star"),
+        "sweep_GBs": sweep_gbs,
+        "kernels_ms": {"col": main_r["ms_col"], "row": main_r["ms_row"]},
+        "roofline": {"bound": "hbm", "kernel": f"k_col_orth" if dom == "col" else "k_row",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "mixed": extra,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/*
+ * uvadmm.h -- C ABI of the MI355X (gfx950) UV-decomposition ADMM conic solver.
+ *
+ * Solves  minimize c'x  subject to  A x = b,  x in K            (Section II,
+ * eq. prob_primal) with K = R_+^{n_orthant} x K_{s_1} x ... x K_{s_q}, a
+ * product of Lorentz cones K_s = { w in R^s : w_1 >= ||(w_2..w_s)||_2 } (the
+ * orthant coordinates are cones of size 1), by the two-block ADMM on the
+ * UV-decomposed reformulation (Section IV, eq. prob_reform, Algorithm 1).
+ *
+ * Every iteration is a closed-form sweep (Algorithm 1, repeat block):
+ *   x-step (Block 1, eq. vvt), y-step with the matrix inversion lemma
+ *   (Block 2), z-step = projection onto K (eq. proj), dual updates.
+ * The library runs it in an algebraically equivalent reduced form that keeps
+ * no per-nonzero vectors: gamma = -U'lambda holds after every iteration, so
+ * y and gamma are never stored, and an iteration is one pass over A in
+ * column-major order (A'u, x-step, projection, delta update) and one in
+ * row-major order (A x, lambda update).
+ *
+ * Conventions for every entry point:
+ *  - All pointers passed in are HOST pointers unless stated otherwise.  The
+ *    library copies what it needs during the call; the caller keeps
+ *    ownership of its buffers and may free them as soon as the call returns.
+ *  - Every int-returning function returns UV_OK (0) or a negative UV_E* code;
+ *    solver_strerror() names it.  On error no state is changed unless stated.
+ *  - The returned multiplier lambda is the paper's: it multiplies U y = b in
+ *    the augmented Lagrangian (eq. lll), so the textbook dual variable of
+ *    A x = b is -lambda, the dual objective is -b'lambda and the gap is
+ *    c'x + b'lambda.
+ *  - Device work is ordered on one HIP stream (opts.hip_stream, or a stream
+ *    the library creates when it is NULL).  A solver handle must not be used
+ *    from two host threads at once.
+ */
+#ifndef UVADMM_H
+#define UVADMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Error codes. */
+#define UV_OK        0
+#define UV_EINVAL   -1  /* null pointer, mu <= 0, m < 1, n < 1, bad option */
+#define UV_EBADCSR  -2  /* row_ptr not starting at 0 / not monotone / not ending
+                           at nnz, column index out of range, or column indices
+                           not strictly increasing within a row */
+#define UV_ECONE    -3  /* cone sizes do not sum to n, a size < 1, or a
+                           second-order cone larger than UV_MAX_CONE */
+#define UV_ENOMEM   -4  /* device or pinned-host allocation failed */
+#define UV_EHIP     -5  /* a HIP runtime call failed */
+#define UV_ENUMERIC -6  /* NaN or Inf met in a residual check */
+#define UV_ETOOBIG  -7  /* nnz >= 2^31 (device indices are 32-bit) */
+
+/* Largest second-order cone handled (one workgroup projects a cone). */
+#define UV_MAX_CONE 1024
+
+/* Arithmetic of the sweep. */
+#define UV_FP64  0   /* everything in FP64 */
+#define UV_MIXED 1   /* A, x, z, u, b, c in FP32 for the sweep; lambda and
+                        delta accumulate in FP64; residuals in FP64 with the
+                        FP64 values of A */
+
+/* Solver status (uv_residuals.status). */
+#define UV_STATUS_RUNNING   0
+#define UV_STATUS_CONVERGED 1  /* kkt <= eps_kkt at a check */
+#define UV_STATUS_MAX_ITER  2  /* max_iter reached without convergence */
+#define UV_STATUS_NUMERIC   3  /* NaN/Inf seen at a check; iteration stopped */
+
+/* A in compressed sparse row form: row i holds the entries
+ * col_idx[row_ptr[i] .. row_ptr[i+1]-1] with values val[...].  Column
+ * indices strictly increase within a row.  Explicitly stored zeros are kept
+ * as entries (they are still a valid UV decomposition: their column of U is
+ * zero and they count in V V'). */
+typedef struct {
+    int32_t m, n;            /* rows (constraints), columns (variables) */
+    int64_t nnz;             /* stored entries, row_ptr[m] */
+    const int64_t *row_ptr;  /* m + 1 entries */
+    const int32_t *col_idx;  /* nnz entries */
+    const double *val;       /* nnz entries */
+} uv_csr;
+
+/* K: the first n_orthant coordinates are nonnegative; then n_soc Lorentz
+ * cones of sizes soc_sizes[0..n_soc-1] follow in order, each with its
+ * "t" coordinate first (Section II).  n_orthant + sum(soc_sizes) == n. */
+typedef struct {
+    int32_t n_orthant;
+    int32_t n_soc;
+    const int32_t *soc_sizes;
+} uv_cones;
+
+typedef struct {
+    double mu;            /* ADMM penalty, > 0 (Algorithm 1 takes a fixed mu) */
+    int32_t precision;    /* UV_FP64 or UV_MIXED */
+    int32_t check_every;  /* residual check every this many iterations (>= 1) */
+    double eps_kkt;       /* stop when kkt <= eps_kkt at a check (0 = never) */
+    int64_t max_iter;     /* cap on the total iteration count (0 = none) */
+    void *hip_stream;     /* hipStream_t to order all device work on, or NULL */
+    int32_t lanes_row;    /* lanes per row in the A x pass (0 = automatic;
+                             else 1, 2, 4, 8, 16, 32 or 64) */
+    int32_t lanes_col;    /* lanes per column in the A'u pass (same values) */
+    int32_t use_graph;    /* 1 = replay check_every iterations as one captured
+                             HIP graph; 0 = launch kernels one by one */
+} uv_opts;
+
+/* Residuals at the last check, evaluated at (z, lambda, delta), all FP64
+ * (the SCS-form test of Section V-B, with the dual residual taken for
+ * x in K and an absolute gap):
+ *   r_prim = ||A z - b|| / (1 + ||b||)
+ *   r_dual = ||A'lambda + c - delta|| / (1 + ||c||)
+ *   r_gap  = |c'z + b'lambda| / (1 + |c'z| + |b'lambda|)
+ *   kkt    = max(r_prim, r_dual, r_gap)
+ * pobj = c'z, dobj = -b'lambda, res_ax_b = ||A x - b|| (at x, as printed). */
+typedef struct {
+    double r_prim, r_dual, r_gap, kkt;
+    double pobj, dobj;
+    double res_ax_b;
+    int64_t iter;         /* iterations done when these were evaluated */
+    int32_t status;       /* UV_STATUS_* */
+} uv_residuals;
+
+typedef struct uv_solver uv_solver;
+
+/* Fills *o with the defaults: mu = 1, UV_FP64, check_every = 10,
+ * eps_kkt = 1e-4, max_iter = 0, NULL stream, automatic lanes, graphs on. */
+void uv_default_opts(uv_opts *o);
+
+/* Validates and copies the problem to the device, builds the column-major
+ * copy of A and the diagonal factors F_U = (I + U U')^{-1} and
+ * F_V = (I + V V')^{-1} (Algorithm 1, steps 1-3; U U' = diag of the squared
+ * row norms of A and V V' = diag of the column counts), and sets the zero
+ * start.  b has m entries, c has n.  opts may be NULL (defaults).  On
+ * success *out owns device memory until solver_destroy. */
+int solver_create(const uv_csr *A, const double *b, const double *c,
+                  const uv_cones *K, const uv_opts *opts, uv_solver **out);
+
+/* Sets the starting point (Algorithm 1's "initial points"): x, z, delta
+ * (n entries) and lambda (m entries), any of them NULL for zero.  The
+ * per-nonzero variables start at y = V'x and gamma = -U'lambda.  Resets the
+ * iteration count and the status. */
+int solver_set_start(uv_solver *s, const double *x, const double *z,
+                     const double *delta, const double *lambda);
+
+/* Restores a state returned by solver_solution so that iterating continues
+ * the interrupted run (checkpoint / resume).  The iterate (x, z, delta,
+ * lambda) at the end of an iteration fixes the per-nonzero variables too:
+ * gamma = -U'lambda, and y is the y-step's output at x with that gamma,
+ * y = (I - U'F_U U)(U'b + V'x) (Block 2 with the matrix inversion lemma).
+ * (solver_set_start instead takes y = V'x, the plain starting point.)
+ * Resets the iteration count and the status; NULL means zero. */
+int solver_resume(uv_solver *s, const double *x, const double *z,
+                  const double *delta, const double *lambda);
+
+/* Runs up to k iterations (fewer if kkt <= eps_kkt at a check, or max_iter
+ * is reached) and waits for them.  Checks happen when the total iteration
+ * count is a multiple of check_every.  *done (may be NULL) is set to 1 when
+ * the solver has stopped (converged, max_iter, or numeric failure). */
+int solver_iterate(uv_solver *s, int64_t k, int32_t *done);
+
+/* Residuals of the current iterate (evaluated now if the state changed
+ * since the last check). */
+int solver_residuals(uv_solver *s, uv_residuals *r);
+
+/* Copies the current iterate to caller-owned host buffers: x, z, delta
+ * (n doubles each), lambda (m doubles); any may be NULL. */
+int solver_solution(uv_solver *s, double *x, double *z, double *lambda,
+                    double *delta);
+
+/* Frees everything the handle owns.  NULL is ignored. */
+void solver_destroy(uv_solver *s);
+
+/* Static string for a UV_E* code. */
+const char *solver_strerror(int code);
+
+/* Measurement: runs `iters` iterations (no residual checks), timing every
+ * kernel launch with HIP events on the solver's stream, and returns the
+ * average duration in milliseconds of the column pass (A'u, x-step,
+ * projection, delta update) and of the row pass (A x, lambda update). */
+int solver_time_kernels(uv_solver *s, int32_t iters, double *ms_col,
+                        double *ms_row);
+
+/* The resolved launch shape: lanes per row and per column. */
+int solver_launch_shape(const uv_solver *s, int32_t *lanes_row,
+                        int32_t *lanes_col);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UVADMM_H */

@@ -58,6 +58,8 @@ def _load():
     lib.orc_set_state.restype = None
     lib.orc_set_start.argtypes = [P, P, P, P, P]
     lib.orc_set_start.restype = None
+    lib.orc_resume.argtypes = [P, P, P, P, P]
+    lib.orc_resume.restype = None
     lib.orc_get_state.argtypes = [P, P, P, P, P, P, P]
     lib.orc_get_state.restype = None
     lib.orc_iteration.argtypes = [P]
@@ -166,6 +168,11 @@ class Oracle:
     def set_start(self, x=None, z=None, delta=None, lam=None):
         args = [_f64(v) for v in (x, z, delta, lam)]
         self._lib.orc_set_start(self._h, *[_ptr(a) for a in args])
+
+    def resume(self, x=None, z=None, delta=None, lam=None):
+        """State at the end of an iteration from (x, z, delta, lambda)."""
+        args = [_f64(v) for v in (x, z, delta, lam)]
+        self._lib.orc_resume(self._h, *[_ptr(a) for a in args])
 
     def state(self):
         x, z, d = np.empty(self.n), np.empty(self.n), np.empty(self.n)

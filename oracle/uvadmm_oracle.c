@@ -296,6 +296,44 @@ void orc_get_state(const orc_t *h, double *x, double *z, double *delta,
 
 int64_t orc_iteration(const orc_t *h) { return h->iter; }
 
+static void y_step(orc_t *h);
+
+/* The full state at the end of an iteration from its problem-space part
+ * (x, z, delta, lambda): every iteration leaves gamma = -U'lambda (the
+ * y-step's optimality condition combined with the lambda and gamma
+ * updates), and y is the y-step's output at this x with that gamma. */
+void orc_resume(orc_t *h, const double *x, const double *z, const double *delta,
+                const double *lambda)
+{
+    orc_set_state(h, x, z, delta, NULL, NULL, lambda);
+    #pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < h->o; ++k) h->gamma[k] = -h->ak[k] * h->lambda[h->rk[k]];
+    y_step(h);
+}
+
+/* Step 6 (Block 2, y-step) at the current x, lambda, gamma:
+ *   t = U'(b - lambda/mu) + V'x - gamma/mu,   t_k = a_k (b - lambda/mu)_{i_k} + x_{j_k} - gamma_k/mu
+ *   y = (I - U' F_U U) t = t - U'(F_U (U t)). */
+static void y_step(orc_t *h)
+{
+    const int32_t m = h->m;
+    const int64_t o = h->o;
+    const double mu = h->mu;
+    #pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < o; ++k) {
+        int32_t i = h->rk[k];
+        h->t[k] = h->ak[k] * (h->b[i] - h->lambda[i] / mu) + h->x[h->ck[k]] - h->gamma[k] / mu;
+    }
+    #pragma omp parallel for schedule(static)
+    for (int32_t i = 0; i < m; ++i) {
+        double ut = 0.0;
+        for (int64_t k = h->row_ptr[i]; k < h->row_ptr[i + 1]; ++k) ut += h->ak[k] * h->t[k];
+        h->s[i] = h->FU[i] * ut;
+    }
+    #pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < o; ++k) h->y[k] = h->t[k] - h->ak[k] * h->s[h->rk[k]];
+}
+
 /* One pass of Algorithm 1's repeat block. */
 static void iterate_once(orc_t *h)
 {
@@ -315,22 +353,7 @@ static void iterate_once(orc_t *h)
         h->x[j] = h->FV[j] * (vy + h->z[j] + h->delta[j] / mu - h->c[j] / mu);
     }
 
-    /* Step 6 (Block 2, y-step):
-     *   t = U'(b - lambda/mu) + V'x - gamma/mu,   t_k = a_k (b - lambda/mu)_{i_k} + x_{j_k} - gamma_k/mu
-     *   y = (I - U' F_U U) t = t - U'(F_U (U t)). */
-    #pragma omp parallel for schedule(static)
-    for (int64_t k = 0; k < o; ++k) {
-        int32_t i = h->rk[k];
-        h->t[k] = h->ak[k] * (h->b[i] - h->lambda[i] / mu) + h->x[h->ck[k]] - h->gamma[k] / mu;
-    }
-    #pragma omp parallel for schedule(static)
-    for (int32_t i = 0; i < m; ++i) {
-        double ut = 0.0;
-        for (int64_t k = h->row_ptr[i]; k < h->row_ptr[i + 1]; ++k) ut += h->ak[k] * h->t[k];
-        h->s[i] = h->FU[i] * ut;
-    }
-    #pragma omp parallel for schedule(static)
-    for (int64_t k = 0; k < o; ++k) h->y[k] = h->t[k] - h->ak[k] * h->s[h->rk[k]];
+    y_step(h);
 
     /* Step 7 (Block 2, z-step): z = proj_K(x - delta/mu). */
     #pragma omp parallel for schedule(static)

@@ -1,0 +1,1095 @@
+// solver.hip -- single-problem UV-decomposition ADMM on gfx950.
+//
+// The iteration is Algorithm 1's repeat block (Section IV) in a reduced form
+// that stores no per-nonzero vectors.  The y-step's optimality condition and
+// the two dual updates of lambda and gamma give U'lambda + gamma = 0 after
+// every iteration, so with gamma = -U'lambda:
+//   * U y - b = F_U (A x - b)           -> lambda <- lambda + mu F_U (A x - b)
+//   * V(y + gamma/mu) = N x + A'u,  u = F_U (b - A x) - lambda/mu
+// where N = V V' (column counts) and F_U = (I + U U')^{-1} (U U' = squared
+// row norms).  Hence one iteration is
+//   column pass (CSC):  p = N x + A'u;  x = F_V (p + z + delta/mu - c/mu);
+//                       z = proj_K(x - delta/mu);  delta += mu (z - x)
+//   row pass    (CSR):  q = A x;  e = F_U (b - q);  lambda -= mu e;
+//                       u = e - lambda/mu
+// The first column pass after a start (x0, lambda0) needs
+// V(y0 + gamma0/mu) with y0 = V'x0, gamma0 = -U'lambda0, which is N x0 + A'u
+// with u = -lambda0/mu; a start therefore only sets x and u.
+//
+// Residual checks (Section V-B, SCS form; see uvadmm.h) reduce in FP64 into
+// per-workgroup partials that one workgroup then adds in a fixed order, so
+// every run is bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/uvadmm.h"
+#include "common.hpp"
+
+using uv::kWG;
+
+namespace {
+
+// Device-side status, copied to pinned host memory after every call.
+struct DevStatus {
+    double r_prim, r_dual, r_gap, kkt, pobj, dobj, res_ax_b;
+    double bnorm2, cnorm2;
+    long long iter;        // iterations done
+    long long check_iter;  // iteration count at the last residual evaluation
+    int done;              // 1 = stop: every sweep kernel returns at once
+    int status;            // UV_STATUS_*
+};
+
+constexpr int kSocTile = 256;  // columns per SOC tile when cones are small
+
+// ---------------------------------------------------------------------------
+// Setup kernels (Algorithm 1, steps 1-3)
+// ---------------------------------------------------------------------------
+
+// F_U[i] = 1 / (1 + sum_j A_ij^2)   (U U' is diagonal: squared row norms)
+template <typename T>
+__global__ void __launch_bounds__(kWG)
+k_row_factor(int m, const int *__restrict__ rp, const double *__restrict__ va, T *__restrict__ fu)
+{
+    int i = blockIdx.x * kWG + threadIdx.x;
+    if (i >= m) return;
+    double d = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) d += va[k] * va[k];
+    fu[i] = (T)(1.0 / (1.0 + d));
+}
+
+// Column-major copy of A (the pattern of V): count, scan, scatter, then a
+// per-column sort by row so the layout is deterministic.
+__global__ void __launch_bounds__(kWG)
+k_col_count(int nnz, const int *__restrict__ ci, int *__restrict__ cnt)
+{
+    int k = blockIdx.x * kWG + threadIdx.x;
+    if (k < nnz) atomicAdd(&cnt[ci[k]], 1);
+}
+
+// Inclusive scan of 4*kWG items per workgroup; block totals to bsum.
+__global__ void __launch_bounds__(kWG)
+k_scan_local(int n, const int *__restrict__ in, int *__restrict__ out, int *__restrict__ bsum)
+{
+    __shared__ int s[kWG];
+    const int base = blockIdx.x * 4 * kWG + threadIdx.x * 4;
+    int v[4], t = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        v[r] = (base + r < n) ? in[base + r] : 0;
+        t += v[r];
+        v[r] = t;
+    }
+    s[threadIdx.x] = t;
+    __syncthreads();
+    for (int off = 1; off < kWG; off <<= 1) {
+        int a = (threadIdx.x >= off) ? s[threadIdx.x - off] : 0;
+        __syncthreads();
+        s[threadIdx.x] += a;
+        __syncthreads();
+    }
+    int excl = s[threadIdx.x] - t;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if (base + r < n) out[base + r] = v[r] + excl;
+    if (threadIdx.x == kWG - 1) bsum[blockIdx.x] = s[kWG - 1];
+}
+
+// Exclusive scan of the block totals, one workgroup, chunk by chunk.
+__global__ void __launch_bounds__(kWG) k_scan_blocks(int nb, int *__restrict__ bsum)
+{
+    __shared__ int s[kWG];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nb; base += kWG) {
+        int i = base + threadIdx.x;
+        int v = (i < nb) ? bsum[i] : 0;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < kWG; off <<= 1) {
+            int a = (threadIdx.x >= off) ? s[threadIdx.x - off] : 0;
+            __syncthreads();
+            s[threadIdx.x] += a;
+            __syncthreads();
+        }
+        if (i < nb) bsum[i] = carry + s[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == kWG - 1) carry += s[kWG - 1];
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kWG)
+k_scan_add(int n, int *__restrict__ out, const int *__restrict__ bsum)
+{
+    int i = blockIdx.x * kWG + threadIdx.x;
+    if (i < n) out[i] += bsum[i / (4 * kWG)];
+}
+
+__global__ void __launch_bounds__(kWG)
+k_col_scatter(int m, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ va,
+              const int *__restrict__ cp, int *__restrict__ fill, int *__restrict__ ri, double *__restrict__ vc)
+{
+    int i = blockIdx.x * kWG + threadIdx.x;
+    if (i >= m) return;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+        int j = ci[k];
+        int pos = cp[j] + atomicAdd(&fill[j], 1);
+        ri[pos] = i;
+        vc[pos] = va[k];
+    }
+}
+
+__device__ void sift_down(int *key, double *val, int root, int len)
+{
+    for (;;) {
+        int child = 2 * root + 1;
+        if (child >= len) return;
+        if (child + 1 < len && key[child + 1] > key[child]) ++child;
+        if (key[root] >= key[child]) return;
+        int tk = key[root]; key[root] = key[child]; key[child] = tk;
+        double tv = val[root]; val[root] = val[child]; val[child] = tv;
+        root = child;
+    }
+}
+
+// Sorts each column's (row, value) pairs by row: insertion sort for short
+// columns, heapsort otherwise (rows within a column are distinct).
+__global__ void __launch_bounds__(kWG)
+k_col_sort(int n, const int *__restrict__ cp, int *__restrict__ ri, double *__restrict__ vc)
+{
+    int j = blockIdx.x * kWG + threadIdx.x;
+    if (j >= n) return;
+    int *key = ri + cp[j];
+    double *val = vc + cp[j];
+    int len = cp[j + 1] - cp[j];
+    if (len <= 32) {
+        for (int a = 1; a < len; ++a) {
+            int kk = key[a];
+            double vv = val[a];
+            int p = a - 1;
+            while (p >= 0 && key[p] > kk) { key[p + 1] = key[p]; val[p + 1] = val[p]; --p; }
+            key[p + 1] = kk;
+            val[p + 1] = vv;
+        }
+        return;
+    }
+    for (int r = len / 2 - 1; r >= 0; --r) sift_down(key, val, r, len);
+    for (int e = len - 1; e > 0; --e) {
+        int tk = key[0]; key[0] = key[e]; key[e] = tk;
+        double tv = val[0]; val[0] = val[e]; val[e] = tv;
+        sift_down(key, val, 0, e);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kWG) k_narrow(int64_t len, const double *__restrict__ src, T *__restrict__ dst)
+{
+    int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (i < len) dst[i] = (T)src[i];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kWG) k_widen(int64_t len, const T *__restrict__ src, double *__restrict__ dst)
+{
+    int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (i < len) dst[i] = (double)src[i];
+}
+
+// ||b||^2 and ||c||^2 in FP64 (one workgroup, fixed order).
+__global__ void __launch_bounds__(kWG)
+k_norms(int m, const double *__restrict__ b, int n, const double *__restrict__ c, DevStatus *st)
+{
+    double v[2] = {0.0, 0.0};
+    for (int i = threadIdx.x; i < m; i += kWG) v[0] += b[i] * b[i];
+    for (int j = threadIdx.x; j < n; j += kWG) v[1] += c[j] * c[j];
+    double out[2];
+    uv::block_sum<2>(v, out);
+    if (threadIdx.x == 0) { st->bnorm2 = out[0]; st->cnorm2 = out[1]; }
+}
+
+// Start: u = -lambda/mu (see the header comment), iteration state reset.
+template <typename T>
+__global__ void __launch_bounds__(kWG)
+k_start(int m, const double *__restrict__ lam, T *__restrict__ u, double inv_mu, DevStatus *st)
+{
+    int i = blockIdx.x * kWG + threadIdx.x;
+    if (i < m) u[i] = (T)(-lam[i] * inv_mu);
+    if (i == 0) {
+        st->iter = 0;
+        st->check_iter = -1;
+        st->done = 0;
+        st->status = UV_STATUS_RUNNING;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Sweep kernels
+// ---------------------------------------------------------------------------
+
+// Dot product of one sparse row/column segment [beg, end) with a gathered
+// vector, L lanes cooperating (lane-strided, 2-way unrolled so two gathers
+// are in flight per lane).
+template <int L, typename T, typename TV>
+__device__ __forceinline__ T seg_dot(int beg, int end, int lane, const int *__restrict__ idx,
+                                     const TV *__restrict__ val, const T *__restrict__ vec)
+{
+    T a0 = 0, a1 = 0;
+    int k = beg + lane;
+    for (; k + L < end; k += 2 * L) {
+        int j0 = idx[k], j1 = idx[k + L];
+        TV v0 = val[k], v1 = val[k + L];
+        a0 += (T)v0 * vec[j0];
+        a1 += (T)v1 * vec[j1];
+    }
+    if (k < end) a0 += (T)val[k] * vec[idx[k]];
+    return uv::group_sum<L>(a0 + a1);
+}
+
+// Row pass.  MODE 0: iterate.  MODE 1: iterate and gather z for the
+// residual partials (||A z - b||^2, b'lambda, ||A x - b||^2) of the new
+// lambda.  MODE 2 (resume): u = F_U (b - A x) - lambda/mu with lambda kept,
+// which is the u an iteration leaves behind at this (x, lambda).
+template <typename T, int L, int MODE>
+__global__ void __launch_bounds__(kWG)
+k_row(int m, const int *__restrict__ rp, const int *__restrict__ ci, const T *__restrict__ va,
+      const T *__restrict__ x, const T *__restrict__ z, const T *__restrict__ b, const T *__restrict__ fu,
+      double *__restrict__ lam, T *__restrict__ u, double mu, double inv_mu, double *__restrict__ part,
+      DevStatus *st)
+{
+    if (MODE != 2 && st->done) return;
+    const int lane = threadIdx.x & (L - 1);
+    const int row = blockIdx.x * (kWG / L) + threadIdx.x / L;
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (row < m) {
+        const int beg = rp[row], end = rp[row + 1];
+        T q = seg_dot<L>(beg, end, lane, ci, va, x);
+        T qz = 0;
+        if (MODE == 1) qz = seg_dot<L>(beg, end, lane, ci, va, z);
+        if (lane == 0) {
+            const T bi = b[row];
+            const T e = fu[row] * (bi - q);
+            const double li = (MODE == 2) ? lam[row] : lam[row] - mu * (double)e;
+            if (MODE != 2) lam[row] = li;
+            u[row] = (T)((double)e - li * inv_mu);
+            if (MODE == 1) {
+                double rz = (double)qz - (double)bi, rx = (double)q - (double)bi;
+                acc[0] = rz * rz;
+                acc[1] = (double)bi * li;
+                acc[2] = rx * rx;
+            }
+        }
+    }
+    if (MODE != 2 && blockIdx.x == 0 && threadIdx.x == 0) st->iter += 1;
+    if (MODE == 1) uv::block_sum<3>(acc, part + 3 * blockIdx.x);
+}
+
+// Residual-only row pass with FP64 values of A (same partial layout as the
+// CHECK row pass, with the row pass's lane count).
+template <typename T, int L>
+__global__ void __launch_bounds__(kWG)
+k_res_row(int m, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ va,
+          const T *__restrict__ x, const T *__restrict__ z, const double *__restrict__ b,
+          const double *__restrict__ lam, double *__restrict__ part)
+{
+    const int lane = threadIdx.x & (L - 1);
+    const int row = blockIdx.x * (kWG / L) + threadIdx.x / L;
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (row < m) {
+        const int beg = rp[row], end = rp[row + 1];
+        double qx = 0.0, qz = 0.0;
+        for (int k = beg + lane; k < end; k += L) {
+            const int j = ci[k];
+            qx += va[k] * (double)x[j];
+            qz += va[k] * (double)z[j];
+        }
+        qx = uv::group_sum<L>(qx);
+        qz = uv::group_sum<L>(qz);
+        if (lane == 0) {
+            const double bi = b[row];
+            acc[0] = (qz - bi) * (qz - bi);
+            acc[1] = bi * lam[row];
+            acc[2] = (qx - bi) * (qx - bi);
+        }
+    }
+    uv::block_sum<3>(acc, part + 3 * blockIdx.x);
+}
+
+// Column pass over the orthant columns [0, n_orth).
+template <typename T, int L>
+__global__ void __launch_bounds__(kWG)
+k_col_orth(int n_orth, const int *__restrict__ cp, const int *__restrict__ ri, const T *__restrict__ vc,
+           const T *__restrict__ u, T *__restrict__ x, T *__restrict__ z, double *__restrict__ delta,
+           const T *__restrict__ c, double mu, double inv_mu, const DevStatus *st)
+{
+    if (st->done) return;
+    const int lane = threadIdx.x & (L - 1);
+    const int col = blockIdx.x * (kWG / L) + threadIdx.x / L;
+    if (col >= n_orth) return;   // whole L-lane groups leave together
+    const int beg = cp[col], end = cp[col + 1];
+    const T atu = seg_dot<L>(beg, end, lane, ri, vc, u);
+    if (lane == 0) {
+        const int cnt = end - beg;
+        const double d = delta[col];
+        const T dm = (T)(d * inv_mu);
+        const T p = (T)cnt * x[col] + atu;
+        const T xn = (p + z[col] + dm - c[col] * (T)inv_mu) / (T)(1 + cnt);
+        const T v = xn - dm;
+        const T zn = v > (T)0 ? v : (T)0;
+        x[col] = xn;
+        z[col] = zn;
+        delta[col] = d + mu * ((double)zn - (double)xn);
+    }
+}
+
+// Column pass over second-order cones.  Workgroup t owns whole cones
+// [tcone[t], tcone[t+1]) = columns [tcol[t], tcol[t+1]) (at most TC
+// columns): phase 1 computes x and v = x - delta/mu per column into LDS,
+// phase 2 takes each cone's tail norm and its projection case (eq. proj),
+// phase 3 writes x, z and delta.
+template <typename T, int L, int TC>
+__global__ void __launch_bounds__(kWG)
+k_col_soc(const int *__restrict__ tcol, const int *__restrict__ tcone, const int *__restrict__ soc_off,
+          const int *__restrict__ cp, const int *__restrict__ ri, const T *__restrict__ vc,
+          const T *__restrict__ u, T *__restrict__ x, T *__restrict__ z, double *__restrict__ delta,
+          const T *__restrict__ c, double mu, double inv_mu, const DevStatus *st)
+{
+    if (st->done) return;
+    __shared__ T sx[TC];
+    __shared__ T sv[TC];
+    __shared__ double sd[TC];
+    __shared__ short sown[TC];
+    __shared__ double sa1[TC];
+    __shared__ double sbeta[TC];
+    __shared__ short shead[TC];
+
+    const int t = blockIdx.x;
+    const int c0 = tcol[t], ncols = tcol[t + 1] - c0;
+    const int q0 = tcone[t], ncones = tcone[t + 1] - q0;
+    const int lane = threadIdx.x & (L - 1);
+
+    for (int jj = threadIdx.x / L; jj < ncols; jj += kWG / L) {
+        const int col = c0 + jj;
+        const int beg = cp[col], end = cp[col + 1];
+        const T atu = seg_dot<L>(beg, end, lane, ri, vc, u);
+        if (lane == 0) {
+            const int cnt = end - beg;
+            const double d = delta[col];
+            const T dm = (T)(d * inv_mu);
+            const T p = (T)cnt * x[col] + atu;
+            const T xn = (p + z[col] + dm - c[col] * (T)inv_mu) / (T)(1 + cnt);
+            sx[jj] = xn;
+            sv[jj] = xn - dm;
+            sd[jj] = d;
+        }
+    }
+    __syncthreads();
+    for (int qi = threadIdx.x; qi < ncones; qi += kWG) {
+        const int s0 = soc_off[q0 + qi] - c0, s1 = soc_off[q0 + qi + 1] - c0;
+        double a2 = 0.0;
+        for (int j = s0 + 1; j < s1; ++j) a2 += (double)sv[j] * (double)sv[j];
+        for (int j = s0; j < s1; ++j) sown[j] = (short)qi;
+        const double w1 = (double)sv[s0];
+        const double alpha = sqrt(a2);
+        double a1, beta;
+        if (alpha <= -w1) { a1 = 0.0; beta = 0.0; }
+        else if (alpha <= w1) { a1 = w1; beta = 1.0; }
+        else { a1 = 0.5 * (w1 + alpha); beta = 0.5 * (1.0 + w1 / alpha); }
+        sa1[qi] = a1;
+        sbeta[qi] = beta;
+        shead[qi] = (short)s0;
+    }
+    __syncthreads();
+    for (int jj = threadIdx.x; jj < ncols; jj += kWG) {
+        const int qi = sown[jj];
+        const T zn = (jj == shead[qi]) ? (T)sa1[qi] : (T)(sbeta[qi] * (double)sv[jj]);
+        const T xn = sx[jj];
+        const int col = c0 + jj;
+        x[col] = xn;
+        z[col] = zn;
+        delta[col] = sd[jj] + mu * ((double)zn - (double)xn);
+    }
+}
+
+// Residual-only column pass: ||A'lambda + c - delta||^2 and c'z partials,
+// FP64 values of A.
+template <typename T, int L>
+__global__ void __launch_bounds__(kWG)
+k_res_col(int n, const int *__restrict__ cp, const int *__restrict__ ri, const double *__restrict__ vc,
+          const double *__restrict__ lam, const double *__restrict__ c, const double *__restrict__ delta,
+          const T *__restrict__ z, double *__restrict__ part)
+{
+    const int lane = threadIdx.x & (L - 1);
+    const int col = blockIdx.x * (kWG / L) + threadIdx.x / L;
+    double acc[2] = {0.0, 0.0};
+    if (col < n) {
+        double a = 0.0;
+        for (int k = cp[col] + lane; k < cp[col + 1]; k += L) a += vc[k] * lam[ri[k]];
+        a = uv::group_sum<L>(a);
+        if (lane == 0) {
+            const double r = a + c[col] - delta[col];
+            acc[0] = r * r;
+            acc[1] = c[col] * (double)z[col];
+        }
+    }
+    uv::block_sum<2>(acc, part + 2 * blockIdx.x);
+}
+
+// Adds the partials in a fixed order, forms the residuals and decides
+// whether to stop.
+__global__ void __launch_bounds__(kWG)
+k_finalize(int nrow, const double *__restrict__ prow, int ncol, const double *__restrict__ pcol,
+           double eps, DevStatus *st)
+{
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < nrow; i += kWG) {
+        v[0] += prow[3 * i];
+        v[1] += prow[3 * i + 1];
+        v[2] += prow[3 * i + 2];
+    }
+    for (int i = threadIdx.x; i < ncol; i += kWG) {
+        v[3] += pcol[2 * i];
+        v[4] += pcol[2 * i + 1];
+    }
+    double s[5];
+    uv::block_sum<5>(v, s);
+    if (threadIdx.x != 0) return;
+    const double rp = sqrt(s[0]) / (1.0 + sqrt(st->bnorm2));
+    const double rd = sqrt(s[3]) / (1.0 + sqrt(st->cnorm2));
+    const double cz = s[4], bl = s[1];
+    const double rg = fabs(cz + bl) / (1.0 + fabs(cz) + fabs(bl));
+    const double kkt = fmax(rp, fmax(rd, rg));
+    st->r_prim = rp;
+    st->r_dual = rd;
+    st->r_gap = rg;
+    st->kkt = kkt;
+    st->pobj = cz;
+    st->dobj = -bl;
+    st->res_ax_b = sqrt(s[2]);
+    st->check_iter = st->iter;
+    if (!isfinite(kkt)) {
+        st->status = UV_STATUS_NUMERIC;
+        st->done = 1;
+    } else if (kkt <= eps) {
+        st->status = UV_STATUS_CONVERGED;
+        st->done = 1;
+    }
+}
+
+inline unsigned blocks_for(int64_t items, int per_block)
+{
+    return (unsigned)((items + per_block - 1) / per_block);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Solver handle
+// ---------------------------------------------------------------------------
+struct uv_solver {
+    int32_t m = 0, n = 0;
+    int64_t nnz = 0;
+    int32_t n_orth = 0, n_soc = 0;
+    uv_opts o{};
+    hipStream_t stream = nullptr, cap = nullptr;
+    bool own_stream = false;
+    std::vector<void *> allocs;
+
+    int *rp = nullptr, *ci = nullptr, *cp = nullptr, *ri = nullptr;
+    double *va64 = nullptr, *vc64 = nullptr;  // FP64 values (CSR, CSC)
+    void *va = nullptr, *vc = nullptr;        // sweep values (alias of the FP64 ones in FP64 mode)
+    double *b64 = nullptr, *c64 = nullptr;
+    void *b = nullptr, *c = nullptr, *fu = nullptr;
+    void *x = nullptr, *z = nullptr, *u = nullptr;
+    double *lam = nullptr, *delta = nullptr;
+    double *scratch = nullptr;                // max(m, n) doubles
+    double *part_row = nullptr, *part_col = nullptr;
+    int nblk_row = 0, nblk_rescol = 0;
+    int *tcol = nullptr, *tcone = nullptr, *soc_off = nullptr;
+    int ntiles = 0, tile_cap = kSocTile;
+    DevStatus *st = nullptr;
+    DevStatus *st_host = nullptr;             // pinned
+    int L_row = 8, L_col = 4;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t host_iter = 0;
+};
+
+namespace {
+
+template <typename T>
+T *dalloc(uv_solver *s, size_t count)
+{
+    void *p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return nullptr;
+    s->allocs.push_back(p);
+    return (T *)p;
+}
+
+#define UV_TRY(expr)                               \
+    do {                                           \
+        if ((expr) != hipSuccess) return UV_EHIP;  \
+    } while (0)
+
+int pick_lanes(double avg)
+{
+    // about four entries per lane, whole power-of-two groups
+    int L = 1;
+    while (L < 64 && L * 4 < avg) L <<= 1;
+    return L;
+}
+
+bool lanes_ok(int L) { return L == 0 || (L >= 1 && L <= 64 && (L & (L - 1)) == 0); }
+
+// ---- launch helpers (dispatch on precision and lane count) ----
+
+template <typename T, int L, int MODE>
+void launch_row_mode(uv_solver *s, hipStream_t st)
+{
+    const unsigned g = blocks_for(s->m, kWG / L);
+    const double mu = s->o.mu, im = 1.0 / s->o.mu;
+    k_row<T, L, MODE><<<g, kWG, 0, st>>>(s->m, s->rp, s->ci, (const T *)s->va, (const T *)s->x,
+                                         (const T *)s->z, (const T *)s->b, (const T *)s->fu, s->lam,
+                                         (T *)s->u, mu, im, s->part_row, s->st);
+}
+
+// mode: 0 iterate, 1 iterate + residual partials (FP64 only), 2 resume
+template <typename T, int L>
+void launch_row_t(uv_solver *s, hipStream_t st, int mode)
+{
+    if (mode == 1) launch_row_mode<T, L, 1>(s, st);
+    else if (mode == 2) launch_row_mode<T, L, 2>(s, st);
+    else launch_row_mode<T, L, 0>(s, st);
+}
+
+template <typename T, int L>
+void launch_res_row_t(uv_solver *s, hipStream_t st)
+{
+    const unsigned g = blocks_for(s->m, kWG / L);
+    k_res_row<T, L><<<g, kWG, 0, st>>>(s->m, s->rp, s->ci, s->va64, (const T *)s->x, (const T *)s->z, s->b64,
+                                       s->lam, s->part_row);
+}
+
+template <typename T, int L>
+void launch_col_t(uv_solver *s, hipStream_t st)
+{
+    const double mu = s->o.mu, im = 1.0 / s->o.mu;
+    if (s->n_orth > 0) {
+        const unsigned g = blocks_for(s->n_orth, kWG / L);
+        k_col_orth<T, L><<<g, kWG, 0, st>>>(s->n_orth, s->cp, s->ri, (const T *)s->vc, (const T *)s->u,
+                                            (T *)s->x, (T *)s->z, s->delta, (const T *)s->c, mu, im, s->st);
+    }
+    if (s->ntiles > 0) {
+        if (s->tile_cap <= kSocTile)
+            k_col_soc<T, L, kSocTile><<<s->ntiles, kWG, 0, st>>>(
+                s->tcol, s->tcone, s->soc_off, s->cp, s->ri, (const T *)s->vc, (const T *)s->u, (T *)s->x,
+                (T *)s->z, s->delta, (const T *)s->c, mu, im, s->st);
+        else
+            k_col_soc<T, L, UV_MAX_CONE><<<s->ntiles, kWG, 0, st>>>(
+                s->tcol, s->tcone, s->soc_off, s->cp, s->ri, (const T *)s->vc, (const T *)s->u, (T *)s->x,
+                (T *)s->z, s->delta, (const T *)s->c, mu, im, s->st);
+    }
+}
+
+template <typename T, int L>
+void launch_res_col_t(uv_solver *s, hipStream_t st)
+{
+    const unsigned g = blocks_for(s->n, kWG / L);
+    k_res_col<T, L><<<g, kWG, 0, st>>>(s->n, s->cp, s->ri, s->vc64, s->lam, s->c64, s->delta, (const T *)s->z,
+                                       s->part_col);
+}
+
+#define UV_LANE_SWITCH(L, FN, T, ...)                 \
+    switch (L) {                                     \
+    case 1: FN<T, 1>(__VA_ARGS__); break;            \
+    case 2: FN<T, 2>(__VA_ARGS__); break;            \
+    case 4: FN<T, 4>(__VA_ARGS__); break;            \
+    case 8: FN<T, 8>(__VA_ARGS__); break;            \
+    case 16: FN<T, 16>(__VA_ARGS__); break;          \
+    case 32: FN<T, 32>(__VA_ARGS__); break;          \
+    default: FN<T, 64>(__VA_ARGS__); break;          \
+    }
+
+void launch_col(uv_solver *s, hipStream_t st)
+{
+    if (s->o.precision == UV_MIXED) { UV_LANE_SWITCH(s->L_col, launch_col_t, float, s, st) }
+    else { UV_LANE_SWITCH(s->L_col, launch_col_t, double, s, st) }
+}
+
+void launch_row(uv_solver *s, hipStream_t st, int mode)
+{
+    if (s->o.precision == UV_MIXED) { UV_LANE_SWITCH(s->L_row, launch_row_t, float, s, st, mode == 1 ? 0 : mode) }
+    else { UV_LANE_SWITCH(s->L_row, launch_row_t, double, s, st, mode) }
+}
+
+// Residual evaluation of the current state.  In FP64 mode right after a
+// CHECK row pass only the column residuals remain.
+void launch_residuals(uv_solver *s, hipStream_t st, bool row_done)
+{
+    if (!row_done) {
+        if (s->o.precision == UV_MIXED) { UV_LANE_SWITCH(s->L_row, launch_res_row_t, float, s, st) }
+        else { UV_LANE_SWITCH(s->L_row, launch_res_row_t, double, s, st) }
+    }
+    if (s->o.precision == UV_MIXED) { UV_LANE_SWITCH(s->L_col, launch_res_col_t, float, s, st) }
+    else { UV_LANE_SWITCH(s->L_col, launch_res_col_t, double, s, st) }
+    k_finalize<<<1, kWG, 0, st>>>(s->nblk_row, s->part_row, s->nblk_rescol, s->part_col, s->o.eps_kkt, s->st);
+}
+
+// One iteration; with check, the residuals of the new iterate follow it.
+void launch_iteration(uv_solver *s, hipStream_t st, bool check)
+{
+    launch_col(s, st);
+    const bool fused = check && s->o.precision == UV_FP64;
+    launch_row(s, st, fused ? 1 : 0);
+    if (check) launch_residuals(s, st, fused);
+}
+
+int build_graph(uv_solver *s)
+{
+    if (hipStreamBeginCapture(s->cap, hipStreamCaptureModeRelaxed) != hipSuccess) return UV_EHIP;
+    for (int i = 0; i < s->o.check_every; ++i) launch_iteration(s, s->cap, i == s->o.check_every - 1);
+    if (hipStreamEndCapture(s->cap, &s->graph) != hipSuccess) return UV_EHIP;
+    if (hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0) != hipSuccess) return UV_EHIP;
+    return UV_OK;
+}
+
+int sync_status(uv_solver *s)
+{
+    UV_TRY(hipMemcpyAsync(s->st_host, s->st, sizeof(DevStatus), hipMemcpyDeviceToHost, s->stream));
+    UV_TRY(hipStreamSynchronize(s->stream));
+    s->host_iter = s->st_host->iter;
+    return UV_OK;
+}
+
+int validate(const uv_csr *A, const double *b, const double *c, const uv_cones *K, const uv_opts *o)
+{
+    if (!A || !b || !c || !K || !o) return UV_EINVAL;
+    if (A->m < 1 || A->n < 1 || A->nnz < 0) return UV_EINVAL;
+    if (!(o->mu > 0.0) || !std::isfinite(o->mu)) return UV_EINVAL;
+    if (o->precision != UV_FP64 && o->precision != UV_MIXED) return UV_EINVAL;
+    if (o->check_every < 1 || !(o->eps_kkt >= 0.0) || o->max_iter < 0) return UV_EINVAL;
+    if (!lanes_ok(o->lanes_row) || !lanes_ok(o->lanes_col)) return UV_EINVAL;
+    if (A->nnz > 0 && (!A->col_idx || !A->val)) return UV_EINVAL;
+    if (!A->row_ptr) return UV_EINVAL;
+    if (A->nnz >= ((int64_t)1 << 31)) return UV_ETOOBIG;
+    if (A->row_ptr[0] != 0 || A->row_ptr[A->m] != A->nnz) return UV_EBADCSR;
+    for (int32_t i = 0; i < A->m; ++i) {
+        const int64_t b0 = A->row_ptr[i], b1 = A->row_ptr[i + 1];
+        if (b1 < b0 || b1 > A->nnz) return UV_EBADCSR;
+        for (int64_t k = b0; k < b1; ++k) {
+            const int32_t j = A->col_idx[k];
+            if (j < 0 || j >= A->n) return UV_EBADCSR;
+            if (k > b0 && j <= A->col_idx[k - 1]) return UV_EBADCSR;
+        }
+    }
+    if (K->n_orthant < 0 || K->n_soc < 0 || (K->n_soc > 0 && !K->soc_sizes)) return UV_ECONE;
+    int64_t tot = K->n_orthant;
+    for (int32_t q = 0; q < K->n_soc; ++q) {
+        if (K->soc_sizes[q] < 1 || K->soc_sizes[q] > UV_MAX_CONE) return UV_ECONE;
+        tot += K->soc_sizes[q];
+    }
+    if (tot != A->n) return UV_ECONE;
+    return UV_OK;
+}
+
+int setup(uv_solver *s, const uv_csr *A, const double *b, const double *c, const uv_cones *K)
+{
+    const int m = s->m, n = s->n;
+    const int nnz = (int)s->nnz;
+    const bool mixed = s->o.precision == UV_MIXED;
+    const size_t ts = mixed ? sizeof(float) : sizeof(double);
+
+    if (s->o.hip_stream) {
+        s->stream = (hipStream_t)s->o.hip_stream;
+    } else {
+        UV_TRY(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+        s->own_stream = true;
+    }
+    UV_TRY(hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking));
+    hipStream_t st = s->stream;
+
+    s->rp = dalloc<int>(s, m + 1);
+    s->ci = dalloc<int>(s, nnz);
+    s->va64 = dalloc<double>(s, nnz);
+    s->cp = dalloc<int>(s, n + 1);
+    s->ri = dalloc<int>(s, nnz);
+    s->vc64 = dalloc<double>(s, nnz);
+    s->b64 = dalloc<double>(s, m);
+    s->c64 = dalloc<double>(s, n);
+    s->lam = dalloc<double>(s, m);
+    s->delta = dalloc<double>(s, n);
+    s->scratch = dalloc<double>(s, std::max(m, n));
+    s->x = dalloc<char>(s, ts * n);
+    s->z = dalloc<char>(s, ts * n);
+    s->u = dalloc<char>(s, ts * m);
+    s->fu = dalloc<char>(s, ts * m);
+    if (mixed) {
+        s->va = dalloc<float>(s, nnz);
+        s->vc = dalloc<float>(s, nnz);
+        s->b = dalloc<float>(s, m);
+        s->c = dalloc<float>(s, n);
+    } else {
+        s->va = s->va64;
+        s->vc = s->vc64;
+        s->b = s->b64;
+        s->c = s->c64;
+    }
+    s->nblk_row = (int)blocks_for(m, kWG / s->L_row);
+    s->nblk_rescol = (int)blocks_for(n, kWG / s->L_col);
+    s->part_row = dalloc<double>(s, 3 * (size_t)s->nblk_row);
+    s->part_col = dalloc<double>(s, 2 * (size_t)s->nblk_rescol);
+    s->st = dalloc<DevStatus>(s, 1);
+    int *cnt = dalloc<int>(s, n);
+    const int nscan = (int)blocks_for(n, 4 * kWG);
+    int *bsum = dalloc<int>(s, nscan);
+    for (void *p : {(void *)s->rp, (void *)s->ci, (void *)s->va64, (void *)s->cp, (void *)s->ri,
+                    (void *)s->vc64, (void *)s->b64, (void *)s->c64, (void *)s->lam, (void *)s->delta,
+                    (void *)s->scratch, s->x, s->z, s->u, s->fu, s->va, s->vc, s->b, s->c,
+                    (void *)s->part_row, (void *)s->part_col, (void *)s->st, (void *)cnt, (void *)bsum})
+        if (!p) return UV_ENOMEM;
+    if (hipHostMalloc((void **)&s->st_host, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess) {
+        s->st_host = nullptr;
+        return UV_ENOMEM;
+    }
+
+    // SOC tiles: whole cones, at most tile_cap columns per workgroup.
+    if (K->n_soc > 0) {
+        int maxc = 0;
+        for (int q = 0; q < K->n_soc; ++q) maxc = std::max(maxc, (int)K->soc_sizes[q]);
+        s->tile_cap = maxc <= kSocTile ? kSocTile : UV_MAX_CONE;
+        std::vector<int> off(K->n_soc + 1), tcol, tcone;
+        off[0] = K->n_orthant;
+        for (int q = 0; q < K->n_soc; ++q) off[q + 1] = off[q] + K->soc_sizes[q];
+        tcol.push_back(off[0]);
+        tcone.push_back(0);
+        for (int q = 0; q < K->n_soc; ++q) {
+            if (off[q + 1] - tcol.back() > s->tile_cap) {
+                tcol.push_back(off[q]);
+                tcone.push_back(q);
+            }
+        }
+        tcol.push_back(off[K->n_soc]);
+        tcone.push_back(K->n_soc);
+        s->ntiles = (int)tcol.size() - 1;
+        s->tcol = dalloc<int>(s, tcol.size());
+        s->tcone = dalloc<int>(s, tcone.size());
+        s->soc_off = dalloc<int>(s, off.size());
+        if (!s->tcol || !s->tcone || !s->soc_off) return UV_ENOMEM;
+        UV_TRY(hipMemcpy(s->tcol, tcol.data(), tcol.size() * 4, hipMemcpyHostToDevice));
+        UV_TRY(hipMemcpy(s->tcone, tcone.data(), tcone.size() * 4, hipMemcpyHostToDevice));
+        UV_TRY(hipMemcpy(s->soc_off, off.data(), off.size() * 4, hipMemcpyHostToDevice));
+    }
+
+    // Upload (row_ptr narrowed to 32-bit; nnz < 2^31 was checked).
+    {
+        std::vector<int> rp32(m + 1);
+        for (int i = 0; i <= m; ++i) rp32[i] = (int)A->row_ptr[i];
+        UV_TRY(hipMemcpy(s->rp, rp32.data(), (m + 1) * sizeof(int), hipMemcpyHostToDevice));
+    }
+    if (nnz > 0) {
+        UV_TRY(hipMemcpy(s->ci, A->col_idx, (size_t)nnz * 4, hipMemcpyHostToDevice));
+        UV_TRY(hipMemcpy(s->va64, A->val, (size_t)nnz * 8, hipMemcpyHostToDevice));
+    }
+    UV_TRY(hipMemcpy(s->b64, b, (size_t)m * 8, hipMemcpyHostToDevice));
+    UV_TRY(hipMemcpy(s->c64, c, (size_t)n * 8, hipMemcpyHostToDevice));
+
+    // Column-major copy of A.
+    UV_TRY(hipMemsetAsync(cnt, 0, (size_t)n * 4, st));
+    UV_TRY(hipMemsetAsync(s->cp, 0, 4, st));
+    if (nnz > 0) k_col_count<<<blocks_for(nnz, kWG), kWG, 0, st>>>(nnz, s->ci, cnt);
+    k_scan_local<<<nscan, kWG, 0, st>>>(n, cnt, s->cp + 1, bsum);
+    k_scan_blocks<<<1, kWG, 0, st>>>(nscan, bsum);
+    k_scan_add<<<blocks_for(n, kWG), kWG, 0, st>>>(n, s->cp + 1, bsum);
+    UV_TRY(hipMemsetAsync(cnt, 0, (size_t)n * 4, st));
+    k_col_scatter<<<blocks_for(m, kWG), kWG, 0, st>>>(m, s->rp, s->ci, s->va64, s->cp, cnt, s->ri, s->vc64);
+    k_col_sort<<<blocks_for(n, kWG), kWG, 0, st>>>(n, s->cp, s->ri, s->vc64);
+
+    // F_U, narrowed copies, norms.
+    if (mixed) {
+        k_row_factor<float><<<blocks_for(m, kWG), kWG, 0, st>>>(m, s->rp, s->va64, (float *)s->fu);
+        if (nnz > 0) {
+            k_narrow<float><<<blocks_for(nnz, kWG), kWG, 0, st>>>(nnz, s->va64, (float *)s->va);
+            k_narrow<float><<<blocks_for(nnz, kWG), kWG, 0, st>>>(nnz, s->vc64, (float *)s->vc);
+        }
+        k_narrow<float><<<blocks_for(m, kWG), kWG, 0, st>>>(m, s->b64, (float *)s->b);
+        k_narrow<float><<<blocks_for(n, kWG), kWG, 0, st>>>(n, s->c64, (float *)s->c);
+    } else {
+        k_row_factor<double><<<blocks_for(m, kWG), kWG, 0, st>>>(m, s->rp, s->va64, (double *)s->fu);
+    }
+    k_norms<<<1, kWG, 0, st>>>(m, s->b64, n, s->c64, s->st);
+    UV_TRY(hipGetLastError());
+    UV_TRY(hipStreamSynchronize(st));
+    return UV_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void uv_default_opts(uv_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->mu = 1.0;
+    o->precision = UV_FP64;
+    o->check_every = 10;
+    o->eps_kkt = 1e-4;
+    o->max_iter = 0;
+    o->hip_stream = nullptr;
+    o->lanes_row = 0;
+    o->lanes_col = 0;
+    o->use_graph = 1;
+}
+
+const char *solver_strerror(int code)
+{
+    switch (code) {
+    case UV_OK: return "ok";
+    case UV_EINVAL: return "invalid argument (null pointer, mu <= 0, m or n < 1, or a bad option)";
+    case UV_EBADCSR: return "malformed CSR (row_ptr, column range or column order within a row)";
+    case UV_ECONE: return "bad cone specification (sizes must be >= 1, <= UV_MAX_CONE and sum to n)";
+    case UV_ENOMEM: return "out of device or pinned host memory";
+    case UV_EHIP: return "HIP runtime error";
+    case UV_ENUMERIC: return "NaN or Inf in a residual check";
+    case UV_ETOOBIG: return "nnz must be below 2^31";
+    default: return "unknown error code";
+    }
+}
+
+void solver_destroy(uv_solver *s)
+{
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    if (s->exec) (void)hipGraphExecDestroy(s->exec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    for (void *p : s->allocs) (void)hipFree(p);
+    if (s->st_host) (void)hipHostFree(s->st_host);
+    if (s->cap) (void)hipStreamDestroy(s->cap);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+int solver_create(const uv_csr *A, const double *b, const double *c, const uv_cones *K, const uv_opts *opts,
+                  uv_solver **out)
+{
+    if (!out) return UV_EINVAL;
+    *out = nullptr;
+    uv_opts o;
+    uv_default_opts(&o);
+    if (opts) o = *opts;
+    int rc = validate(A, b, c, K, &o);
+    if (rc != UV_OK) return rc;
+    uv_solver *s = new (std::nothrow) uv_solver();
+    if (!s) return UV_ENOMEM;
+    s->m = A->m;
+    s->n = A->n;
+    s->nnz = A->nnz;
+    s->n_orth = K->n_orthant;
+    s->n_soc = K->n_soc;
+    s->o = o;
+    s->L_row = o.lanes_row ? o.lanes_row : pick_lanes((double)A->nnz / A->m);
+    s->L_col = o.lanes_col ? o.lanes_col : pick_lanes((double)A->nnz / A->n);
+    rc = setup(s, A, b, c, K);
+    if (rc == UV_OK) rc = solver_set_start(s, nullptr, nullptr, nullptr, nullptr);
+    if (rc == UV_OK && s->o.use_graph) rc = build_graph(s);
+    if (rc != UV_OK) {
+        solver_destroy(s);
+        return rc;
+    }
+    *out = s;
+    return UV_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Uploads (x, z, delta, lambda) (NULL = zero) and resets the status; u is
+// set by the caller's kernel.
+int upload_state(uv_solver *s, const double *x, const double *z, const double *delta, const double *lambda)
+{
+    hipStream_t st = s->stream;
+    const bool mixed = s->o.precision == UV_MIXED;
+    const size_t ts = mixed ? 4 : 8;
+    const int m = s->m, n = s->n;
+    auto put_t = [&](void *dst, const double *src, int len) -> int {
+        if (!src) return hipMemsetAsync(dst, 0, ts * len, st) == hipSuccess ? UV_OK : UV_EHIP;
+        if (!mixed) return hipMemcpyAsync(dst, src, 8 * (size_t)len, hipMemcpyHostToDevice, st) == hipSuccess
+                               ? UV_OK : UV_EHIP;
+        if (hipMemcpyAsync(s->scratch, src, 8 * (size_t)len, hipMemcpyHostToDevice, st) != hipSuccess)
+            return UV_EHIP;
+        k_narrow<float><<<blocks_for(len, kWG), kWG, 0, st>>>(len, s->scratch, (float *)dst);
+        // the scratch buffer is reused by the next upload: wait for this one
+        return hipStreamSynchronize(st) == hipSuccess ? UV_OK : UV_EHIP;
+    };
+    int rc;
+    if ((rc = put_t(s->x, x, n)) != UV_OK) return rc;
+    if ((rc = put_t(s->z, z, n)) != UV_OK) return rc;
+    if (delta) UV_TRY(hipMemcpyAsync(s->delta, delta, 8 * (size_t)n, hipMemcpyHostToDevice, st));
+    else UV_TRY(hipMemsetAsync(s->delta, 0, 8 * (size_t)n, st));
+    if (lambda) UV_TRY(hipMemcpyAsync(s->lam, lambda, 8 * (size_t)m, hipMemcpyHostToDevice, st));
+    else UV_TRY(hipMemsetAsync(s->lam, 0, 8 * (size_t)m, st));
+    const double im = 1.0 / s->o.mu;
+    // k_start also sets u = -lambda/mu (the start mapping); resume overwrites it
+    if (mixed) k_start<float><<<blocks_for(m, kWG), kWG, 0, st>>>(m, s->lam, (float *)s->u, im, s->st);
+    else k_start<double><<<blocks_for(m, kWG), kWG, 0, st>>>(m, s->lam, (double *)s->u, im, s->st);
+    UV_TRY(hipGetLastError());
+    return UV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int solver_set_start(uv_solver *s, const double *x, const double *z, const double *delta, const double *lambda)
+{
+    if (!s) return UV_EINVAL;
+    int rc = upload_state(s, x, z, delta, lambda);
+    if (rc != UV_OK) return rc;
+    return sync_status(s);
+}
+
+int solver_resume(uv_solver *s, const double *x, const double *z, const double *delta, const double *lambda)
+{
+    if (!s) return UV_EINVAL;
+    int rc = upload_state(s, x, z, delta, lambda);
+    if (rc != UV_OK) return rc;
+    launch_row(s, s->stream, 2);
+    UV_TRY(hipGetLastError());
+    return sync_status(s);
+}
+
+int solver_iterate(uv_solver *s, int64_t k, int32_t *done)
+{
+    if (!s || k < 0) return UV_EINVAL;
+    if (done) *done = 0;
+    if (!s->st_host->done) {
+        int64_t left = k;
+        if (s->o.max_iter > 0) left = std::min<int64_t>(left, s->o.max_iter - s->host_iter);
+        int64_t it = s->host_iter;
+        const int ce = s->o.check_every;
+        while (left > 0) {
+            if (s->exec && it % ce == 0 && left >= ce) {
+                UV_TRY(hipGraphLaunch(s->exec, s->stream));
+                it += ce;
+                left -= ce;
+            } else {
+                launch_iteration(s, s->stream, (it + 1) % ce == 0);
+                it += 1;
+                left -= 1;
+            }
+        }
+        UV_TRY(hipGetLastError());
+        int rc = sync_status(s);
+        if (rc != UV_OK) return rc;
+    }
+    DevStatus *h = s->st_host;
+    if (!h->done && s->o.max_iter > 0 && s->host_iter >= s->o.max_iter) {
+        h->status = UV_STATUS_MAX_ITER;
+        h->done = 1;
+        UV_TRY(hipMemcpyAsync(s->st, h, sizeof(DevStatus), hipMemcpyHostToDevice, s->stream));
+        UV_TRY(hipStreamSynchronize(s->stream));
+    }
+    if (done) *done = h->done;
+    return h->status == UV_STATUS_NUMERIC ? UV_ENUMERIC : UV_OK;
+}
+
+int solver_residuals(uv_solver *s, uv_residuals *r)
+{
+    if (!s || !r) return UV_EINVAL;
+    if (s->st_host->check_iter != s->st_host->iter) {
+        launch_residuals(s, s->stream, false);
+        UV_TRY(hipGetLastError());
+        int rc = sync_status(s);
+        if (rc != UV_OK) return rc;
+    }
+    const DevStatus *h = s->st_host;
+    r->r_prim = h->r_prim;
+    r->r_dual = h->r_dual;
+    r->r_gap = h->r_gap;
+    r->kkt = h->kkt;
+    r->pobj = h->pobj;
+    r->dobj = h->dobj;
+    r->res_ax_b = h->res_ax_b;
+    r->iter = h->iter;
+    r->status = h->status;
+    return UV_OK;
+}
+
+int solver_solution(uv_solver *s, double *x, double *z, double *lambda, double *delta)
+{
+    if (!s) return UV_EINVAL;
+    hipStream_t st = s->stream;
+    const bool mixed = s->o.precision == UV_MIXED;
+    auto get_t = [&](double *dst, const void *src, int len) -> int {
+        if (!dst) return UV_OK;
+        if (mixed) {
+            k_widen<float><<<blocks_for(len, kWG), kWG, 0, st>>>(len, (const float *)src, s->scratch);
+            src = s->scratch;
+        }
+        if (hipMemcpyAsync(dst, src, 8 * (size_t)len, hipMemcpyDeviceToHost, st) != hipSuccess) return UV_EHIP;
+        return hipStreamSynchronize(st) == hipSuccess ? UV_OK : UV_EHIP;
+    };
+    int rc;
+    if ((rc = get_t(x, s->x, s->n)) != UV_OK) return rc;
+    if ((rc = get_t(z, s->z, s->n)) != UV_OK) return rc;
+    if (lambda) UV_TRY(hipMemcpyAsync(lambda, s->lam, 8 * (size_t)s->m, hipMemcpyDeviceToHost, st));
+    if (delta) UV_TRY(hipMemcpyAsync(delta, s->delta, 8 * (size_t)s->n, hipMemcpyDeviceToHost, st));
+    UV_TRY(hipStreamSynchronize(st));
+    return UV_OK;
+}
+
+int solver_time_kernels(uv_solver *s, int32_t iters, double *ms_col, double *ms_row)
+{
+    if (!s || iters < 1 || !ms_col || !ms_row) return UV_EINVAL;
+    if (s->st_host->done) return UV_EINVAL;   // a stopped solver launches nothing to time
+    std::vector<hipEvent_t> ev(3 * (size_t)iters, nullptr);
+    int rc = UV_OK;
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) { rc = UV_EHIP; break; }
+    if (rc == UV_OK) {
+        for (int i = 0; i < iters; ++i) {
+            (void)hipEventRecord(ev[3 * i], s->stream);
+            launch_col(s, s->stream);
+            (void)hipEventRecord(ev[3 * i + 1], s->stream);
+            launch_row(s, s->stream, 0);
+            (void)hipEventRecord(ev[3 * i + 2], s->stream);
+        }
+        if (hipStreamSynchronize(s->stream) != hipSuccess) rc = UV_EHIP;
+    }
+    double tc = 0.0, tr = 0.0;
+    if (rc == UV_OK) {
+        for (int i = 0; i < iters; ++i) {
+            float a = 0.f, b = 0.f;
+            (void)hipEventElapsedTime(&a, ev[3 * i], ev[3 * i + 1]);
+            (void)hipEventElapsedTime(&b, ev[3 * i + 1], ev[3 * i + 2]);
+            tc += a;
+            tr += b;
+        }
+        *ms_col = tc / iters;
+        *ms_row = tr / iters;
+        rc = sync_status(s);
+    }
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return rc;
+}
+
+int solver_launch_shape(const uv_solver *s, int32_t *lanes_row, int32_t *lanes_col)
+{
+    if (!s) return UV_EINVAL;
+    if (lanes_row) *lanes_row = s->L_row;
+    if (lanes_col) *lanes_col = s->L_col;
+    return UV_OK;
+}
+
+}  // extern "C"

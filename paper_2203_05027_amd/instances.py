@@ -36,7 +36,7 @@ import math
 import numpy as np
 
 __all__ = [
-    "lp_instance", "socp_instance", "batch_lp_sizes", "batch_lp_instance",
+    "lp_instance", "socp_instance", "conic_instance", "batch_lp_sizes", "batch_lp_instance",
     "ParametricFamily", "config_instance", "CONFIGS",
 ]
 
@@ -114,6 +114,30 @@ def lp_instance(m: int, n: int, k: int, seed: int, unit_rows: bool = False) -> d
         "col_idx": col_idx, "val": val, "b": b, "c": c, "n_orth": n,
         "soc_sizes": np.zeros(0, dtype=np.int32), "x0": x0, "y0": y0, "s0": s0,
         "p_star": float(c @ x0), "d_star": float(b @ y0), "seed": seed,
+    }
+
+
+def conic_instance(m: int, n_orth: int, soc_sizes, k: int, seed: int) -> dict:
+    """General family: K = R_+^{n_orth} x K_{soc_sizes[0]} x ...; x0 and s0
+    are drawn strictly inside K (orthant part: |N(0,1)| + U(0.1, 1))."""
+    rng = np.random.default_rng(seed)
+    sizes = np.asarray(soc_sizes, dtype=np.int32)
+    n = int(n_orth + sizes.sum())
+    rows = _distinct_rows(rng, m, n, k)
+    vals = rng.standard_normal((n, k))
+    row_ptr, col_idx, val, r = _csr_from_columns(m, n, rows, vals)
+    x0 = np.concatenate([np.abs(rng.standard_normal(n_orth)) + rng.uniform(0.1, 1.0, n_orth),
+                         _interior_cone_points(rng, sizes) if sizes.size else np.zeros(0)])
+    s0 = np.concatenate([np.abs(rng.standard_normal(n_orth)) + rng.uniform(0.1, 1.0, n_orth),
+                         _interior_cone_points(rng, sizes) if sizes.size else np.zeros(0)])
+    y0 = rng.standard_normal(m)
+    b = _matvec(m, r, col_idx, val, x0)
+    c = _rmatvec(n, r, col_idx, val, y0) + s0
+    return {
+        "m": m, "n": n, "nnz": int(row_ptr[-1]), "row_ptr": row_ptr,
+        "col_idx": col_idx, "val": val, "b": b, "c": c, "n_orth": n_orth,
+        "soc_sizes": sizes, "x0": x0, "y0": y0, "s0": s0,
+        "p_upper": float(c @ x0), "d_lower": float(b @ y0), "seed": seed,
     }
 
 

@@ -1,0 +1,221 @@
+"""ctypes binding of ``libuvadmm.so`` (the C ABI declared in include/uvadmm.h).
+
+Argument marshalling only: every step of the solver runs in the library's HIP
+kernels.  The binding refuses to work without the built library; there is no
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libuvadmm.so")
+
+UV_OK, UV_EINVAL, UV_EBADCSR, UV_ECONE, UV_ENOMEM, UV_EHIP, UV_ENUMERIC, UV_ETOOBIG = 0, -1, -2, -3, -4, -5, -6, -7
+UV_FP64, UV_MIXED = 0, 1
+UV_MAX_CONE = 1024
+STATUS = {0: "running", 1: "converged", 2: "max_iter", 3: "numeric"}
+
+
+class UvCsr(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class UvCones(ctypes.Structure):
+    _fields_ = [("n_orthant", ctypes.c_int32), ("n_soc", ctypes.c_int32),
+                ("soc_sizes", ctypes.c_void_p)]
+
+
+class UvOpts(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("eps_kkt", ctypes.c_double),
+                ("max_iter", ctypes.c_int64), ("hip_stream", ctypes.c_void_p),
+                ("lanes_row", ctypes.c_int32), ("lanes_col", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
+
+
+class UvResiduals(ctypes.Structure):
+    _fields_ = [("r_prim", ctypes.c_double), ("r_dual", ctypes.c_double),
+                ("r_gap", ctypes.c_double), ("kkt", ctypes.c_double),
+                ("pobj", ctypes.c_double), ("dobj", ctypes.c_double),
+                ("res_ax_b", ctypes.c_double), ("iter", ctypes.c_int64),
+                ("status", ctypes.c_int32)]
+
+
+class UvError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {lib().solver_strerror(code).decode()} (code {code})")
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it first "
+                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.uv_default_opts.argtypes = [ctypes.POINTER(UvOpts)]
+    L.uv_default_opts.restype = None
+    L.solver_create.argtypes = [ctypes.POINTER(UvCsr), P, P, ctypes.POINTER(UvCones),
+                                ctypes.POINTER(UvOpts), ctypes.POINTER(P)]
+    L.solver_create.restype = ctypes.c_int
+    L.solver_set_start.argtypes = [P, P, P, P, P]
+    L.solver_set_start.restype = ctypes.c_int
+    L.solver_resume.argtypes = [P, P, P, P, P]
+    L.solver_resume.restype = ctypes.c_int
+    L.solver_iterate.argtypes = [P, i64, ctypes.POINTER(i32)]
+    L.solver_iterate.restype = ctypes.c_int
+    L.solver_residuals.argtypes = [P, ctypes.POINTER(UvResiduals)]
+    L.solver_residuals.restype = ctypes.c_int
+    L.solver_solution.argtypes = [P, P, P, P, P]
+    L.solver_solution.restype = ctypes.c_int
+    L.solver_destroy.argtypes = [P]
+    L.solver_destroy.restype = None
+    L.solver_strerror.argtypes = [ctypes.c_int]
+    L.solver_strerror.restype = ctypes.c_char_p
+    L.solver_time_kernels.argtypes = [P, i32, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double)]
+    L.solver_time_kernels.restype = ctypes.c_int
+    L.solver_launch_shape.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.solver_launch_shape.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int, where: str):
+    if rc != UV_OK:
+        raise UvError(rc, where)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a, size=None):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if size is not None and a.size != size:
+        raise ValueError(f"expected {size} entries, got {a.size}")
+    return a
+
+
+def default_opts() -> UvOpts:
+    o = UvOpts()
+    lib().uv_default_opts(ctypes.byref(o))
+    return o
+
+
+class Solver:
+    """One problem on the GPU: ``min c'x s.t. A x = b, x in K``.
+
+    ``A`` is given in CSR (``row_ptr`` int64, ``col_idx`` int32, ``val``
+    float64); ``K`` is ``n_orth`` orthant coordinates followed by the
+    second-order cones of ``soc_sizes``.
+    """
+
+    def __init__(self, m, n, row_ptr, col_idx, val, b, c, n_orth, soc_sizes=(), *,
+                 mu=1.0, precision="fp64", check_every=10, eps=1e-4, max_iter=0,
+                 lanes_row=0, lanes_col=0, use_graph=True, stream=None):
+        L = lib()
+        self.m, self.n = int(m), int(n)
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        va = np.ascontiguousarray(val, dtype=np.float64)
+        sizes = np.ascontiguousarray(soc_sizes, dtype=np.int32)
+        csr = UvCsr(self.m, self.n, int(rp[-1]) if rp.size else 0, _ptr(rp), _ptr(ci), _ptr(va))
+        cones = UvCones(int(n_orth), int(sizes.size), _ptr(sizes) if sizes.size else None)
+        o = default_opts()
+        o.mu = float(mu)
+        o.precision = {"fp64": UV_FP64, "mixed": UV_MIXED}[precision]
+        o.check_every = int(check_every)
+        o.eps_kkt = float(eps)
+        o.max_iter = int(max_iter)
+        o.hip_stream = stream
+        o.lanes_row, o.lanes_col = int(lanes_row), int(lanes_col)
+        o.use_graph = 1 if use_graph else 0
+        self.precision = precision
+        self.nnz = csr.nnz
+        bb = _f64(b, self.m)
+        cc = _f64(c, self.n)
+        h = ctypes.c_void_p()
+        _check(L.solver_create(ctypes.byref(csr), _ptr(bb), _ptr(cc), ctypes.byref(cones),
+                               ctypes.byref(o), ctypes.byref(h)), "solver_create")
+        self._h = h
+
+    @classmethod
+    def from_instance(cls, inst, **kw):
+        return cls(inst["m"], inst["n"], inst["row_ptr"], inst["col_idx"], inst["val"],
+                   inst["b"], inst["c"], inst["n_orth"], inst["soc_sizes"], **kw)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().solver_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_start(self, x=None, z=None, delta=None, lam=None):
+        n, m = self.n, self.m
+        args = (_f64(x, n), _f64(z, n), _f64(delta, n), _f64(lam, m))
+        _check(lib().solver_set_start(self._h, *[_ptr(a) for a in args]), "solver_set_start")
+
+    def resume(self, x=None, z=None, delta=None, lam=None):
+        """Continue a run from a state returned by solution() (checkpoint)."""
+        n, m = self.n, self.m
+        args = (_f64(x, n), _f64(z, n), _f64(delta, n), _f64(lam, m))
+        _check(lib().solver_resume(self._h, *[_ptr(a) for a in args]), "solver_resume")
+
+    def iterate(self, k: int) -> bool:
+        done = ctypes.c_int32(0)
+        rc = lib().solver_iterate(self._h, int(k), ctypes.byref(done))
+        if rc not in (UV_OK, UV_ENUMERIC):
+            _check(rc, "solver_iterate")
+        return bool(done.value)
+
+    def residuals(self) -> dict:
+        r = UvResiduals()
+        _check(lib().solver_residuals(self._h, ctypes.byref(r)), "solver_residuals")
+        d = {k: getattr(r, k) for k, _ in UvResiduals._fields_}
+        d["status"] = STATUS.get(d["status"], d["status"])
+        return d
+
+    def solution(self) -> dict:
+        x, z, d = np.empty(self.n), np.empty(self.n), np.empty(self.n)
+        lam = np.empty(self.m)
+        _check(lib().solver_solution(self._h, _ptr(x), _ptr(z), _ptr(lam), _ptr(d)),
+               "solver_solution")
+        return {"x": x, "z": z, "delta": d, "lambda": lam}
+
+    def time_kernels(self, iters: int):
+        a, b = ctypes.c_double(), ctypes.c_double()
+        _check(lib().solver_time_kernels(self._h, int(iters), ctypes.byref(a), ctypes.byref(b)),
+               "solver_time_kernels")
+        return a.value, b.value
+
+    def launch_shape(self):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().solver_launch_shape(self._h, ctypes.byref(a), ctypes.byref(b)),
+               "solver_launch_shape")
+        return a.value, b.value

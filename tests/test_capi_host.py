@@ -1,0 +1,127 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+include/uvadmm.h declares, and rejects malformed input before any device
+call (validation runs on the host first, so these need no GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2203_05027_amd import solver as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(", text, re.M):
+            if not m.group(0).lstrip().startswith(("#", "typedef", "return")):
+                names.append(m.group(1))
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_function():
+    names = _declared_functions()
+    assert "solver_create" in names and "solver_iterate" in names
+    L = S.lib()
+    for name in names:
+        assert hasattr(L, name), f"{name} declared in include/ but not exported"
+
+
+def test_strerror_names_every_code():
+    L = S.lib()
+    for code in range(0, -8, -1):
+        assert L.solver_strerror(code).decode() != "unknown error code"
+    assert L.solver_strerror(-99).decode() == "unknown error code"
+
+
+def test_default_opts():
+    o = S.default_opts()
+    assert o.mu == 1.0 and o.precision == S.UV_FP64 and o.check_every == 10
+    assert o.eps_kkt == 1e-4 and o.max_iter == 0 and o.use_graph == 1
+
+
+def _try_create(m, n, rp, ci, va, b, c, n_orth, sizes=(), **kw):
+    with pytest.raises(S.UvError) as ei:
+        S.Solver(m, n, rp, ci, va, b, c, n_orth, sizes, **kw)
+    return ei.value.code
+
+
+GOOD = dict(m=2, n=3, rp=[0, 2, 3], ci=[0, 2, 1], va=[1.0, 2.0, 3.0],
+            b=[1.0, 1.0], c=[1.0, 1.0, 1.0])
+
+
+def _args(**over):
+    d = dict(GOOD)
+    d.update(over)
+    return d
+
+
+@pytest.mark.parametrize("over,code", [
+    (dict(rp=[1, 2, 3]), S.UV_EBADCSR),            # row_ptr[0] != 0
+    (dict(rp=[0, 3, 2]), S.UV_EBADCSR),            # not monotone / exceeds nnz
+    (dict(ci=[0, 3, 1]), S.UV_EBADCSR),            # column out of range
+    (dict(ci=[0, -1, 1]), S.UV_EBADCSR),           # negative column
+    (dict(ci=[2, 0, 1]), S.UV_EBADCSR),            # not increasing in a row
+    (dict(ci=[1, 1, 1]), S.UV_EBADCSR),            # duplicate in a row
+])
+def test_rejects_malformed_csr(over, code):
+    a = _args(**over)
+    assert _try_create(a["m"], a["n"], a["rp"], a["ci"], a["va"], a["b"], a["c"], 3) == code
+
+
+@pytest.mark.parametrize("n_orth,sizes", [(2, ()), (0, (2,)), (1, (1, 0)), (0, (4,)), (-1, (4,))])
+def test_rejects_bad_cones(n_orth, sizes):
+    a = GOOD
+    assert _try_create(a["m"], a["n"], a["rp"], a["ci"], a["va"], a["b"], a["c"],
+                       n_orth, sizes) == S.UV_ECONE
+
+
+def test_rejects_oversized_cone():
+    n = S.UV_MAX_CONE + 1
+    code = _try_create(1, n, [0, 1], [0], [1.0], [1.0], np.ones(n), 0, (n,))
+    assert code == S.UV_ECONE
+
+
+@pytest.mark.parametrize("kw", [dict(mu=0.0), dict(mu=-1.0), dict(mu=float("nan")),
+                                dict(check_every=0), dict(eps=-1.0), dict(max_iter=-5),
+                                dict(lanes_row=3), dict(lanes_col=128)])
+def test_rejects_bad_options(kw):
+    a = GOOD
+    assert _try_create(a["m"], a["n"], a["rp"], a["ci"], a["va"], a["b"], a["c"], 3,
+                       **kw) == S.UV_EINVAL
+
+
+def test_rejects_empty_dimensions():
+    assert _try_create(0, 3, [0], [], [], [], [1.0, 1.0, 1.0], 3) == S.UV_EINVAL
+
+
+def test_rejects_nnz_mismatch():
+    """row_ptr[m] must equal the declared nnz."""
+    rp = np.array([0, 2, 3], np.int64)
+    ci = np.array([0, 2, 1], np.int32)
+    va = np.array([1.0, 2.0, 3.0])
+    b, c = np.ones(2), np.ones(3)
+    for nnz in (2, 4):
+        csr = S.UvCsr(2, 3, nnz, S._ptr(rp), S._ptr(ci), S._ptr(va))
+        cones = S.UvCones(3, 0, None)
+        h = ctypes.c_void_p()
+        rc = S.lib().solver_create(ctypes.byref(csr), S._ptr(b), S._ptr(c), ctypes.byref(cones),
+                                   None, ctypes.byref(h))
+        assert rc == S.UV_EBADCSR and not h.value
+
+
+def test_null_arguments():
+    L = S.lib()
+    h = ctypes.c_void_p()
+    assert L.solver_create(None, None, None, None, None, ctypes.byref(h)) == S.UV_EINVAL
+    assert L.solver_iterate(None, 1, None) == S.UV_EINVAL
+    assert L.solver_residuals(None, None) == S.UV_EINVAL
+    assert L.solver_solution(None, None, None, None, None) == S.UV_EINVAL
+    L.solver_destroy(None)

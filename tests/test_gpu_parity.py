@@ -1,0 +1,222 @@
+"""GPU parity: the HIP solver (through the C ABI) against the FP64 CPU oracle.
+
+The oracle runs Algorithm 1 literally (o-space y and gamma); the GPU runs the
+reduced form.  In exact arithmetic both produce the same iterates; in FP64
+they agree to rounding, and the bar is ||v_gpu - v_oracle||_inf <=
+1e-9 * ||v_oracle||_inf for v in {x, z, delta, lambda} after 200 iterations
+from the same start.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2203_05027_amd import instances as I
+from paper_2203_05027_amd.solver import Solver
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-9
+KEYS = ("x", "z", "delta", "lambda")
+
+
+def say(msg):
+    sys.__stderr__.write(f"[gpu-test] {msg}\n")
+    sys.__stderr__.flush()
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)) if b.size else 0.0
+
+
+def run_pair(inst, iters, mu=1.0, start=None, **kw):
+    say(f"m={inst['m']} n={inst['n']} nnz={inst['nnz']} iters={iters} mu={mu} {kw}")
+    orc = oracle.Oracle.from_instance(inst, mu=mu)
+    with Solver.from_instance(inst, mu=mu, eps=0.0, **kw) as s:
+        if start is not None:
+            orc.set_start(*start)
+            s.set_start(*start)
+        orc.iterate(iters)
+        s.iterate(iters)
+        g = s.solution()
+        gr = s.residuals()
+    o = orc.state()
+    return g, o, gr, orc.residuals()
+
+
+def assert_parity(g, o, tol=TOL64):
+    errs = {k: rel(g[k], o[k]) for k in KEYS}
+    say(f"rel errors {errs}")
+    for k in KEYS:
+        assert errs[k] <= tol, (k, errs[k])
+
+
+def test_small_lp_200_iterations():
+    g, o, gr, orr = run_pair(I.config_instance("lp_small"), 200)
+    assert_parity(g, o)
+    for k in ("r_prim", "r_dual", "r_gap", "kkt", "pobj", "dobj", "res_ax_b"):
+        assert abs(gr[k] - orr[k]) <= 1e-9 * max(abs(orr[k]), 1e-12), k
+    assert gr["iter"] == 200
+
+
+@pytest.mark.parametrize("lanes", [(1, 1), (2, 16), (64, 64), (32, 4)])
+@pytest.mark.parametrize("graph", [True, False])
+def test_launch_shapes(lanes, graph):
+    inst = I.lp_instance(333, 777, 4, seed=17)          # ragged: no size divides a tile
+    g, o, _, _ = run_pair(inst, 200, mu=0.7, lanes_row=lanes[0], lanes_col=lanes[1],
+                          use_graph=graph, check_every=7)
+    assert_parity(g, o)
+
+
+def test_scaled_large_lp_unit_rows():
+    inst = I.lp_instance(20_000, 40_000, 10, seed=1, unit_rows=True)
+    g, o, _, _ = run_pair(inst, 200)
+    assert_parity(g, o)
+
+
+def test_socp_200_iterations():
+    inst = I.socp_instance(400, 8, seed=2)
+    g, o, gr, orr = run_pair(inst, 200)
+    assert_parity(g, o)
+    assert abs(gr["kkt"] - orr["kkt"]) <= 1e-9 * orr["kkt"]
+
+
+def test_mixed_cones_big_and_size1():
+    """Orthant + SOCs of sizes 1 (a half line), 2, and above 256 columns
+    (one cone alone fills a wider tile)."""
+    sizes = [1, 2, 3, 700, 1, 50, 1024, 5] + [4] * 60
+    inst = I.conic_instance(900, 123, sizes, 3, seed=5)
+    g, o, _, _ = run_pair(inst, 200, mu=1.3)
+    assert_parity(g, o)
+
+
+def test_warm_start():
+    inst = I.socp_instance(60, 5, seed=8)
+    rng = np.random.default_rng(3)
+    n, m = inst["n"], inst["m"]
+    start = (rng.standard_normal(n), rng.standard_normal(n), rng.standard_normal(n),
+             rng.standard_normal(m))
+    g, o, _, _ = run_pair(inst, 200, mu=0.5, start=start)
+    assert_parity(g, o)
+
+
+def test_empty_rows_and_columns():
+    base = I.lp_instance(300, 700, 3, seed=4)
+    A = np.zeros((300, 700))
+    rows = np.repeat(np.arange(300), np.diff(base["row_ptr"]))
+    A[rows, base["col_idx"]] = base["val"]
+    A[:10, :] = 0.0
+    A[:, :20] = 0.0
+    rr, cc = np.nonzero(A)
+    row_ptr = np.zeros(301, np.int64)
+    np.cumsum(np.bincount(rr, minlength=300), out=row_ptr[1:])
+    inst = dict(base, row_ptr=row_ptr, col_idx=cc.astype(np.int32), val=A[rr, cc],
+                nnz=int(rr.size), b=A @ base["x0"])
+    g, o, _, _ = run_pair(inst, 200)
+    assert_parity(g, o)
+
+
+def test_no_nonzeros():
+    m, n = 5, 9
+    inst = dict(m=m, n=n, nnz=0, row_ptr=np.zeros(m + 1, np.int64), col_idx=np.zeros(0, np.int32),
+                val=np.zeros(0), b=np.zeros(m), c=np.linspace(-1, 1, n), n_orth=4,
+                soc_sizes=np.array([5], np.int32))
+    g, o, _, _ = run_pair(inst, 50)
+    assert_parity(g, o)
+
+
+def test_converges_at_same_check_as_oracle():
+    inst = I.config_instance("lp_small")
+    orc = oracle.Oracle.from_instance(inst)
+    ro = orc.solve(1e-4, check_every=10, max_iter=50_000)
+    say(f"oracle converged at {ro['iter']}")
+    with Solver.from_instance(inst, eps=1e-4, check_every=10) as s:
+        done = s.iterate(50_000)
+        r = s.residuals()
+    assert done and r["status"] == "converged"
+    assert r["iter"] == ro["iter"]
+    assert r["kkt"] <= 1e-4
+    assert abs(r["pobj"] - inst["p_star"]) <= 1e-3 * abs(inst["p_star"])
+
+
+def test_max_iter_and_resume():
+    inst = I.lp_instance(200, 400, 4, seed=6)
+    with Solver.from_instance(inst, eps=0.0, max_iter=25, check_every=10) as s:
+        assert s.iterate(100)
+        r = s.residuals()
+        assert r["status"] == "max_iter" and r["iter"] == 25
+    # checkpoint / resume: solution + resume continues the same trajectory
+    with Solver.from_instance(inst, eps=0.0) as a, Solver.from_instance(inst, eps=0.0) as b:
+        a.iterate(40)
+        sol = a.solution()
+        a.iterate(60)
+        b.resume(sol["x"], sol["z"], sol["delta"], sol["lambda"])
+        b.iterate(60)
+        assert_parity(b.solution(), a.solution(), tol=1e-12)
+
+
+def test_resume_matches_oracle_resume():
+    inst = I.socp_instance(80, 6, seed=14)
+    rng = np.random.default_rng(5)
+    st = (rng.standard_normal(inst["n"]), rng.standard_normal(inst["n"]),
+          rng.standard_normal(inst["n"]), rng.standard_normal(inst["m"]))
+    orc = oracle.Oracle.from_instance(inst, mu=0.9)
+    orc.resume(*st)
+    orc.iterate(150)
+    with Solver.from_instance(inst, mu=0.9, eps=0.0) as s:
+        s.resume(*st)
+        s.iterate(150)
+        assert_parity(s.solution(), orc.state())
+
+
+def test_residuals_off_check_iteration():
+    inst = I.socp_instance(50, 6, seed=9)
+    orc = oracle.Oracle.from_instance(inst)
+    orc.iterate(7)
+    with Solver.from_instance(inst, eps=0.0, check_every=10) as s:
+        s.iterate(7)
+        r = s.residuals()
+    ro = orc.residuals()
+    assert r["iter"] == 7
+    for k in ("r_prim", "r_dual", "r_gap", "pobj", "dobj"):
+        assert abs(r[k] - ro[k]) <= 1e-9 * max(abs(ro[k]), 1e-12), k
+
+
+def test_bitwise_reproducible():
+    inst = I.socp_instance(300, 8, seed=12)
+    outs = []
+    for graph in (True, True, False):
+        with Solver.from_instance(inst, eps=0.0, use_graph=graph) as s:
+            s.iterate(100)
+            outs.append(s.solution())
+    for o in outs[1:]:
+        for k in KEYS:
+            assert np.array_equal(o[k], outs[0][k])
+
+
+def test_mixed_precision_small_lp():
+    """FP32 sweep, FP64 duals and residuals: reaches 1e-4 and the objective
+    stays within the KKT bound of the oracle's optimum."""
+    inst = I.config_instance("lp_small")
+    g, o, _, _ = run_pair(inst, 200, precision="mixed")
+    errs = {k: rel(g[k], o[k]) for k in KEYS}
+    say(f"mixed vs fp64 oracle after 200 iterations: {errs}")
+    for k in KEYS:
+        assert errs[k] <= 1e-4, (k, errs[k])
+    with Solver.from_instance(inst, eps=1e-4, precision="mixed") as s:
+        assert s.iterate(60_000)
+        r = s.residuals()
+    say(f"mixed converged: {r}")
+    assert r["status"] == "converged" and r["kkt"] <= 1e-4
+    assert abs(r["pobj"] - inst["p_star"]) <= 2e-3 * abs(inst["p_star"])
+
+
+def test_mixed_precision_socp():
+    inst = I.socp_instance(400, 8, seed=2)
+    with Solver.from_instance(inst, eps=1e-4, precision="mixed") as s:
+        assert s.iterate(20_000)
+        r = s.residuals()
+    say(f"mixed socp: {r}")
+    assert r["status"] == "converged" and r["kkt"] <= 1e-4
+    assert inst["d_lower"] - 1e-3 <= r["pobj"] <= inst["p_upper"] + 1e-3

@@ -253,6 +253,25 @@ def test_iterate_invariants(oracle_mod, kind):
                                        atol=1e-11 * scale)
 
 
+def test_resume_continues_the_literal_run(oracle_mod):
+    """The full Algorithm 1 state at the end of an iteration is fixed by
+    (x, z, delta, lambda): resuming from those four continues the run that
+    kept y and gamma."""
+    inst = I.socp_instance(15, 4, seed=4)
+    a = oracle_mod.Oracle.from_instance(inst, mu=0.6)
+    a.iterate(30)
+    s = a.state()
+    b = oracle_mod.Oracle.from_instance(inst, mu=0.6)
+    b.resume(s["x"], s["z"], s["delta"], s["lambda"])
+    sb = b.state()
+    np.testing.assert_allclose(sb["y"], s["y"], atol=1e-12 * (1 + np.abs(s["y"]).max()))
+    np.testing.assert_allclose(sb["gamma"], s["gamma"], atol=1e-12 * (1 + np.abs(s["gamma"]).max()))
+    a.iterate(40)
+    b.iterate(40)
+    for k in ("x", "z", "delta", "lambda"):
+        np.testing.assert_allclose(b.state()[k], a.state()[k], atol=1e-11)
+
+
 @pytest.mark.parametrize("mu", [0.37, 1.0, 4.0])
 def test_fixed_point_at_known_optimum(oracle_mod, mu):
     """At a primal-dual optimum (x0, lambda = -y0, delta = s0) every vector
