@@ -54,8 +54,7 @@ def measure(inst, precision, steps, warmup, check_every, ttk_cap, mu, ttk=True):
     s = Solver.from_instance(inst, mu=mu, precision=precision, eps=0.0,
                              check_every=check_every)
     out["create_s"] = time.time() - t0
-    lr, lc = s.launch_shape()
-    out["lanes_row"], out["lanes_col"] = lr, lc
+    out.update(s.launch_shape())
     s.iterate(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -182,7 +181,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: LP m={m} n={n} nnz={nnz}, unit-norm rows, "
                                f"orthant cone, mu={args.mu}, check_every={args.check_every}",
-                   "lanes_row": main_r["lanes_row"], "lanes_col": main_r["lanes_col"]},
+                   "launch": {k: main_r[k] for k in ("lanes_row", "unroll_row", "lanes_col",
+                                                     "unroll_col")}},
         "time_to_1e-4_s": main_r["ttk_s"],
         "iters_to_1e-4": main_r["ttk_iters"],
         "ttk_status": main_r["ttk_status"],

@@ -101,6 +101,9 @@ typedef struct {
     int32_t lanes_col;    /* lanes per column in the A'u pass (same values) */
     int32_t use_graph;    /* 1 = replay check_every iterations as one captured
                              HIP graph; 0 = launch kernels one by one */
+    int32_t unroll_row;   /* gathers in flight per lane in the A x pass
+                             (0 = automatic; else 1, 2, 4 or 8) */
+    int32_t unroll_col;   /* same for the A'u pass */
 } uv_opts;
 
 /* Residuals at the last check, evaluated at (z, lambda, delta), all FP64
@@ -179,9 +182,10 @@ const char *solver_strerror(int code);
 int solver_time_kernels(uv_solver *s, int32_t iters, double *ms_col,
                         double *ms_row);
 
-/* The resolved launch shape: lanes per row and per column. */
-int solver_launch_shape(const uv_solver *s, int32_t *lanes_row,
-                        int32_t *lanes_col);
+/* The resolved launch shape: shape[0] lanes per row and shape[1] gathers in
+ * flight per lane in the row pass, shape[2], shape[3] the same for the
+ * column pass (shape holds 4 entries). */
+int solver_launch_shape(const uv_solver *s, int32_t *shape);
 
 #ifdef __cplusplus
 }

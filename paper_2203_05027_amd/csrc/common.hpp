@@ -21,9 +21,10 @@ __device__ __forceinline__ T group_sum(T v)
 }
 
 // Workgroup sum of K doubles, deterministic (wave butterfly, then thread 0
-// adds the per-wave totals in wave order).  Result valid in thread 0.
+// adds the per-wave totals in wave order).  Thread 0 writes component k to
+// out[k * stride].
 template <int K>
-__device__ __forceinline__ void block_sum(double (&v)[K], double *out)
+__device__ __forceinline__ void block_sum(double (&v)[K], double *out, int stride)
 {
     __shared__ double s[K][kWG / kWave];
 #pragma unroll
@@ -40,7 +41,7 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double *out)
             double t = 0.0;
 #pragma unroll
             for (int i = 0; i < kWG / kWave; ++i) t += s[k][i];
-            out[k] = t;
+            out[k * stride] = t;
         }
     }
 }

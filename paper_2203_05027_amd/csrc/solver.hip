@@ -210,7 +210,7 @@ k_norms(int m, const double *__restrict__ b, int n, const double *__restrict__ c
     for (int i = threadIdx.x; i < m; i += kWG) v[0] += b[i] * b[i];
     for (int j = threadIdx.x; j < n; j += kWG) v[1] += c[j] * c[j];
     double out[2];
-    uv::block_sum<2>(v, out);
+    uv::block_sum<2>(v, out, 1);
     if (threadIdx.x == 0) { st->bnorm2 = out[0]; st->cnorm2 = out[1]; }
 }
 
@@ -234,48 +234,64 @@ k_start(int m, const double *__restrict__ lam, T *__restrict__ u, double inv_mu,
 // ---------------------------------------------------------------------------
 
 // Dot product of one sparse row/column segment [beg, end) with a gathered
-// vector, L lanes cooperating (lane-strided, 2-way unrolled so two gathers
-// are in flight per lane).
-template <int L, typename T, typename TV>
+// vector: L lanes cooperate, lane-strided, and each lane issues E index and
+// value loads and then E gathers before it accumulates, so E gathers per
+// lane are in flight at once (the sweep is bound by gather latency, not by
+// arithmetic).  Slots past the segment's end reload its last entry (a cache
+// hit) and add zero, which keeps the loop free of divergent branches.  The
+// streamed index and value arrays are read with non-temporal loads so they
+// do not evict the gathered vector from the caches.
+template <int L, int E, typename T, typename TV>
 __device__ __forceinline__ T seg_dot(int beg, int end, int lane, const int *__restrict__ idx,
                                      const TV *__restrict__ val, const T *__restrict__ vec)
 {
-    T a0 = 0, a1 = 0;
-    int k = beg + lane;
-    for (; k + L < end; k += 2 * L) {
-        int j0 = idx[k], j1 = idx[k + L];
-        TV v0 = val[k], v1 = val[k + L];
-        a0 += (T)v0 * vec[j0];
-        a1 += (T)v1 * vec[j1];
+    T acc = 0;
+    for (int base = beg + lane; base < end; base += L * E) {
+        int j[E];
+        TV v[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = base + e * L;
+            const int kk = k < end ? k : end - 1;
+            j[e] = __builtin_nontemporal_load(idx + kk);
+            v[e] = __builtin_nontemporal_load(val + kk);
+        }
+        T g[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) g[e] = vec[j[e]];
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (base + e * L < end) acc += (T)v[e] * g[e];
     }
-    if (k < end) a0 += (T)val[k] * vec[idx[k]];
-    return uv::group_sum<L>(a0 + a1);
+    return uv::group_sum<L>(acc);
 }
 
 // Row pass.  MODE 0: iterate.  MODE 1: iterate and gather z for the
 // residual partials (||A z - b||^2, b'lambda, ||A x - b||^2) of the new
 // lambda.  MODE 2 (resume): u = F_U (b - A x) - lambda/mu with lambda kept,
 // which is the u an iteration leaves behind at this (x, lambda).
-template <typename T, int L, int MODE>
+template <typename T, int L, int E, int MODE>
 __global__ void __launch_bounds__(kWG)
 k_row(int m, const int *__restrict__ rp, const int *__restrict__ ci, const T *__restrict__ va,
       const T *__restrict__ x, const T *__restrict__ z, const T *__restrict__ b, const T *__restrict__ fu,
       double *__restrict__ lam, T *__restrict__ u, double mu, double inv_mu, double *__restrict__ part,
-      DevStatus *st)
+      int pstride, DevStatus *st)
 {
     if (MODE != 2 && st->done) return;
     const int lane = threadIdx.x & (L - 1);
     const int row = blockIdx.x * (kWG / L) + threadIdx.x / L;
     double acc[3] = {0.0, 0.0, 0.0};
     if (row < m) {
+        // epilogue operands first: independent of the gathers below
+        const T bi = b[row], fi = fu[row];
+        const double l0 = lam[row];
         const int beg = rp[row], end = rp[row + 1];
-        T q = seg_dot<L>(beg, end, lane, ci, va, x);
+        const T q = seg_dot<L, E>(beg, end, lane, ci, va, x);
         T qz = 0;
-        if (MODE == 1) qz = seg_dot<L>(beg, end, lane, ci, va, z);
+        if (MODE == 1) qz = seg_dot<L, E>(beg, end, lane, ci, va, z);
         if (lane == 0) {
-            const T bi = b[row];
-            const T e = fu[row] * (bi - q);
-            const double li = (MODE == 2) ? lam[row] : lam[row] - mu * (double)e;
+            const T e = fi * (bi - q);
+            const double li = (MODE == 2) ? l0 : l0 - mu * (double)e;
             if (MODE != 2) lam[row] = li;
             u[row] = (T)((double)e - li * inv_mu);
             if (MODE == 1) {
@@ -287,21 +303,22 @@ k_row(int m, const int *__restrict__ rp, const int *__restrict__ ci, const T *__
         }
     }
     if (MODE != 2 && blockIdx.x == 0 && threadIdx.x == 0) st->iter += 1;
-    if (MODE == 1) uv::block_sum<3>(acc, part + 3 * blockIdx.x);
+    if (MODE == 1) uv::block_sum<3>(acc, part + blockIdx.x, pstride);
 }
 
 // Residual-only row pass with FP64 values of A (same partial layout as the
-// CHECK row pass, with the row pass's lane count).
+// MODE 1 row pass, with the row pass's lane count).
 template <typename T, int L>
 __global__ void __launch_bounds__(kWG)
 k_res_row(int m, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ va,
           const T *__restrict__ x, const T *__restrict__ z, const double *__restrict__ b,
-          const double *__restrict__ lam, double *__restrict__ part)
+          const double *__restrict__ lam, double *__restrict__ part, int pstride)
 {
     const int lane = threadIdx.x & (L - 1);
     const int row = blockIdx.x * (kWG / L) + threadIdx.x / L;
     double acc[3] = {0.0, 0.0, 0.0};
     if (row < m) {
+        const double bi = b[row], li = lam[row];
         const int beg = rp[row], end = rp[row + 1];
         double qx = 0.0, qz = 0.0;
         for (int k = beg + lane; k < end; k += L) {
@@ -312,17 +329,25 @@ k_res_row(int m, const int *__restrict__ rp, const int *__restrict__ ci, const d
         qx = uv::group_sum<L>(qx);
         qz = uv::group_sum<L>(qz);
         if (lane == 0) {
-            const double bi = b[row];
             acc[0] = (qz - bi) * (qz - bi);
-            acc[1] = bi * lam[row];
+            acc[1] = bi * li;
             acc[2] = (qx - bi) * (qx - bi);
         }
     }
-    uv::block_sum<3>(acc, part + 3 * blockIdx.x);
+    uv::block_sum<3>(acc, part + blockIdx.x, pstride);
+}
+
+// x-step (Block 1) for one column from p = N x + A'u, and the projected
+// point v = x - delta/mu.
+template <typename T>
+__device__ __forceinline__ T x_step(int cnt, T xo, T zo, T atu, T dm, T cj, double inv_mu)
+{
+    const T p = (T)cnt * xo + atu;
+    return (p + zo + dm - cj * (T)inv_mu) / (T)(1 + cnt);
 }
 
 // Column pass over the orthant columns [0, n_orth).
-template <typename T, int L>
+template <typename T, int L, int E>
 __global__ void __launch_bounds__(kWG)
 k_col_orth(int n_orth, const int *__restrict__ cp, const int *__restrict__ ri, const T *__restrict__ vc,
            const T *__restrict__ u, T *__restrict__ x, T *__restrict__ z, double *__restrict__ delta,
@@ -332,14 +357,13 @@ k_col_orth(int n_orth, const int *__restrict__ cp, const int *__restrict__ ri, c
     const int lane = threadIdx.x & (L - 1);
     const int col = blockIdx.x * (kWG / L) + threadIdx.x / L;
     if (col >= n_orth) return;   // whole L-lane groups leave together
+    const T xo = x[col], zo = z[col], cj = c[col];
+    const double d = delta[col];
     const int beg = cp[col], end = cp[col + 1];
-    const T atu = seg_dot<L>(beg, end, lane, ri, vc, u);
+    const T atu = seg_dot<L, E>(beg, end, lane, ri, vc, u);
     if (lane == 0) {
-        const int cnt = end - beg;
-        const double d = delta[col];
         const T dm = (T)(d * inv_mu);
-        const T p = (T)cnt * x[col] + atu;
-        const T xn = (p + z[col] + dm - c[col] * (T)inv_mu) / (T)(1 + cnt);
+        const T xn = x_step<T>(end - beg, xo, zo, atu, dm, cj, inv_mu);
         const T v = xn - dm;
         const T zn = v > (T)0 ? v : (T)0;
         x[col] = xn;
@@ -353,7 +377,7 @@ k_col_orth(int n_orth, const int *__restrict__ cp, const int *__restrict__ ri, c
 // columns): phase 1 computes x and v = x - delta/mu per column into LDS,
 // phase 2 takes each cone's tail norm and its projection case (eq. proj),
 // phase 3 writes x, z and delta.
-template <typename T, int L, int TC>
+template <typename T, int L, int E, int TC>
 __global__ void __launch_bounds__(kWG)
 k_col_soc(const int *__restrict__ tcol, const int *__restrict__ tcone, const int *__restrict__ soc_off,
           const int *__restrict__ cp, const int *__restrict__ ri, const T *__restrict__ vc,
@@ -376,14 +400,13 @@ k_col_soc(const int *__restrict__ tcol, const int *__restrict__ tcone, const int
 
     for (int jj = threadIdx.x / L; jj < ncols; jj += kWG / L) {
         const int col = c0 + jj;
+        const T xo = x[col], zo = z[col], cj = c[col];
+        const double d = delta[col];
         const int beg = cp[col], end = cp[col + 1];
-        const T atu = seg_dot<L>(beg, end, lane, ri, vc, u);
+        const T atu = seg_dot<L, E>(beg, end, lane, ri, vc, u);
         if (lane == 0) {
-            const int cnt = end - beg;
-            const double d = delta[col];
             const T dm = (T)(d * inv_mu);
-            const T p = (T)cnt * x[col] + atu;
-            const T xn = (p + z[col] + dm - c[col] * (T)inv_mu) / (T)(1 + cnt);
+            const T xn = x_step<T>(end - beg, xo, zo, atu, dm, cj, inv_mu);
             sx[jj] = xn;
             sv[jj] = xn - dm;
             sd[jj] = d;
@@ -423,42 +446,62 @@ template <typename T, int L>
 __global__ void __launch_bounds__(kWG)
 k_res_col(int n, const int *__restrict__ cp, const int *__restrict__ ri, const double *__restrict__ vc,
           const double *__restrict__ lam, const double *__restrict__ c, const double *__restrict__ delta,
-          const T *__restrict__ z, double *__restrict__ part)
+          const T *__restrict__ z, double *__restrict__ part, int pstride)
 {
     const int lane = threadIdx.x & (L - 1);
     const int col = blockIdx.x * (kWG / L) + threadIdx.x / L;
     double acc[2] = {0.0, 0.0};
     if (col < n) {
-        double a = 0.0;
-        for (int k = cp[col] + lane; k < cp[col + 1]; k += L) a += vc[k] * lam[ri[k]];
-        a = uv::group_sum<L>(a);
+        const double cj = c[col], dj = delta[col], zj = (double)z[col];
+        const double a = seg_dot<L, 4>(cp[col], cp[col + 1], lane, ri, vc, lam);
         if (lane == 0) {
-            const double r = a + c[col] - delta[col];
+            const double r = a + cj - dj;
             acc[0] = r * r;
-            acc[1] = c[col] * (double)z[col];
+            acc[1] = cj * zj;
         }
     }
-    uv::block_sum<2>(acc, part + 2 * blockIdx.x);
+    uv::block_sum<2>(acc, part + blockIdx.x, pstride);
 }
 
-// Adds the partials in a fixed order, forms the residuals and decides
-// whether to stop.
+// Adds the partials in a fixed order (eight independent loads in flight
+// per thread), forms the residuals and decides whether to stop.  Partials
+// are stored component-major: prow[k * nrow + block].
 __global__ void __launch_bounds__(kWG)
 k_finalize(int nrow, const double *__restrict__ prow, int ncol, const double *__restrict__ pcol,
            double eps, DevStatus *st)
 {
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int i = threadIdx.x; i < nrow; i += kWG) {
-        v[0] += prow[3 * i];
-        v[1] += prow[3 * i + 1];
-        v[2] += prow[3 * i + 2];
+    for (int base = threadIdx.x; base < nrow; base += 8 * kWG) {
+        double a[3][8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int i = base + r * kWG;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) a[k][r] = i < nrow ? prow[k * nrow + i] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            v[0] += a[0][r];
+            v[1] += a[1][r];
+            v[2] += a[2][r];
+        }
     }
-    for (int i = threadIdx.x; i < ncol; i += kWG) {
-        v[3] += pcol[2 * i];
-        v[4] += pcol[2 * i + 1];
+    for (int base = threadIdx.x; base < ncol; base += 8 * kWG) {
+        double a[2][8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int i = base + r * kWG;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) a[k][r] = i < ncol ? pcol[k * ncol + i] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            v[3] += a[0][r];
+            v[4] += a[1][r];
+        }
     }
     double s[5];
-    uv::block_sum<5>(v, s);
+    uv::block_sum<5>(v, s, 1);
     if (threadIdx.x != 0) return;
     const double rp = sqrt(s[0]) / (1.0 + sqrt(st->bnorm2));
     const double rd = sqrt(s[3]) / (1.0 + sqrt(st->cnorm2));
@@ -515,7 +558,8 @@ struct uv_solver {
     int ntiles = 0, tile_cap = kSocTile;
     DevStatus *st = nullptr;
     DevStatus *st_host = nullptr;             // pinned
-    int L_row = 8, L_col = 4;
+    int L_row = 8, L_col = 4;   // lanes per row / column
+    int E_row = 4, E_col = 4;   // gathers in flight per lane
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int64_t host_iter = 0;
@@ -547,97 +591,136 @@ int pick_lanes(double avg)
 
 bool lanes_ok(int L) { return L == 0 || (L >= 1 && L <= 64 && (L & (L - 1)) == 0); }
 
-// ---- launch helpers (dispatch on precision and lane count) ----
+bool unroll_ok(int E) { return E == 0 || E == 1 || E == 2 || E == 4 || E == 8; }
 
-template <typename T, int L, int MODE>
-void launch_row_mode(uv_solver *s, hipStream_t st)
+// ---- launch helpers (dispatch on precision, lanes L and unroll E) ----
+
+template <typename T, int L, int E>
+struct RowLaunch {
+    static void run(uv_solver *s, hipStream_t st, int mode)
+    {
+        const unsigned g = blocks_for(s->m, kWG / L);
+        const double mu = s->o.mu, im = 1.0 / s->o.mu;
+#define UV_ROW_ARGS                                                                                        \
+    s->m, s->rp, s->ci, (const T *)s->va, (const T *)s->x, (const T *)s->z, (const T *)s->b,              \
+        (const T *)s->fu, s->lam, (T *)s->u, mu, im, s->part_row, s->nblk_row, s->st
+        if (mode == 1) k_row<T, L, E, 1><<<g, kWG, 0, st>>>(UV_ROW_ARGS);
+        else if (mode == 2) k_row<T, L, E, 2><<<g, kWG, 0, st>>>(UV_ROW_ARGS);
+        else k_row<T, L, E, 0><<<g, kWG, 0, st>>>(UV_ROW_ARGS);
+#undef UV_ROW_ARGS
+    }
+};
+
+template <typename T, int L, int E>
+struct ColLaunch {
+    static void run(uv_solver *s, hipStream_t st, int)
+    {
+        const double mu = s->o.mu, im = 1.0 / s->o.mu;
+        if (s->n_orth > 0) {
+            const unsigned g = blocks_for(s->n_orth, kWG / L);
+            k_col_orth<T, L, E><<<g, kWG, 0, st>>>(s->n_orth, s->cp, s->ri, (const T *)s->vc, (const T *)s->u,
+                                                   (T *)s->x, (T *)s->z, s->delta, (const T *)s->c, mu, im,
+                                                   s->st);
+        }
+        if (s->ntiles > 0) {
+#define UV_SOC_ARGS                                                                                        \
+    s->tcol, s->tcone, s->soc_off, s->cp, s->ri, (const T *)s->vc, (const T *)s->u, (T *)s->x, (T *)s->z, \
+        s->delta, (const T *)s->c, mu, im, s->st
+            if (s->tile_cap <= kSocTile) k_col_soc<T, L, E, kSocTile><<<s->ntiles, kWG, 0, st>>>(UV_SOC_ARGS);
+            else k_col_soc<T, L, E, UV_MAX_CONE><<<s->ntiles, kWG, 0, st>>>(UV_SOC_ARGS);
+#undef UV_SOC_ARGS
+        }
+    }
+};
+
+template <typename T, int L, int E>
+struct ResRowLaunch {
+    static void run(uv_solver *s, hipStream_t st, int)
+    {
+        const unsigned g = blocks_for(s->m, kWG / L);
+        k_res_row<T, L><<<g, kWG, 0, st>>>(s->m, s->rp, s->ci, s->va64, (const T *)s->x, (const T *)s->z,
+                                           s->b64, s->lam, s->part_row, s->nblk_row);
+    }
+};
+
+template <typename T, int L, int E>
+struct ResColLaunch {
+    static void run(uv_solver *s, hipStream_t st, int)
+    {
+        const unsigned g = blocks_for(s->n, kWG / L);
+        k_res_col<T, L><<<g, kWG, 0, st>>>(s->n, s->cp, s->ri, s->vc64, s->lam, s->c64, s->delta,
+                                           (const T *)s->z, s->part_col, s->nblk_rescol);
+    }
+};
+
+template <template <typename, int, int> class F, typename T, int L>
+void dispatch_e(int E, uv_solver *s, hipStream_t st, int mode)
 {
-    const unsigned g = blocks_for(s->m, kWG / L);
-    const double mu = s->o.mu, im = 1.0 / s->o.mu;
-    k_row<T, L, MODE><<<g, kWG, 0, st>>>(s->m, s->rp, s->ci, (const T *)s->va, (const T *)s->x,
-                                         (const T *)s->z, (const T *)s->b, (const T *)s->fu, s->lam,
-                                         (T *)s->u, mu, im, s->part_row, s->st);
+    switch (E) {
+    case 1: F<T, L, 1>::run(s, st, mode); break;
+    case 2: F<T, L, 2>::run(s, st, mode); break;
+    case 4: F<T, L, 4>::run(s, st, mode); break;
+    default: F<T, L, 8>::run(s, st, mode); break;
+    }
 }
+
+template <template <typename, int, int> class F, typename T>
+void dispatch_le(int L, int E, uv_solver *s, hipStream_t st, int mode)
+{
+    switch (L) {
+    case 1: dispatch_e<F, T, 1>(E, s, st, mode); break;
+    case 2: dispatch_e<F, T, 2>(E, s, st, mode); break;
+    case 4: dispatch_e<F, T, 4>(E, s, st, mode); break;
+    case 8: dispatch_e<F, T, 8>(E, s, st, mode); break;
+    case 16: dispatch_e<F, T, 16>(E, s, st, mode); break;
+    case 32: dispatch_e<F, T, 32>(E, s, st, mode); break;
+    default: dispatch_e<F, T, 64>(E, s, st, mode); break;
+    }
+}
+
+template <template <typename, int, int> class F>
+void dispatch(uv_solver *s, hipStream_t st, int L, int E, int mode)
+{
+    if (s->o.precision == UV_MIXED) dispatch_le<F, float>(L, E, s, st, mode);
+    else dispatch_le<F, double>(L, E, s, st, mode);
+}
+
+template <template <typename, int, int> class F>
+void dispatch_le_res(uv_solver *s, hipStream_t st, int L)
+{
+    const bool mixed = s->o.precision == UV_MIXED;
+    switch (L) {
+#define UV_RES_CASE(LL)                                   \
+    case LL:                                              \
+        if (mixed) F<float, LL, 4>::run(s, st, 0);        \
+        else F<double, LL, 4>::run(s, st, 0);             \
+        break;
+        UV_RES_CASE(1) UV_RES_CASE(2) UV_RES_CASE(4) UV_RES_CASE(8) UV_RES_CASE(16) UV_RES_CASE(32)
+    default:
+        if (mixed) F<float, 64, 4>::run(s, st, 0);
+        else F<double, 64, 4>::run(s, st, 0);
+        break;
+#undef UV_RES_CASE
+    }
+}
+
+void launch_col(uv_solver *s, hipStream_t st) { dispatch<ColLaunch>(s, st, s->L_col, s->E_col, 0); }
 
 // mode: 0 iterate, 1 iterate + residual partials (FP64 only), 2 resume
-template <typename T, int L>
-void launch_row_t(uv_solver *s, hipStream_t st, int mode)
-{
-    if (mode == 1) launch_row_mode<T, L, 1>(s, st);
-    else if (mode == 2) launch_row_mode<T, L, 2>(s, st);
-    else launch_row_mode<T, L, 0>(s, st);
-}
-
-template <typename T, int L>
-void launch_res_row_t(uv_solver *s, hipStream_t st)
-{
-    const unsigned g = blocks_for(s->m, kWG / L);
-    k_res_row<T, L><<<g, kWG, 0, st>>>(s->m, s->rp, s->ci, s->va64, (const T *)s->x, (const T *)s->z, s->b64,
-                                       s->lam, s->part_row);
-}
-
-template <typename T, int L>
-void launch_col_t(uv_solver *s, hipStream_t st)
-{
-    const double mu = s->o.mu, im = 1.0 / s->o.mu;
-    if (s->n_orth > 0) {
-        const unsigned g = blocks_for(s->n_orth, kWG / L);
-        k_col_orth<T, L><<<g, kWG, 0, st>>>(s->n_orth, s->cp, s->ri, (const T *)s->vc, (const T *)s->u,
-                                            (T *)s->x, (T *)s->z, s->delta, (const T *)s->c, mu, im, s->st);
-    }
-    if (s->ntiles > 0) {
-        if (s->tile_cap <= kSocTile)
-            k_col_soc<T, L, kSocTile><<<s->ntiles, kWG, 0, st>>>(
-                s->tcol, s->tcone, s->soc_off, s->cp, s->ri, (const T *)s->vc, (const T *)s->u, (T *)s->x,
-                (T *)s->z, s->delta, (const T *)s->c, mu, im, s->st);
-        else
-            k_col_soc<T, L, UV_MAX_CONE><<<s->ntiles, kWG, 0, st>>>(
-                s->tcol, s->tcone, s->soc_off, s->cp, s->ri, (const T *)s->vc, (const T *)s->u, (T *)s->x,
-                (T *)s->z, s->delta, (const T *)s->c, mu, im, s->st);
-    }
-}
-
-template <typename T, int L>
-void launch_res_col_t(uv_solver *s, hipStream_t st)
-{
-    const unsigned g = blocks_for(s->n, kWG / L);
-    k_res_col<T, L><<<g, kWG, 0, st>>>(s->n, s->cp, s->ri, s->vc64, s->lam, s->c64, s->delta, (const T *)s->z,
-                                       s->part_col);
-}
-
-#define UV_LANE_SWITCH(L, FN, T, ...)                 \
-    switch (L) {                                     \
-    case 1: FN<T, 1>(__VA_ARGS__); break;            \
-    case 2: FN<T, 2>(__VA_ARGS__); break;            \
-    case 4: FN<T, 4>(__VA_ARGS__); break;            \
-    case 8: FN<T, 8>(__VA_ARGS__); break;            \
-    case 16: FN<T, 16>(__VA_ARGS__); break;          \
-    case 32: FN<T, 32>(__VA_ARGS__); break;          \
-    default: FN<T, 64>(__VA_ARGS__); break;          \
-    }
-
-void launch_col(uv_solver *s, hipStream_t st)
-{
-    if (s->o.precision == UV_MIXED) { UV_LANE_SWITCH(s->L_col, launch_col_t, float, s, st) }
-    else { UV_LANE_SWITCH(s->L_col, launch_col_t, double, s, st) }
-}
-
 void launch_row(uv_solver *s, hipStream_t st, int mode)
 {
-    if (s->o.precision == UV_MIXED) { UV_LANE_SWITCH(s->L_row, launch_row_t, float, s, st, mode == 1 ? 0 : mode) }
-    else { UV_LANE_SWITCH(s->L_row, launch_row_t, double, s, st, mode) }
+    if (s->o.precision == UV_MIXED && mode == 1) mode = 0;
+    dispatch<RowLaunch>(s, st, s->L_row, s->E_row, mode);
 }
 
 // Residual evaluation of the current state.  In FP64 mode right after a
-// CHECK row pass only the column residuals remain.
+// MODE 1 row pass only the column residuals remain.  The residual kernels
+// take one fixed unroll; their lane counts follow the sweep's so the
+// partial arrays are sized once.
 void launch_residuals(uv_solver *s, hipStream_t st, bool row_done)
 {
-    if (!row_done) {
-        if (s->o.precision == UV_MIXED) { UV_LANE_SWITCH(s->L_row, launch_res_row_t, float, s, st) }
-        else { UV_LANE_SWITCH(s->L_row, launch_res_row_t, double, s, st) }
-    }
-    if (s->o.precision == UV_MIXED) { UV_LANE_SWITCH(s->L_col, launch_res_col_t, float, s, st) }
-    else { UV_LANE_SWITCH(s->L_col, launch_res_col_t, double, s, st) }
+    if (!row_done) dispatch_le_res<ResRowLaunch>(s, st, s->L_row);
+    dispatch_le_res<ResColLaunch>(s, st, s->L_col);
     k_finalize<<<1, kWG, 0, st>>>(s->nblk_row, s->part_row, s->nblk_rescol, s->part_col, s->o.eps_kkt, s->st);
 }
 
@@ -675,6 +758,7 @@ int validate(const uv_csr *A, const double *b, const double *c, const uv_cones *
     if (o->precision != UV_FP64 && o->precision != UV_MIXED) return UV_EINVAL;
     if (o->check_every < 1 || !(o->eps_kkt >= 0.0) || o->max_iter < 0) return UV_EINVAL;
     if (!lanes_ok(o->lanes_row) || !lanes_ok(o->lanes_col)) return UV_EINVAL;
+    if (!unroll_ok(o->unroll_row) || !unroll_ok(o->unroll_col)) return UV_EINVAL;
     if (A->nnz > 0 && (!A->col_idx || !A->val)) return UV_EINVAL;
     if (!A->row_ptr) return UV_EINVAL;
     if (A->nnz >= ((int64_t)1 << 31)) return UV_ETOOBIG;
@@ -848,6 +932,8 @@ void uv_default_opts(uv_opts *o)
     o->lanes_row = 0;
     o->lanes_col = 0;
     o->use_graph = 1;
+    o->unroll_row = 0;
+    o->unroll_col = 0;
 }
 
 const char *solver_strerror(int code)
@@ -898,6 +984,8 @@ int solver_create(const uv_csr *A, const double *b, const double *c, const uv_co
     s->o = o;
     s->L_row = o.lanes_row ? o.lanes_row : pick_lanes((double)A->nnz / A->m);
     s->L_col = o.lanes_col ? o.lanes_col : pick_lanes((double)A->nnz / A->n);
+    s->E_row = o.unroll_row ? o.unroll_row : 4;
+    s->E_col = o.unroll_col ? o.unroll_col : 4;
     rc = setup(s, A, b, c, K);
     if (rc == UV_OK) rc = solver_set_start(s, nullptr, nullptr, nullptr, nullptr);
     if (rc == UV_OK && s->o.use_graph) rc = build_graph(s);
@@ -1084,11 +1172,13 @@ int solver_time_kernels(uv_solver *s, int32_t iters, double *ms_col, double *ms_
     return rc;
 }
 
-int solver_launch_shape(const uv_solver *s, int32_t *lanes_row, int32_t *lanes_col)
+int solver_launch_shape(const uv_solver *s, int32_t *shape)
 {
-    if (!s) return UV_EINVAL;
-    if (lanes_row) *lanes_row = s->L_row;
-    if (lanes_col) *lanes_col = s->L_col;
+    if (!s || !shape) return UV_EINVAL;
+    shape[0] = s->L_row;
+    shape[1] = s->E_row;
+    shape[2] = s->L_col;
+    shape[3] = s->E_col;
     return UV_OK;
 }
 

@@ -35,7 +35,8 @@ class UvOpts(ctypes.Structure):
                 ("check_every", ctypes.c_int32), ("eps_kkt", ctypes.c_double),
                 ("max_iter", ctypes.c_int64), ("hip_stream", ctypes.c_void_p),
                 ("lanes_row", ctypes.c_int32), ("lanes_col", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("unroll_row", ctypes.c_int32),
+                ("unroll_col", ctypes.c_int32)]
 
 
 class UvResiduals(ctypes.Structure):
@@ -87,7 +88,7 @@ def lib():
     L.solver_time_kernels.argtypes = [P, i32, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_double)]
     L.solver_time_kernels.restype = ctypes.c_int
-    L.solver_launch_shape.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.solver_launch_shape.argtypes = [P, ctypes.POINTER(i32)]
     L.solver_launch_shape.restype = ctypes.c_int
     _lib = L
     return L
@@ -127,7 +128,8 @@ class Solver:
 
     def __init__(self, m, n, row_ptr, col_idx, val, b, c, n_orth, soc_sizes=(), *,
                  mu=1.0, precision="fp64", check_every=10, eps=1e-4, max_iter=0,
-                 lanes_row=0, lanes_col=0, use_graph=True, stream=None):
+                 lanes_row=0, lanes_col=0, unroll_row=0, unroll_col=0, use_graph=True,
+                 stream=None):
         L = lib()
         self.m, self.n = int(m), int(n)
         rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
@@ -144,6 +146,7 @@ class Solver:
         o.max_iter = int(max_iter)
         o.hip_stream = stream
         o.lanes_row, o.lanes_col = int(lanes_row), int(lanes_col)
+        o.unroll_row, o.unroll_col = int(unroll_row), int(unroll_col)
         o.use_graph = 1 if use_graph else 0
         self.precision = precision
         self.nnz = csr.nnz
@@ -214,8 +217,8 @@ class Solver:
                "solver_time_kernels")
         return a.value, b.value
 
-    def launch_shape(self):
-        a, b = ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().solver_launch_shape(self._h, ctypes.byref(a), ctypes.byref(b)),
-               "solver_launch_shape")
-        return a.value, b.value
+    def launch_shape(self) -> dict:
+        """Lanes and gathers in flight per lane of the row and column passes."""
+        a = (ctypes.c_int32 * 4)()
+        _check(lib().solver_launch_shape(self._h, a), "solver_launch_shape")
+        return {"lanes_row": a[0], "unroll_row": a[1], "lanes_col": a[2], "unroll_col": a[3]}

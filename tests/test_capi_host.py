@@ -91,7 +91,8 @@ def test_rejects_oversized_cone():
 
 @pytest.mark.parametrize("kw", [dict(mu=0.0), dict(mu=-1.0), dict(mu=float("nan")),
                                 dict(check_every=0), dict(eps=-1.0), dict(max_iter=-5),
-                                dict(lanes_row=3), dict(lanes_col=128)])
+                                dict(lanes_row=3), dict(lanes_col=128), dict(unroll_row=3),
+                                dict(unroll_col=16)])
 def test_rejects_bad_options(kw):
     a = GOOD
     assert _try_create(a["m"], a["n"], a["rp"], a["ci"], a["va"], a["b"], a["c"], 3,

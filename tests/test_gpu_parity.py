@@ -60,12 +60,21 @@ def test_small_lp_200_iterations():
     assert gr["iter"] == 200
 
 
-@pytest.mark.parametrize("lanes", [(1, 1), (2, 16), (64, 64), (32, 4)])
+@pytest.mark.parametrize("lanes,unroll", [((1, 1), (1, 8)), ((2, 16), (8, 1)), ((64, 64), (2, 4)),
+                                          ((32, 4), (4, 2)), ((4, 2), (8, 8))])
 @pytest.mark.parametrize("graph", [True, False])
-def test_launch_shapes(lanes, graph):
+def test_launch_shapes(lanes, unroll, graph):
     inst = I.lp_instance(333, 777, 4, seed=17)          # ragged: no size divides a tile
     g, o, _, _ = run_pair(inst, 200, mu=0.7, lanes_row=lanes[0], lanes_col=lanes[1],
-                          use_graph=graph, check_every=7)
+                          unroll_row=unroll[0], unroll_col=unroll[1], use_graph=graph,
+                          check_every=7)
+    assert_parity(g, o)
+
+
+@pytest.mark.parametrize("unroll", [1, 2, 8])
+def test_socp_unroll_shapes(unroll):
+    inst = I.socp_instance(150, 8, seed=21)
+    g, o, _, _ = run_pair(inst, 100, unroll_row=unroll, unroll_col=unroll, lanes_col=2)
     assert_parity(g, o)
 
 
