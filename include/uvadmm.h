@@ -187,6 +187,60 @@ int solver_time_kernels(uv_solver *s, int32_t iters, double *ms_col,
  * column pass (shape holds 4 entries). */
 int solver_launch_shape(const uv_solver *s, int32_t *shape);
 
+/* ------------------------------------------------------------------------
+ * Batched solver: many independent problems with the orthant cone
+ * (min c_i'x s.t. A_i x = b_i, x >= 0), solved together.  One persistent
+ * launch (replayed as a captured HIP graph) gives each workgroup one
+ * instance at a time, longest first; x and u of the instance live in LDS,
+ * so (m_i + n_i) * 4 bytes (UV_MIXED) or * 8 bytes (UV_FP64) must fit in
+ * 160 KiB.  The iteration, residuals and stopping rule are those of the
+ * single-problem solver; each instance keeps its own iteration count and
+ * status, and an instance that has stopped is skipped by later launches.
+ * ------------------------------------------------------------------------ */
+typedef struct uv_batch uv_batch;
+
+/* count instances; A[i] in CSR, b[i] (A[i].m doubles), c[i] (A[i].n
+ * doubles).  opts as for solver_create (lanes and unroll fields unused; the
+ * tiles below set the lanes).  Everything is copied.  UV_ETOOBIG if an
+ * instance's x and u do not fit in LDS or the totals reach 2^31. */
+int batch_create(int32_t count, const uv_csr *A, const double *const *b,
+                 const double *const *c, const uv_opts *opts, uv_batch **out);
+
+/* Runs up to k more iterations of every running instance; *n_active (may
+ * be NULL) receives the number still running afterwards. */
+int batch_iterate(uv_batch *h, int64_t k, int32_t *n_active);
+
+/* Residuals / status of instance i at its last check (see uv_residuals). */
+int batch_residuals(uv_batch *h, int32_t i, uv_residuals *r);
+
+/* Iterate of instance i into caller-owned host buffers (any may be NULL):
+ * x, z, delta (n_i doubles), lambda (m_i doubles). */
+int batch_solution(uv_batch *h, int32_t i, double *x, double *z,
+                   double *lambda, double *delta);
+
+/* Starting point of instance i (as solver_set_start); resets its iteration
+ * count and status so later launches run it again. */
+int batch_set_start(uv_batch *h, int32_t i, const double *x, const double *z,
+                    const double *delta, const double *lambda);
+
+/* Launch tiles: threads per workgroup (64..1024, a power of two) and
+ * lanes[8] = (lanes per row, lanes per column) for the four size buckets
+ * m < 128, m < 512, m < 2048, m >= 2048 (powers of two, <= threads). */
+int batch_set_tiles(uv_batch *h, int32_t threads, const int32_t *lanes);
+int batch_get_tiles(const uv_batch *h, int32_t *threads, int32_t *lanes);
+
+/* Measurement for the tile search: duration (ms) of one launch running
+ * `iters` iterations of the instances of one size bucket (0..3, or -1 for
+ * all) with the current tiles.  The state is saved before and restored
+ * after, so timing does not advance any instance. */
+int batch_time(uv_batch *h, int32_t bucket, int32_t iters, double *ms);
+
+/* info[0..5] = count, total rows, total columns, total nonzeros,
+ * workgroups per launch, LDS bytes per workgroup. */
+int batch_info(const uv_batch *h, int64_t *info);
+
+void batch_destroy(uv_batch *h);
+
 #ifdef __cplusplus
 }
 #endif

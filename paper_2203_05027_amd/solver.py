@@ -222,3 +222,141 @@ class Solver:
         a = (ctypes.c_int32 * 4)()
         _check(lib().solver_launch_shape(self._h, a), "solver_launch_shape")
         return {"lanes_row": a[0], "unroll_row": a[1], "lanes_col": a[2], "unroll_col": a[3]}
+
+
+def _bind_batch(L):
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.batch_create.argtypes = [i32, P, P, P, ctypes.POINTER(UvOpts), ctypes.POINTER(P)]
+    L.batch_create.restype = ctypes.c_int
+    L.batch_iterate.argtypes = [P, i64, ctypes.POINTER(i32)]
+    L.batch_iterate.restype = ctypes.c_int
+    L.batch_residuals.argtypes = [P, i32, ctypes.POINTER(UvResiduals)]
+    L.batch_residuals.restype = ctypes.c_int
+    L.batch_solution.argtypes = [P, i32, P, P, P, P]
+    L.batch_solution.restype = ctypes.c_int
+    L.batch_set_start.argtypes = [P, i32, P, P, P, P]
+    L.batch_set_start.restype = ctypes.c_int
+    L.batch_set_tiles.argtypes = [P, i32, P]
+    L.batch_set_tiles.restype = ctypes.c_int
+    L.batch_get_tiles.argtypes = [P, ctypes.POINTER(i32), P]
+    L.batch_get_tiles.restype = ctypes.c_int
+    L.batch_time.argtypes = [P, i32, i32, ctypes.POINTER(ctypes.c_double)]
+    L.batch_time.restype = ctypes.c_int
+    L.batch_info.argtypes = [P, P]
+    L.batch_info.restype = ctypes.c_int
+    L.batch_destroy.argtypes = [P]
+    L.batch_destroy.restype = None
+
+
+class Batch:
+    """Many independent LPs (orthant cone) solved together on the GPU by one
+    persistent launch.  ``instances`` is a list of dicts with m, n, row_ptr,
+    col_idx, val, b, c."""
+
+    BUCKETS = (0, 128, 512, 2048)  # lower bounds of the size buckets on m
+
+    def __init__(self, instances, *, mu=1.0, precision="mixed", check_every=10, eps=1e-4,
+                 max_iter=0, use_graph=True, stream=None):
+        L = lib()
+        if not hasattr(L, "_batch_bound"):
+            _bind_batch(L)
+            L._batch_bound = True
+        self.count = len(instances)
+        self.ms = [int(i["m"]) for i in instances]
+        self.ns = [int(i["n"]) for i in instances]
+        keep = []
+        csrs = (UvCsr * self.count)()
+        bp = (ctypes.c_void_p * self.count)()
+        cpp = (ctypes.c_void_p * self.count)()
+        for k, inst in enumerate(instances):
+            rp = np.ascontiguousarray(inst["row_ptr"], dtype=np.int64)
+            ci = np.ascontiguousarray(inst["col_idx"], dtype=np.int32)
+            va = np.ascontiguousarray(inst["val"], dtype=np.float64)
+            bb = _f64(inst["b"], self.ms[k])
+            cc = _f64(inst["c"], self.ns[k])
+            keep += [rp, ci, va, bb, cc]
+            csrs[k] = UvCsr(self.ms[k], self.ns[k], int(rp[-1]), _ptr(rp), _ptr(ci), _ptr(va))
+            bp[k] = bb.ctypes.data
+            cpp[k] = cc.ctypes.data
+        o = default_opts()
+        o.mu = float(mu)
+        o.precision = {"fp64": UV_FP64, "mixed": UV_MIXED}[precision]
+        o.check_every = int(check_every)
+        o.eps_kkt = float(eps)
+        o.max_iter = int(max_iter)
+        o.hip_stream = stream
+        o.use_graph = 1 if use_graph else 0
+        self.precision = precision
+        h = ctypes.c_void_p()
+        _check(L.batch_create(self.count, csrs, bp, cpp, ctypes.byref(o), ctypes.byref(h)),
+               "batch_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def iterate(self, k: int) -> int:
+        """Runs up to k iterations of every running instance; returns how
+        many are still running."""
+        a = ctypes.c_int32(0)
+        _check(lib().batch_iterate(self._h, int(k), ctypes.byref(a)), "batch_iterate")
+        return a.value
+
+    def residuals(self, i: int) -> dict:
+        r = UvResiduals()
+        _check(lib().batch_residuals(self._h, int(i), ctypes.byref(r)), "batch_residuals")
+        d = {k: getattr(r, k) for k, _ in UvResiduals._fields_}
+        d["status"] = STATUS.get(d["status"], d["status"])
+        return d
+
+    def solution(self, i: int) -> dict:
+        n, m = self.ns[i], self.ms[i]
+        x, z, d, lam = np.empty(n), np.empty(n), np.empty(n), np.empty(m)
+        _check(lib().batch_solution(self._h, int(i), _ptr(x), _ptr(z), _ptr(lam), _ptr(d)),
+               "batch_solution")
+        return {"x": x, "z": z, "delta": d, "lambda": lam}
+
+    def set_start(self, i: int, x=None, z=None, delta=None, lam=None):
+        n, m = self.ns[i], self.ms[i]
+        args = (_f64(x, n), _f64(z, n), _f64(delta, n), _f64(lam, m))
+        _check(lib().batch_set_start(self._h, int(i), *[_ptr(a) for a in args]), "batch_set_start")
+
+    def set_tiles(self, threads: int, lanes):
+        arr = (ctypes.c_int32 * 8)(*[int(v) for v in lanes])
+        _check(lib().batch_set_tiles(self._h, int(threads), arr), "batch_set_tiles")
+
+    def get_tiles(self):
+        t = ctypes.c_int32()
+        arr = (ctypes.c_int32 * 8)()
+        _check(lib().batch_get_tiles(self._h, ctypes.byref(t), arr), "batch_get_tiles")
+        return t.value, list(arr)
+
+    def time(self, bucket: int, iters: int) -> float:
+        ms = ctypes.c_double()
+        _check(lib().batch_time(self._h, int(bucket), int(iters), ctypes.byref(ms)), "batch_time")
+        return ms.value
+
+    def info(self) -> dict:
+        arr = (ctypes.c_int64 * 6)()
+        _check(lib().batch_info(self._h, arr), "batch_info")
+        return dict(zip(("count", "rows", "cols", "nnz", "workgroups", "lds_bytes"), list(arr)))
+
+    def bucket_counts(self):
+        out = [0, 0, 0, 0]
+        for m in self.ms:
+            out[sum(m >= lo for lo in self.BUCKETS) - 1] += 1
+        return out

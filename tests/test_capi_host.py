@@ -126,3 +126,23 @@ def test_null_arguments():
     assert L.solver_residuals(None, None) == S.UV_EINVAL
     assert L.solver_solution(None, None, None, None, None) == S.UV_EINVAL
     L.solver_destroy(None)
+
+
+def _batch_err(insts, **kw):
+    with pytest.raises(S.UvError) as ei:
+        S.Batch(insts, **kw)
+    return ei.value.code
+
+
+def test_batch_rejects_bad_input():
+    good = dict(m=2, n=3, row_ptr=[0, 2, 3], col_idx=[0, 2, 1], val=[1.0, 2.0, 3.0],
+                b=[1.0, 1.0], c=[1.0, 1.0, 1.0])
+    bad = dict(good, col_idx=[2, 0, 1])
+    assert _batch_err([good, bad]) == S.UV_EBADCSR
+    assert _batch_err([good], mu=0.0) == S.UV_EINVAL
+    assert _batch_err([good], check_every=0) == S.UV_EINVAL
+    # x and u of an instance must fit in one workgroup's LDS (160 KiB)
+    n = 41_000
+    wide = dict(m=1, n=n, row_ptr=[0, 1], col_idx=[0], val=[1.0], b=[1.0], c=np.ones(n))
+    assert _batch_err([good, wide], precision="mixed") == S.UV_ETOOBIG
+    assert _batch_err([dict(wide, n=20_000, c=np.ones(20_000))], precision="fp64") == S.UV_ETOOBIG

@@ -1,0 +1,146 @@
+"""GPU tests of the batched persistent solver against the CPU oracle.
+
+FP64 batch: every instance's iterate after 200 iterations matches the oracle
+run of that instance alone (the 1e-9 bar).  Mixed batch: every instance
+reaches the 1e-4 KKT residual and the known optimum.  Masks, restarts, the
+tile search and the full 4096-instance workload are covered too.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2203_05027_amd import autotune
+from paper_2203_05027_amd import instances as I
+from paper_2203_05027_amd.solver import Batch
+
+pytestmark = pytest.mark.gpu
+KEYS = ("x", "z", "delta", "lambda")
+
+
+def say(msg):
+    sys.__stderr__.write(f"[gpu-test] {msg}\n")
+    sys.__stderr__.flush()
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)) if b.size else 0.0
+
+
+def oracle_run(inst, iters, mu=1.0):
+    o = oracle.Oracle.from_instance(inst, mu=mu)
+    o.iterate(iters)
+    return o.state()
+
+
+def small_mix(seed=0):
+    sizes = [(1, 2, 1), (7, 13, 2), (50, 100, 6), (64, 128, 6), (129, 300, 4), (333, 666, 6),
+             (600, 1200, 6), (2100, 4200, 6), (40, 55, 5), (5, 9, 3)]
+    return [I.lp_instance(m, n, k, seed=seed * 100 + i) for i, (m, n, k) in enumerate(sizes)]
+
+
+@pytest.mark.parametrize("threads,lanes", [(256, [2, 1] * 4), (64, [1, 1] * 4),
+                                           (1024, [4, 2, 8, 4, 1, 2, 16, 8]), (512, [64, 32] * 4)])
+def test_fp64_batch_matches_oracle(threads, lanes):
+    insts = small_mix()
+    say(f"fp64 batch threads={threads} lanes={lanes}")
+    with Batch(insts, precision="fp64", eps=0.0) as b:
+        b.set_tiles(threads, lanes)
+        b.iterate(120)
+        b.iterate(80)
+        for i, inst in enumerate(insts):
+            o = oracle_run(inst, 200)
+            g = b.solution(i)
+            errs = {k: rel(g[k], o[k]) for k in KEYS}
+            assert max(errs.values()) <= 1e-9, (i, errs)
+            assert b.residuals(i)["iter"] == 200
+
+
+def test_fp64_batch_converges_like_oracle():
+    insts = [I.lp_instance(40, 80, 5, seed=s) for s in range(30, 34)]
+    with Batch(insts, precision="fp64", eps=1e-4, check_every=10) as b:
+        left = b.iterate(200_000)
+        assert left == 0
+        for i, inst in enumerate(insts):
+            ro = oracle.Oracle.from_instance(inst).solve(1e-4, check_every=10, max_iter=200_000)
+            r = b.residuals(i)
+            say(f"instance {i}: batch {r['iter']} oracle {ro['iter']}")
+            assert r["status"] == "converged" and r["iter"] == ro["iter"]
+            assert abs(r["pobj"] - ro["pobj"]) <= 1e-9 * abs(ro["pobj"])
+
+
+def test_mixed_batch_reaches_optimum():
+    insts = [I.batch_lp_instance(i, m_hi=400) for i in range(48)]
+    with Batch(insts, precision="mixed", eps=1e-4) as b:
+        left = b.iterate(400_000)
+        say(f"mixed batch: {left} still running")
+        assert left == 0
+        for i, inst in enumerate(insts):
+            r = b.residuals(i)
+            assert r["status"] == "converged" and r["kkt"] <= 1e-4, (i, r)
+            assert abs(r["pobj"] - inst["p_star"]) <= 2e-3 * (1 + abs(inst["p_star"])), (i, r)
+
+
+def test_masks_and_restart():
+    insts = [I.lp_instance(30, 60, 4, seed=s) for s in range(40, 44)]
+    with Batch(insts, precision="fp64", eps=1e-4) as b:
+        assert b.iterate(500_000) == 0
+        before = [b.solution(i) for i in range(4)]
+        iters = [b.residuals(i)["iter"] for i in range(4)]
+        assert b.iterate(1000) == 0                    # stopped instances are skipped
+        for i in range(4):
+            assert b.residuals(i)["iter"] == iters[i]
+            for k in KEYS:
+                assert np.array_equal(b.solution(i)[k], before[i][k])
+        b.set_start(2)                                  # zero start again
+        assert b.iterate(50) == 1
+        o = oracle_run(insts[2], 50)
+        assert max(rel(b.solution(2)[k], o[k]) for k in KEYS) <= 1e-9
+
+
+def test_timing_restores_state():
+    insts = small_mix(seed=1)
+    with Batch(insts, precision="mixed", eps=0.0) as b:
+        b.iterate(30)
+        before = [b.solution(i) for i in range(len(insts))]
+        for bk in (-1, 0, 1, 2, 3):
+            assert b.time(bk, 5) >= 0.0
+        for i in range(len(insts)):
+            assert b.residuals(i)["iter"] == 30
+            for k in KEYS:
+                assert np.array_equal(b.solution(i)[k], before[i][k])
+
+
+def test_autotune_cache(tmp_path):
+    insts = small_mix(seed=2)
+    cache = str(tmp_path / "tiles.json")
+    with Batch(insts, precision="fp64", eps=0.0) as b:
+        rec = autotune.tune(b, iters=5, cache_path=cache, threads=(256, 512))
+        assert not rec["cached"] and os.path.exists(cache)
+        assert b.get_tiles() == (rec["threads"], rec["lanes"])
+        b.iterate(200)
+        for i, inst in enumerate(insts):
+            o = oracle_run(inst, 200)
+            assert max(rel(b.solution(i)[k], o[k]) for k in KEYS) <= 1e-9
+    with Batch(insts, precision="fp64", eps=0.0) as b2:
+        rec2 = autotune.tune(b2, iters=5, cache_path=cache)
+        assert rec2["cached"] and b2.get_tiles() == (rec["threads"], rec["lanes"])
+
+
+def test_full_batched_workload_sampled():
+    """All 4096 instances of the batched workload in one launch (FP64), 50
+    iterations; sampled instances checked one by one against the oracle."""
+    insts = [I.batch_lp_instance(i) for i in range(4096)]
+    say(f"4096 instances, total nnz {sum(i['nnz'] for i in insts)}")
+    with Batch(insts, precision="fp64", eps=0.0) as b:
+        say(f"info {b.info()}")
+        b.iterate(50)
+        rng = np.random.default_rng(0)
+        big = int(np.argmax([i["m"] for i in insts]))
+        for i in sorted(set(rng.integers(0, 4096, 6).tolist() + [big])):
+            o = oracle_run(insts[i], 50)
+            errs = {k: rel(b.solution(i)[k], o[k]) for k in KEYS}
+            say(f"instance {i} m={insts[i]['m']}: {errs}")
+            assert max(errs.values()) <= 1e-9
