@@ -145,4 +145,4 @@ def test_batch_rejects_bad_input():
     n = 41_000
     wide = dict(m=1, n=n, row_ptr=[0, 1], col_idx=[0], val=[1.0], b=[1.0], c=np.ones(n))
     assert _batch_err([good, wide], precision="mixed") == S.UV_ETOOBIG
-    assert _batch_err([dict(wide, n=20_000, c=np.ones(20_000))], precision="fp64") == S.UV_ETOOBIG
+    assert _batch_err([dict(wide, n=20_500, c=np.ones(20_500))], precision="fp64") == S.UV_ETOOBIG
