@@ -241,6 +241,55 @@ int batch_info(const uv_batch *h, int64_t *info);
 
 void batch_destroy(uv_batch *h);
 
+/* ------------------------------------------------------------------------
+ * Parametric family: one A and c (orthant cone), B right-hand sides
+ * b_1..b_B iterated together.  Per-instance vectors live instance-fastest on
+ * the device (entry j of instance l at j * B + l), so every nonzero of A is
+ * read once per 64 instances and its gather is one contiguous line.  Each
+ * instance is checked every check_every iterations and frozen once it stops.
+ * Host arrays below are instance-major: instance l's vector starts at
+ * l * length.
+ * ------------------------------------------------------------------------ */
+typedef struct uv_family uv_family;
+
+/* B: instances per launch, a multiple of 64 in [64, 1024].  opts as for
+ * solver_create (lanes/unroll unused).  A and c are copied. */
+int family_create(const uv_csr *A, const double *c, int32_t B,
+                  const uv_opts *opts, uv_family **out);
+
+/* Right-hand sides of the first nb <= B instances (nb x m doubles) and the
+ * zero start for all of them; instances nb..B-1 stay idle. */
+int family_set_rhs(uv_family *h, int32_t nb, const double *b);
+
+/* Start of the current nb instances (nb x n for x, z, delta; nb x m for
+ * lambda; NULL = zero), with y = V'x and gamma = -U'lambda as in
+ * solver_set_start; resets iteration counts and statuses. */
+int family_set_start(uv_family *h, const double *x, const double *z,
+                     const double *delta, const double *lambda);
+
+/* Start from predicted primal-dual points held on the DEVICE: row l of
+ * xl_dev (FP32, row stride ld >= n + m) is [x (n) ; lambda (m)].  Sets
+ * z = max(x, 0) and delta = max(c + A'lambda, 0) (the stationarity
+ * condition c + A'lambda - delta = 0 projected on the dual cone). */
+int family_set_start_predicted(uv_family *h, const float *xl_dev, int64_t ld);
+
+/* Up to k more iterations; *n_active = instances still running. */
+int family_iterate(uv_family *h, int64_t k, int32_t *n_active);
+
+/* Residuals of the nb current instances into r[0..nb-1]. */
+int family_residuals(uv_family *h, uv_residuals *r);
+
+/* Iterates of the nb instances into host buffers (instance-major; any may
+ * be NULL): x, z, delta (nb x n), lambda (nb x m). */
+int family_solution(uv_family *h, double *x, double *z, double *lambda,
+                    double *delta);
+
+/* FP32 rows [z (n) ; lambda (m)] of the nb instances into a DEVICE matrix
+ * with row stride ld >= n + m (training data for a learned start). */
+int family_solution_device(uv_family *h, float *dst_dev, int64_t ld);
+
+void family_destroy(uv_family *h);
+
 #ifdef __cplusplus
 }
 #endif

@@ -360,3 +360,125 @@ class Batch:
         for m in self.ms:
             out[sum(m >= lo for lo in self.BUCKETS) - 1] += 1
         return out
+
+
+def _bind_family(L):
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.family_create.argtypes = [ctypes.POINTER(UvCsr), P, i32, ctypes.POINTER(UvOpts), ctypes.POINTER(P)]
+    L.family_create.restype = ctypes.c_int
+    L.family_set_rhs.argtypes = [P, i32, P]
+    L.family_set_rhs.restype = ctypes.c_int
+    L.family_set_start.argtypes = [P, P, P, P, P]
+    L.family_set_start.restype = ctypes.c_int
+    L.family_set_start_predicted.argtypes = [P, P, i64]
+    L.family_set_start_predicted.restype = ctypes.c_int
+    L.family_iterate.argtypes = [P, i64, ctypes.POINTER(i32)]
+    L.family_iterate.restype = ctypes.c_int
+    L.family_residuals.argtypes = [P, P]
+    L.family_residuals.restype = ctypes.c_int
+    L.family_solution.argtypes = [P, P, P, P, P]
+    L.family_solution.restype = ctypes.c_int
+    L.family_solution_device.argtypes = [P, P, i64]
+    L.family_solution_device.restype = ctypes.c_int
+    L.family_destroy.argtypes = [P]
+    L.family_destroy.restype = None
+
+
+class Family:
+    """One A and c (orthant cone) with up to B right-hand sides iterated
+    together (B a multiple of 64)."""
+
+    def __init__(self, m, n, row_ptr, col_idx, val, c, B=64, *, mu=1.0, precision="mixed",
+                 check_every=10, eps=1e-4, max_iter=0, use_graph=True, stream=None):
+        L = lib()
+        if not hasattr(L, "_family_bound"):
+            _bind_family(L)
+            L._family_bound = True
+        self.m, self.n, self.B = int(m), int(n), int(B)
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        va = np.ascontiguousarray(val, dtype=np.float64)
+        cc = _f64(c, self.n)
+        csr = UvCsr(self.m, self.n, int(rp[-1]), _ptr(rp), _ptr(ci), _ptr(va))
+        o = default_opts()
+        o.mu = float(mu)
+        o.precision = {"fp64": UV_FP64, "mixed": UV_MIXED}[precision]
+        o.check_every = int(check_every)
+        o.eps_kkt = float(eps)
+        o.max_iter = int(max_iter)
+        o.hip_stream = stream
+        o.use_graph = 1 if use_graph else 0
+        self.precision = precision
+        self.nb = 0
+        h = ctypes.c_void_p()
+        _check(L.family_create(ctypes.byref(csr), _ptr(cc), self.B, ctypes.byref(o), ctypes.byref(h)),
+               "family_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().family_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _mat(self, a, cols):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        if a.shape != (self.nb, cols):
+            raise ValueError(f"expected shape {(self.nb, cols)}, got {a.shape}")
+        return a
+
+    def set_rhs(self, b):
+        b = np.ascontiguousarray(np.atleast_2d(b), dtype=np.float64)
+        if b.shape[1] != self.m or not 1 <= b.shape[0] <= self.B:
+            raise ValueError(f"right-hand sides must be (nb <= {self.B}, {self.m})")
+        self.nb = b.shape[0]
+        _check(lib().family_set_rhs(self._h, self.nb, _ptr(b)), "family_set_rhs")
+
+    def set_start(self, x=None, z=None, delta=None, lam=None):
+        args = (self._mat(x, self.n), self._mat(z, self.n), self._mat(delta, self.n),
+                self._mat(lam, self.m))
+        _check(lib().family_set_start(self._h, *[_ptr(a) for a in args]), "family_set_start")
+
+    def set_start_predicted(self, dev_ptr: int, ld: int):
+        """Start from a device FP32 matrix whose row l is [x ; lambda]."""
+        _check(lib().family_set_start_predicted(self._h, ctypes.c_void_p(dev_ptr), int(ld)),
+               "family_set_start_predicted")
+
+    def iterate(self, k: int) -> int:
+        a = ctypes.c_int32(0)
+        _check(lib().family_iterate(self._h, int(k), ctypes.byref(a)), "family_iterate")
+        return a.value
+
+    def residuals(self):
+        arr = (UvResiduals * max(self.nb, 1))()
+        _check(lib().family_residuals(self._h, arr), "family_residuals")
+        out = []
+        for r in arr[: self.nb]:
+            d = {k: getattr(r, k) for k, _ in UvResiduals._fields_}
+            d["status"] = STATUS.get(d["status"], d["status"])
+            out.append(d)
+        return out
+
+    def solution(self) -> dict:
+        nb, n, m = self.nb, self.n, self.m
+        x, z, d, lam = np.empty((nb, n)), np.empty((nb, n)), np.empty((nb, n)), np.empty((nb, m))
+        _check(lib().family_solution(self._h, _ptr(x), _ptr(z), _ptr(lam), _ptr(d)), "family_solution")
+        return {"x": x, "z": z, "delta": d, "lambda": lam}
+
+    def solution_device(self, dev_ptr: int, ld: int):
+        """Writes FP32 rows [z ; lambda] of the current instances to device memory."""
+        _check(lib().family_solution_device(self._h, ctypes.c_void_p(dev_ptr), int(ld)),
+               "family_solution_device")
