@@ -290,6 +290,67 @@ int family_solution_device(uv_family *h, float *dst_dev, int64_t ld);
 
 void family_destroy(uv_family *h);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start: dense kernels.  Pointers marked _dev are DEVICE
+ * pointers (for instance from framework tensors); the stream argument may be
+ * NULL (the default stream).  All of these wait for their work to finish.
+ * ------------------------------------------------------------------------ */
+
+/* C = alpha * A B + beta * C in FP32: A(i,k) = A[i*a_rs + k*a_cs],
+ * B(k,j) = B[k*b_rs + j*b_cs], C row-major with leading dimension ldc; all
+ * device pointers. */
+int gemm_f32(int32_t M, int32_t N, int32_t K, const float *A_dev, int64_t a_rs,
+             int64_t a_cs, const float *B_dev, int64_t b_rs, int64_t b_cs,
+             float *C_dev, int64_t ldc, float alpha, float beta, void *stream);
+
+/* Y (N x D, leading dimension ld, device) += v (D, device) on every row. */
+int add_row_vector(int64_t N, int64_t D, float *Y_dev, int64_t ld,
+                   const float *v_dev, void *stream);
+
+/* Principal components of the rows of Y (N x D, leading dimension ld,
+ * device; CENTERED IN PLACE): mean_dev (D), basis_dev (k x D, orthonormal
+ * rows, the top-k right singular vectors of the centered Y) and sv (k
+ * singular values, host), by a randomized range finder with power_iters
+ * power iterations and k + oversample (<= 1024) probe vectors. */
+int pca_fit(float *Y_dev, int64_t N, int64_t D, int64_t ld, int32_t k,
+            int32_t oversample, int32_t power_iters, uint64_t seed,
+            float *mean_dev, float *basis_dev, float *sv, void *stream);
+
+/* Symmetric eigen-decomposition (host): S (l x l row-major, destroyed) ->
+ * eigenvalues w (descending) and eigenvectors in the columns of V. */
+int uvla_sym_eig(int32_t l, double *S, double *w, double *V);
+
+/* Multilayer perceptron dims[0] -> dims[1] -> ... -> dims[nlayers], ReLU
+ * between layers, linear output; every width a multiple of 16.  GEMMs on
+ * the BF16 matrix cores with FP32 accumulation; FP32 master weights
+ * (He-uniform initialisation from seed) and Adam state. */
+typedef struct uv_mlp uv_mlp;
+int mlp_create(int32_t nlayers, const int32_t *dims, int32_t max_batch,
+               uint64_t seed, void *stream, uv_mlp **out);
+/* All weights (layer by layer, each dims[l] x dims[l+1] row-major) and
+ * biases as flat host arrays. */
+int mlp_get_params(uv_mlp *h, float *w, float *b);
+int mlp_set_params(uv_mlp *h, const float *w, const float *b);
+/* y_dev (batch x dims[nlayers]) = net(x_dev (batch x dims[0])); batch a
+ * multiple of 16, <= max_batch; device pointers. */
+int mlp_forward(uv_mlp *h, int32_t batch, const float *x_dev, float *y_dev);
+/* Gradients of the mean squared error mean((net(x) - t)^2) into host
+ * arrays laid out as in mlp_get_params, and the loss; no update. */
+int mlp_gradients(uv_mlp *h, int32_t batch, const float *x_dev,
+                  const float *t_dev, float *gw, float *gb, float *loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on that loss; *loss (may
+ * be NULL) receives the loss before the step. */
+int mlp_train_step(uv_mlp *h, int32_t batch, const float *x_dev,
+                   const float *t_dev, float lr, float *loss);
+void mlp_destroy(uv_mlp *h);
+
+/* C (FP32) = A B on BF16 operands (raw bit patterns), strides as gemm_f32;
+ * M, N, K multiples of 16 -- the MLP's matrix-core kernel on its own. */
+int mlp_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t *A_dev,
+                  int64_t a_rs, int64_t a_cs, const uint16_t *B_dev,
+                  int64_t b_rs, int64_t b_cs, float *C_dev, int64_t ldc,
+                  void *stream);
+
 #ifdef __cplusplus
 }
 #endif
