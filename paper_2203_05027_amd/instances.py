@@ -215,6 +215,15 @@ class ParametricFamily:
     def b(self, theta: np.ndarray) -> np.ndarray:
         return _matvec(self.m, self._r, self.col_idx, self.val, self.x_feasible(theta))
 
+    def b_many(self, thetas: np.ndarray) -> np.ndarray:
+        """Right-hand sides of many members at once: rows of thetas -> rows
+        of b (the same values as b() member by member)."""
+        import scipy.sparse as sp
+        thetas = np.atleast_2d(np.asarray(thetas, dtype=np.float64))
+        X = np.maximum(self.W @ thetas.T + self.w[:, None], 0.0)
+        A = sp.csr_matrix((self.val, self.col_idx, self.row_ptr), shape=(self.m, self.n))
+        return np.ascontiguousarray((A @ X).T)
+
     def instance(self, theta: np.ndarray) -> dict:
         return {
             "m": self.m, "n": self.n, "nnz": int(self.row_ptr[-1]),
