@@ -51,6 +51,10 @@
 #include <omp.h>
 #endif
 
+/* Loops over fewer than this many rows, columns or nonzeros run on one
+ * thread (a parallel region costs more than the loop itself below it). */
+#define ORC_PAR_MIN 50000
+
 typedef struct {
     int32_t m, n;
     int64_t o;            /* number of stored nonzeros */
@@ -187,13 +191,13 @@ orc_t *orc_create(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr,
      * of squares of row i's nonzeros (each column of U has a single nonzero
      * a_k in row i_k); V V' is diagonal with entry j equal to the number of
      * nonzeros in column j (each column of V is a single 1 in row j_k). */
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (m >= ORC_PAR_MIN)
     for (int32_t i = 0; i < m; ++i) {
         double d = 0.0;
         for (int64_t k = h->row_ptr[i]; k < h->row_ptr[i + 1]; ++k) d += h->ak[k] * h->ak[k];
         h->FU[i] = 1.0 / (1.0 + d);
     }
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
     for (int32_t j = 0; j < n; ++j) {
         double d = 0.0;
         for (int64_t p = h->col_ptr[j]; p < h->col_ptr[j + 1]; ++p) d += 1.0;
@@ -234,9 +238,9 @@ static void proj_lorentz(const double *w, double *out, int32_t nq)
 static void proj_K(int32_t n_orth, int32_t n_soc, const int32_t *soc_size,
                    const int64_t *soc_off, const double *w, double *out)
 {
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (n_orth >= ORC_PAR_MIN)
     for (int32_t j = 0; j < n_orth; ++j) proj_lorentz(w + j, out + j, 1);
-    #pragma omp parallel for schedule(dynamic, 64)
+    #pragma omp parallel for schedule(dynamic, 64) if (n_soc >= ORC_PAR_MIN / 16)
     for (int32_t q = 0; q < n_soc; ++q)
         proj_lorentz(w + soc_off[q], out + soc_off[q], soc_size[q]);
 }
@@ -275,7 +279,7 @@ void orc_set_start(orc_t *h, const double *x, const double *z, const double *del
                    const double *lambda)
 {
     orc_set_state(h, x, z, delta, NULL, NULL, lambda);
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (h->o >= ORC_PAR_MIN)
     for (int64_t k = 0; k < h->o; ++k) {
         h->y[k] = h->x[h->ck[k]];                    /* (V'x)_k = x_{j_k} */
         h->gamma[k] = -h->ak[k] * h->lambda[h->rk[k]]; /* (U'lambda)_k = a_k lambda_{i_k} */
@@ -306,7 +310,7 @@ void orc_resume(orc_t *h, const double *x, const double *z, const double *delta,
                 const double *lambda)
 {
     orc_set_state(h, x, z, delta, NULL, NULL, lambda);
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (h->o >= ORC_PAR_MIN)
     for (int64_t k = 0; k < h->o; ++k) h->gamma[k] = -h->ak[k] * h->lambda[h->rk[k]];
     y_step(h);
 }
@@ -319,18 +323,18 @@ static void y_step(orc_t *h)
     const int32_t m = h->m;
     const int64_t o = h->o;
     const double mu = h->mu;
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (o >= ORC_PAR_MIN)
     for (int64_t k = 0; k < o; ++k) {
         int32_t i = h->rk[k];
         h->t[k] = h->ak[k] * (h->b[i] - h->lambda[i] / mu) + h->x[h->ck[k]] - h->gamma[k] / mu;
     }
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (m >= ORC_PAR_MIN)
     for (int32_t i = 0; i < m; ++i) {
         double ut = 0.0;
         for (int64_t k = h->row_ptr[i]; k < h->row_ptr[i + 1]; ++k) ut += h->ak[k] * h->t[k];
         h->s[i] = h->FU[i] * ut;
     }
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (o >= ORC_PAR_MIN)
     for (int64_t k = 0; k < o; ++k) h->y[k] = h->t[k] - h->ak[k] * h->s[h->rk[k]];
 }
 
@@ -343,7 +347,7 @@ static void iterate_once(orc_t *h)
 
     /* Step 5 (Block 1, eq. vvt): x = F_V (V(y + gamma/mu) + z + delta/mu - c/mu),
      * (V w)_j = sum over the nonzeros k of column j of w_k. */
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
     for (int32_t j = 0; j < n; ++j) {
         double vy = 0.0;
         for (int64_t p = h->col_ptr[j]; p < h->col_ptr[j + 1]; ++p) {
@@ -356,22 +360,22 @@ static void iterate_once(orc_t *h)
     y_step(h);
 
     /* Step 7 (Block 2, z-step): z = proj_K(x - delta/mu). */
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
     for (int32_t j = 0; j < n; ++j) h->wrk_n[j] = h->x[j] - h->delta[j] / mu;
     proj_K(h->n_orth, h->n_soc, h->soc_size, h->soc_off, h->wrk_n, h->z);
 
     /* Step 8: lambda = lambda + mu (U y - b). */
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (m >= ORC_PAR_MIN)
     for (int32_t i = 0; i < m; ++i) {
         double uy = 0.0;
         for (int64_t k = h->row_ptr[i]; k < h->row_ptr[i + 1]; ++k) uy += h->ak[k] * h->y[k];
         h->lambda[i] += mu * (uy - h->b[i]);
     }
     /* Step 9: gamma = gamma + mu (y - V'x). */
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (o >= ORC_PAR_MIN)
     for (int64_t k = 0; k < o; ++k) h->gamma[k] += mu * (h->y[k] - h->x[h->ck[k]]);
     /* Step 10: delta = delta + mu (z - x). */
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
     for (int32_t j = 0; j < n; ++j) h->delta[j] += mu * (h->z[j] - h->x[j]);
 
     h->iter++;
@@ -411,14 +415,14 @@ void orc_residuals(orc_t *h, double *out)
     const int32_t m = h->m, n = h->n;
     double *rm = h->wrk_m, *rn = h->wrk_n;
 
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (m >= ORC_PAR_MIN)
     for (int32_t i = 0; i < m; ++i) {
         double az = 0.0;
         for (int64_t k = h->row_ptr[i]; k < h->row_ptr[i + 1]; ++k) az += h->ak[k] * h->z[h->ck[k]];
         rm[i] = (az - h->b[i]) * (az - h->b[i]);
     }
     double rp2 = serial_sum(rm, m);
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
     for (int32_t j = 0; j < n; ++j) {
         double atl = 0.0;
         for (int64_t p = h->col_ptr[j]; p < h->col_ptr[j + 1]; ++p) {
@@ -433,7 +437,7 @@ void orc_residuals(orc_t *h, double *out)
     for (int32_t i = 0; i < m; ++i) { bb += h->b[i] * h->b[i]; bl += h->b[i] * h->lambda[i]; }
     for (int32_t j = 0; j < n; ++j) { cc += h->c[j] * h->c[j]; cz += h->c[j] * h->z[j]; }
 
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (m >= ORC_PAR_MIN)
     for (int32_t i = 0; i < m; ++i) {
         double ax = 0.0;
         for (int64_t k = h->row_ptr[i]; k < h->row_ptr[i + 1]; ++k) ax += h->ak[k] * h->x[h->ck[k]];

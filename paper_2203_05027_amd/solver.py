@@ -64,6 +64,13 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it first "
                            "(python -c 'import __graft_entry__ as g; g.build()')")
+    # PyTorch ships its own HIP runtime under the same soname; loading torch
+    # first makes this library bind to that one, so a process that also uses
+    # torch for device memory holds a single HIP runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     L.uv_default_opts.argtypes = [ctypes.POINTER(UvOpts)]

@@ -72,13 +72,12 @@ def test_warm_start_at_solution_is_converged(small_family):
     """Starting from a solution (x*, lambda*) the predicted-start mapping
     (z = max(x, 0), delta = max(c + A'lambda, 0)) is converged at once."""
     import torch
-    if not torch.cuda.is_available():
-        pytest.skip("needs torch device memory")
+    assert torch.cuda.is_available()
     fam = small_family
     insts = family_members(fam, [fam.theta(3000 + i, p=8) for i in range(4)])
     b = np.stack([i["b"] for i in insts])
     with Family(fam.m, fam.n, fam.row_ptr, fam.col_idx, fam.val, fam.c, B=64, precision="mixed",
-                eps=1e-6) as F:
+                eps=1e-5) as F:
         F.set_rhs(b)
         assert F.iterate(400_000) == 0
         cold = [r["iter"] for r in F.residuals()]
@@ -110,6 +109,6 @@ def test_mixed_family_reaches_optimum(small_family):
         assert F.iterate(400_000) == 0
         res = F.residuals()
     for l in range(0, 64, 9):
-        ro = oracle.Oracle.from_instance(insts[l]).solve(1e-6, check_every=50, max_iter=400_000)
+        ro = oracle.Oracle.from_instance(insts[l]).solve(1e-5, check_every=50, max_iter=400_000)
         assert res[l]["kkt"] <= 1e-4
         assert abs(res[l]["pobj"] - ro["pobj"]) <= 2e-3 * (1 + abs(ro["pobj"]))
