@@ -88,8 +88,11 @@ def test_mlp_forward_and_gradients(torch_cuda):
         e_bf = np.linalg.norm(gwl[l] - gws[l]) / np.linalg.norm(gws[l])
         e_64 = np.linalg.norm(gwl[l] - gws64[l]) / np.linalg.norm(gws64[l])
         say(f"layer {l}: dW rel err vs bf16 oracle {e_bf:.2e}, vs fp64 oracle {e_64:.2e}")
+        # sharp: same BF16 rounding points, only the FP32 summation order differs
         assert e_bf <= 2e-3, (l, e_bf)
-        assert e_64 <= 3e-2, (l, e_64)
+        # loose: the effect of BF16 operands (2^-9 relative per element, through
+        # three layers of products) on the exact FP64 gradient
+        assert e_64 <= 1e-1, (l, e_64)
         np.testing.assert_allclose(gbl[l], gbs[l], rtol=2e-3, atol=2e-3 * np.abs(gbs[l]).max())
 
 
