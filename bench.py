@@ -107,6 +107,122 @@ def cpu_baseline(inst, mu, seconds):
                       f"workload (timed {dt:.1f} s after one untimed iteration)"}
 
 
+def batched_block(steps_sweep=100, ttk_cap=60_000, plain_sample=8, count=4096, log_fn=log):
+    """The batched workload: all instances in one persistent launch (mixed
+    precision), sweep throughput, time to 1e-4 for the batch, and the plain
+    single-problem solver on a sample of the same instances."""
+    from paper_2203_05027_amd import autotune
+    from paper_2203_05027_amd import instances as I
+    from paper_2203_05027_amd.solver import Batch, Solver
+
+    t0 = time.time()
+    insts = [I.batch_lp_instance(i) for i in range(count)]
+    M = sum(i["m"] for i in insts)
+    N = sum(i["n"] for i in insts)
+    NNZ = sum(i["nnz"] for i in insts)
+    log_fn(f"batched: {count} LPs, rows {M}, cols {N}, nnz {NNZ}, generated in {time.time() - t0:.1f} s")
+    out = {"instances": count, "rows": M, "cols": N, "nnz": NNZ}
+    with Batch(insts, precision="mixed", eps=1e-4, max_iter=ttk_cap) as b:
+        rec = autotune.tune(b, iters=20, log=log_fn)
+        out["tiles"] = {"threads": rec["threads"], "lanes": rec["lanes"], "cached": rec["cached"]}
+        ms = b.time(-1, steps_sweep)
+        rb, cb = alg_bytes(M, N, NNZ, "mixed")
+        out["sweep_ms"] = ms / steps_sweep
+        out["instance_iters_per_s"] = count * steps_sweep / (ms * 1e-3)
+        out["sweep_GBs"] = (rb + cb) * steps_sweep / (ms * 1e-3) / 1e9
+        t0 = time.perf_counter()
+        left = count
+        while left:
+            left = b.iterate(2000)
+            if all(b.residuals(i)["status"] != "running" for i in range(count)):
+                break
+        dt = time.perf_counter() - t0
+        res = [b.residuals(i) for i in range(count)]
+    its = np.array([r["iter"] for r in res])
+    conv = np.array([r["status"] == "converged" for r in res])
+    out.update(time_to_1e4_s=dt, converged=int(conv.sum()), cap=ttk_cap,
+               iters_median=float(np.median(its[conv])), iters_max_converged=int(its[conv].max()))
+    # plain solver, one instance at a time (graph replay), on a sample
+    rng = np.random.default_rng(1)
+    sample = rng.choice(count, plain_sample, replace=False)
+    tp, ip = 0.0, 0
+    for i in sample:
+        with Solver.from_instance(insts[i], precision="mixed", eps=1e-4, max_iter=ttk_cap) as s:
+            t0 = time.perf_counter()
+            while not s.iterate(5000):
+                pass
+            tp += time.perf_counter() - t0
+            ip += s.residuals()["iter"]
+    batch_sample_iters = int(its[sample].sum())
+    out["plain_sample"] = {"instances": plain_sample, "seconds": tp, "iters": ip,
+                           "us_per_iter": tp / ip * 1e6,
+                           "est_all_instances_s": tp / ip * 1e6 * its.sum() * 1e-6,
+                           "batched_iters_same_sample": batch_sample_iters}
+    return out
+
+
+def bench_parametric(args):
+    import torch
+    from paper_2203_05027_amd import instances as I
+    from paper_2203_05027_amd.solver import Solver
+    from paper_2203_05027_amd.warmstart import WarmStart
+
+    t0 = time.time()
+    fam = I.ParametricFamily(m=50_000, n=100_000, k=8, p=64, seed=4)
+    train = np.stack([fam.theta(1_000_000 + i) for i in range(args.train)])
+    held = np.stack([fam.theta(2_000_000 + i) for i in range(args.eval)])
+    log(f"parametric family built in {time.time() - t0:.1f} s")
+    ws = WarmStart(fam, k=256, hidden=(512, 512), B=256, log=log)
+    t0 = time.time()
+    Y, st = ws.solve_members(train, eps=args.train_eps, max_iter=args.train_cap)
+    t_data = time.time() - t0
+    Ytrue = Y[: min(512, len(train))].clone()
+    t0 = time.time()
+    coef = ws.fit_basis(Y)
+    t_pca = time.time() - t0
+    del Y
+    torch.cuda.empty_cache()
+    t0 = time.time()
+    hist = ws.train(train, coef, epochs=args.epochs, batch=256, lr=1e-3)
+    t_train = time.time() - t0
+    fit_err = ws.model_error(ws.predict(train[: len(Ytrue)]), Ytrue)
+    cmp = ws.compare(held, eps=1e-4, max_iter=args.ttk_cap)
+    # plain single-problem solver, cold, on a few held-out members
+    tp, ip = 0.0, 0
+    for th in held[: args.plain]:
+        with Solver.from_instance(fam.instance(th), precision="mixed", eps=1e-4, max_iter=args.ttk_cap) as s:
+            t1 = time.perf_counter()
+            while not s.iterate(5000):
+                pass
+            tp += time.perf_counter() - t1
+            ip += s.residuals()["iter"]
+    ne = len(held)
+    line = {
+        "metric": "time to 1e-4 KKT per member, learned warm start vs cold start (parametric LP family)",
+        "value": cmp["cold_seconds"] / cmp["warm_seconds"],
+        "unit": "x (cold time / warm time, batched family solver)",
+        "n_gpus": 1, "higher_is_better": True, "dtype": "f32 sweep / f64 duals / bf16 mlp",
+        "data": "synthetic",
+        "config": {"workload": f"lp_parametric: m={fam.m} n={fam.n} nnz={fam.row_ptr[-1]}, theta in R^64, "
+                               f"{len(train)} training members (eps {args.train_eps}), {ne} held-out, "
+                               "MLP 64-512-512-256, PCA k=256"},
+        "train_data_s": t_data, "train_converged": float(st["converged"].mean()),
+        "train_iters_median": float(np.median(st["iters"])), "pca_s": t_pca, "train_s": t_train,
+        "train_mse_first_last": [hist[0], hist[-1]], "fit_rel_err_median": fit_err,
+        "cold": {"seconds": cmp["cold_seconds"], "per_member_s": cmp["cold_seconds"] / ne,
+                 "iters_median": float(np.median(cmp["cold_iters"])),
+                 "iters_mean": float(np.mean(cmp["cold_iters"])),
+                 "converged": int(cmp["cold_converged"].sum())},
+        "warm": {"seconds": cmp["warm_seconds"], "per_member_s": cmp["warm_seconds"] / ne,
+                 "iters_median": float(np.median(cmp["warm_iters"])),
+                 "iters_mean": float(np.mean(cmp["warm_iters"])),
+                 "converged": int(cmp["warm_converged"].sum()), "predict_s": cmp["predict_seconds"]},
+        "plain_gpu_cold": {"members": args.plain, "seconds": tp, "per_member_s": tp / max(args.plain, 1),
+                           "iters": ip},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +237,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-ttk", action="store_true", help="skip the time-to-1e-4 runs")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-workload block")
+    ap.add_argument("--train", type=int, default=20_000, help="parametric: training members")
+    ap.add_argument("--eval", type=int, default=1000, help="parametric: held-out members")
+    ap.add_argument("--epochs", type=int, default=60, help="parametric: training epochs")
+    ap.add_argument("--train-eps", type=float, default=1e-3, help="parametric: tolerance of the training solves")
+    ap.add_argument("--train-cap", type=int, default=20_000, help="parametric: iteration cap of training solves")
+    ap.add_argument("--plain", type=int, default=8, help="members solved by the plain single-problem solver")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this solver runs on one GPU; multi-GPU runs are not part of this "
@@ -131,6 +254,15 @@ def main():
     from paper_2203_05027_amd import instances as I
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "lp_parametric":
+        return bench_parametric(args)
+    if args.workload == "lp_batched":
+        out = batched_block()
+        print(json.dumps({"metric": "instance-iterations/s of the batched sweep (4096 LPs, one launch)",
+                          "value": out["instance_iters_per_s"], "unit": "instance-iter/s", "n_gpus": 1,
+                          "higher_is_better": True, "dtype": "f32 sweep / f64 duals", "data": "synthetic",
+                          "config": {"workload": "lp_batched"}, "batched": out}), flush=True)
+        return
     t0 = time.time()
     inst = I.config_instance(args.workload, scale=args.scale)
     m, n, nnz = inst["m"], inst["n"], inst["nnz"]
@@ -149,6 +281,12 @@ def main():
     dom = max(kern, key=lambda k: kern[k][1])
     achieved = kern[dom][0] / (kern[dom][1] * 1e-3) / 1e9
     sweep_gbs = (row_b + col_b) / ((main_r["ms_col"] + main_r["ms_row"]) * 1e-3) / 1e9
+
+    batched = None
+    if not args.no_batched and args.workload == "lp_large":
+        log("batched workload")
+        batched = batched_block()
+        log(f"batched: {json.dumps(batched)}")
 
     cpu = None
     if not args.no_cpu:
@@ -194,6 +332,7 @@ def main():
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "mixed": extra,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
