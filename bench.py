@@ -319,7 +319,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: LP m={m} n={n} nnz={nnz}, unit-norm rows, "
                                f"orthant cone, mu={args.mu}, check_every={args.check_every}",
-                   "launch": {k: main_r[k] for k in ("lanes_row", "unroll_row", "lanes_col",
+                   "launch": {k: main_r[k] for k in ("lanes_row", "unroll_row", "lanes_col", "slabs_row", "slabs_col",
                                                      "unroll_col")}},
         "time_to_1e-4_s": main_r["ttk_s"],
         "iters_to_1e-4": main_r["ttk_iters"],

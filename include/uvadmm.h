@@ -104,6 +104,9 @@ typedef struct {
     int32_t unroll_row;   /* gathers in flight per lane in the A x pass
                              (0 = automatic; else 1, 2, 4 or 8) */
     int32_t unroll_col;   /* same for the A'u pass */
+    int32_t slabs_row;    /* XCD slabs of x in the A x pass: 0 = automatic
+                             (about 2 MiB of x per slab), 1 = none, 2, 4, 8 */
+    int32_t slabs_col;    /* XCD slabs of u in the A'u pass (same values) */
 } uv_opts;
 
 /* Residuals at the last check, evaluated at (z, lambda, delta), all FP64
@@ -184,7 +187,8 @@ int solver_time_kernels(uv_solver *s, int32_t iters, double *ms_col,
 
 /* The resolved launch shape: shape[0] lanes per row and shape[1] gathers in
  * flight per lane in the row pass, shape[2], shape[3] the same for the
- * column pass (shape holds 4 entries). */
+ * column pass, shape[4], shape[5] the XCD slab counts of the row and column
+ * passes (shape holds 6 entries). */
 int solver_launch_shape(const uv_solver *s, int32_t *shape);
 
 /* ------------------------------------------------------------------------

@@ -163,9 +163,64 @@ __global__ void __launch_bounds__(kWG) k_widen(int64_t len, const T *__restrict_
     if (i < len) dst[i] = (double)src[i];
 }
 
+// Slab split of a compressed-row-like matrix (nr rows, ptr, idx): entry k
+// of row r belongs to slab min(idx[k] / w, S - 1) (S <= 8 contiguous index
+// ranges).  cnt[s * nr + r] = entries of row r in slab s.
+__global__ void __launch_bounds__(kWG)
+k_slab_count(int nr, const int *__restrict__ ptr, const int *__restrict__ idx, int S, int w, int *__restrict__ cnt)
+{
+    const int r = blockIdx.x * kWG + threadIdx.x;
+    if (r >= nr) return;
+    int c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = ptr[r]; k < ptr[r + 1]; ++k) c[min(idx[k] / w, S - 1)]++;
+    for (int s = 0; s < S; ++s) cnt[(int64_t)s * nr + r] = c[s];
+}
+
+// Scatter into the slab-major copy: off (S * nr + 1 entries, exclusive
+// prefix sums of cnt) gives where row r of slab s starts.  Entries keep
+// their order within a row, so the copy is deterministic.
+__global__ void __launch_bounds__(kWG)
+k_slab_scatter(int nr, const int *__restrict__ ptr, const int *__restrict__ idx, const double *__restrict__ val,
+               int S, int w, const int *__restrict__ off, int *__restrict__ sidx, double *__restrict__ sval)
+{
+    const int r = blockIdx.x * kWG + threadIdx.x;
+    if (r >= nr) return;
+    int pos[8];
+    for (int s = 0; s < S; ++s) pos[s] = off[(int64_t)s * nr + r];
+    for (int k = ptr[r]; k < ptr[r + 1]; ++k) {
+        const int p = pos[min(idx[k] / w, S - 1)]++;
+        sidx[p] = idx[k];
+        sval[p] = val[k];
+    }
+}
+
 inline unsigned blocks_for(int64_t items, int per_block)
 {
     return (unsigned)((items + per_block - 1) / per_block);
+}
+
+// out[0] = 0, out[i + 1] = in[0] + ... + in[i] for i < len; bsum needs
+// ceil(len / (4 * kWG)) ints.
+inline bool scan_exclusive(int len, const int *in, int *out, int *bsum, hipStream_t st)
+{
+    const int nscan = (int)blocks_for(len, 4 * kWG);
+    if (hipMemsetAsync(out, 0, 4, st) != hipSuccess) return false;
+    k_scan_local<<<nscan, kWG, 0, st>>>(len, in, out + 1, bsum);
+    k_scan_blocks<<<1, kWG, 0, st>>>(nscan, bsum);
+    k_scan_add<<<blocks_for(len, kWG), kWG, 0, st>>>(len, out + 1, bsum);
+    return hipGetLastError() == hipSuccess;
+}
+
+// Slab-major copy of a compressed-row-like matrix (see k_slab_count):
+// off (S * nr + 1), sidx and sval (nnz each); cnt (S * nr ints) and bsum
+// (ceil(S * nr / (4 * kWG)) ints) are scratch.
+inline bool build_slabs(int nr, int nnz, const int *ptr, const int *idx, const double *val, int S, int w, int *off,
+                        int *sidx, double *sval, int *cnt, int *bsum, hipStream_t st)
+{
+    k_slab_count<<<blocks_for(nr, kWG), kWG, 0, st>>>(nr, ptr, idx, S, w, cnt);
+    if (!scan_exclusive(S * nr, cnt, off, bsum, st)) return false;
+    if (nnz > 0) k_slab_scatter<<<blocks_for(nr, kWG), kWG, 0, st>>>(nr, ptr, idx, val, S, w, off, sidx, sval);
+    return hipGetLastError() == hipSuccess;
 }
 
 // Column-major copy (cp, ri, vc) of the CSR matrix (rp, ci, va): counting

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -192,12 +193,26 @@ __device__ __forceinline__ T x_step(int cnt, T xo, T zo, T atu, T dm, T cj, doub
     return (p + zo + dm - cj * (T)inv_mu) / (T)(1 + cnt);
 }
 
+// A'u for column col: the L-lane segment product over the column (S == 1)
+// or the sum of the S slab partials P[s * n + col] in slab order (S > 1).
+template <int L, int E, int S, typename T>
+__device__ __forceinline__ T col_atu(int col, int beg, int end, int lane, const int *__restrict__ ri,
+                                     const T *__restrict__ vc, const T *__restrict__ u, const T *__restrict__ P,
+                                     int n)
+{
+    if (S == 1) return seg_dot<L, E>(beg, end, lane, ri, vc, u);
+    T a = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) a += P[(size_t)s * n + col];
+    return a;
+}
+
 // Column pass over the orthant columns [0, n_orth).
-template <typename T, int L, int E>
+template <typename T, int L, int E, int S>
 __global__ void __launch_bounds__(kWG)
 k_col_orth(int n_orth, const int *__restrict__ cp, const int *__restrict__ ri, const T *__restrict__ vc,
            const T *__restrict__ u, T *__restrict__ x, T *__restrict__ z, double *__restrict__ delta,
-           const T *__restrict__ c, double mu, double inv_mu, const DevStatus *st)
+           const T *__restrict__ c, double mu, double inv_mu, const T *__restrict__ P, int n, const DevStatus *st)
 {
     if (st->done) return;
     const int lane = threadIdx.x & (L - 1);
@@ -206,7 +221,7 @@ k_col_orth(int n_orth, const int *__restrict__ cp, const int *__restrict__ ri, c
     const T xo = x[col], zo = z[col], cj = c[col];
     const double d = delta[col];
     const int beg = cp[col], end = cp[col + 1];
-    const T atu = seg_dot<L, E>(beg, end, lane, ri, vc, u);
+    const T atu = col_atu<L, E, S>(col, beg, end, lane, ri, vc, u, P, n);
     if (lane == 0) {
         const T dm = (T)(d * inv_mu);
         const T xn = x_step<T>(end - beg, xo, zo, atu, dm, cj, inv_mu);
@@ -223,12 +238,12 @@ k_col_orth(int n_orth, const int *__restrict__ cp, const int *__restrict__ ri, c
 // columns): phase 1 computes x and v = x - delta/mu per column into LDS,
 // phase 2 takes each cone's tail norm and its projection case (eq. proj),
 // phase 3 writes x, z and delta.
-template <typename T, int L, int E, int TC>
+template <typename T, int L, int E, int TC, int S>
 __global__ void __launch_bounds__(kWG)
 k_col_soc(const int *__restrict__ tcol, const int *__restrict__ tcone, const int *__restrict__ soc_off,
           const int *__restrict__ cp, const int *__restrict__ ri, const T *__restrict__ vc,
           const T *__restrict__ u, T *__restrict__ x, T *__restrict__ z, double *__restrict__ delta,
-          const T *__restrict__ c, double mu, double inv_mu, const DevStatus *st)
+          const T *__restrict__ c, double mu, double inv_mu, const T *__restrict__ P, int n, const DevStatus *st)
 {
     if (st->done) return;
     __shared__ T sx[TC];
@@ -249,7 +264,7 @@ k_col_soc(const int *__restrict__ tcol, const int *__restrict__ tcone, const int
         const T xo = x[col], zo = z[col], cj = c[col];
         const double d = delta[col];
         const int beg = cp[col], end = cp[col + 1];
-        const T atu = seg_dot<L, E>(beg, end, lane, ri, vc, u);
+        const T atu = col_atu<L, E, S>(col, beg, end, lane, ri, vc, u, P, n);
         if (lane == 0) {
             const T dm = (T)(d * inv_mu);
             const T xn = x_step<T>(end - beg, xo, zo, atu, dm, cj, inv_mu);
@@ -284,6 +299,82 @@ k_col_soc(const int *__restrict__ tcol, const int *__restrict__ tcone, const int
         z[col] = zn;
         delta[col] = sd[jj] + mu * ((double)zn - (double)xn);
     }
+}
+
+// XCD-local slab passes.  The gathered vector (x in the row pass, u in the
+// column pass) is cut into S contiguous slabs and the matrix into the
+// matching slab-major copies; workgroup w works on slab w % S, so with the
+// round-robin workgroup-to-XCD dispatch each XCD only gathers from 1/S of
+// the vector (at most a few MiB, resident in its L2), and writes one partial
+// per row (column) and slab.  The update kernels add the S partials in slab
+// order, so the result is deterministic.
+template <typename T, int L, int E, int S, bool CHECK>
+__global__ void __launch_bounds__(kWG)
+k_row_slab(int m, const int *__restrict__ srp, const int *__restrict__ sci, const T *__restrict__ sva,
+           const T *__restrict__ x, const T *__restrict__ z, T *__restrict__ P, int ignore_done,
+           const DevStatus *st)
+{
+    if (!ignore_done && st->done) return;
+    const int sl = blockIdx.x % S, t = blockIdx.x / S;
+    const int lane = threadIdx.x & (L - 1);
+    const int row = t * (kWG / L) + threadIdx.x / L;
+    if (row >= m) return;
+    const int beg = srp[(size_t)sl * m + row], end = srp[(size_t)sl * m + row + 1];
+    const T q = seg_dot<L, E>(beg, end, lane, sci, sva, x);
+    T qz = 0;
+    if (CHECK) qz = seg_dot<L, E>(beg, end, lane, sci, sva, z);
+    if (lane == 0) {
+        P[(size_t)sl * m + row] = q;
+        if (CHECK) P[(size_t)(S + sl) * m + row] = qz;
+    }
+}
+
+// Row update from slab partials; the MODEs of k_row.
+template <typename T, int S, int MODE>
+__global__ void __launch_bounds__(kWG)
+k_row_combine(int m, const T *__restrict__ P, const T *__restrict__ b, const T *__restrict__ fu,
+              double *__restrict__ lam, T *__restrict__ u, double mu, double inv_mu, double *__restrict__ part,
+              int pstride, DevStatus *st)
+{
+    if (MODE != 2 && st->done) return;
+    const int row = blockIdx.x * kWG + threadIdx.x;
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (row < m) {
+        const T bi = b[row], fi = fu[row];
+        const double l0 = lam[row];
+        T q = 0, qz = 0;
+#pragma unroll
+        for (int sl = 0; sl < S; ++sl) {
+            q += P[(size_t)sl * m + row];
+            if (MODE == 1) qz += P[(size_t)(S + sl) * m + row];
+        }
+        const T e = fi * (bi - q);
+        const double li = (MODE == 2) ? l0 : l0 - mu * (double)e;
+        if (MODE != 2) lam[row] = li;
+        u[row] = (T)((double)e - li * inv_mu);
+        if (MODE == 1) {
+            const double rz = (double)qz - (double)bi, rx = (double)q - (double)bi;
+            acc[0] = rz * rz;
+            acc[1] = (double)bi * li;
+            acc[2] = rx * rx;
+        }
+    }
+    if (MODE != 2 && blockIdx.x == 0 && threadIdx.x == 0) st->iter += 1;
+    if (MODE == 1) uv::block_sum<3>(acc, part + blockIdx.x, pstride);
+}
+
+template <typename T, int L, int E, int S>
+__global__ void __launch_bounds__(kWG)
+k_col_slab(int n, const int *__restrict__ scp, const int *__restrict__ sri, const T *__restrict__ svc,
+           const T *__restrict__ u, T *__restrict__ P, const DevStatus *st)
+{
+    if (st->done) return;
+    const int sl = blockIdx.x % S, t = blockIdx.x / S;
+    const int lane = threadIdx.x & (L - 1);
+    const int col = t * (kWG / L) + threadIdx.x / L;
+    if (col >= n) return;
+    const T a = seg_dot<L, E>(scp[(size_t)sl * n + col], scp[(size_t)sl * n + col + 1], lane, sri, svc, u);
+    if (lane == 0) P[(size_t)sl * n + col] = a;
 }
 
 // Residual-only column pass: ||A'lambda + c - delta||^2 and c'z partials,
@@ -401,6 +492,13 @@ struct uv_solver {
     DevStatus *st_host = nullptr;             // pinned
     int L_row = 8, L_col = 4;   // lanes per row / column
     int E_row = 4, E_col = 4;   // gathers in flight per lane
+    int S_row = 1, S_col = 1;   // XCD slabs of x (row pass) and of u (column pass)
+    int *srp = nullptr, *sci = nullptr;  // row-pass slab copy (S_row * m + 1 offsets)
+    void *sva = nullptr;
+    int *scp = nullptr, *sri = nullptr;  // column-pass slab copy (S_col * n + 1 offsets)
+    void *svc = nullptr;
+    void *P_row = nullptr, *P_col = nullptr;  // slab partials (2 S_row m, S_col n)
+    int nblk_row_fused = 0;     // row-residual partial blocks written by the check row pass
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int64_t host_iter = 0;
@@ -434,12 +532,49 @@ bool lanes_ok(int L) { return L == 0 || (L >= 1 && L <= 64 && (L & (L - 1)) == 0
 
 bool unroll_ok(int E) { return E == 0 || E == 1 || E == 2 || E == 4 || E == 8; }
 
+bool slabs_ok(int S) { return S == 0 || S == 1 || S == 2 || S == 4 || S == 8; }
+
+// Slabs for a gathered vector of `bytes`: none up to 2 MiB, else enough
+// power-of-two slabs (at most one per XCD) for about 2 MiB each.
+int pick_slabs(size_t bytes)
+{
+    int S = 1;
+    while (S < 8 && bytes > (size_t)S * (2u << 20)) S <<= 1;
+    return S;
+}
+
 // ---- launch helpers (dispatch on precision, lanes L and unroll E) ----
+
+template <typename T, int L, int E, int S>
+void row_slab_launch(uv_solver *s, hipStream_t st, int mode)
+{
+    const unsigned g = S * blocks_for(s->m, kWG / L), gc = blocks_for(s->m, kWG);
+    const double mu = s->o.mu, im = 1.0 / s->o.mu;
+#define UV_SLAB_ARGS s->m, s->srp, s->sci, (const T *)s->sva, (const T *)s->x, (const T *)s->z, (T *)s->P_row
+#define UV_COMB_ARGS                                                                                       \
+    s->m, (const T *)s->P_row, (const T *)s->b, (const T *)s->fu, s->lam, (T *)s->u, mu, im, s->part_row,  \
+        s->nblk_row_fused, s->st
+    if (mode == 1) {
+        k_row_slab<T, L, E, S, true><<<g, kWG, 0, st>>>(UV_SLAB_ARGS, 0, s->st);
+        k_row_combine<T, S, 1><<<gc, kWG, 0, st>>>(UV_COMB_ARGS);
+    } else if (mode == 2) {
+        k_row_slab<T, L, E, S, false><<<g, kWG, 0, st>>>(UV_SLAB_ARGS, 1, s->st);
+        k_row_combine<T, S, 2><<<gc, kWG, 0, st>>>(UV_COMB_ARGS);
+    } else {
+        k_row_slab<T, L, E, S, false><<<g, kWG, 0, st>>>(UV_SLAB_ARGS, 0, s->st);
+        k_row_combine<T, S, 0><<<gc, kWG, 0, st>>>(UV_COMB_ARGS);
+    }
+#undef UV_SLAB_ARGS
+#undef UV_COMB_ARGS
+}
 
 template <typename T, int L, int E>
 struct RowLaunch {
     static void run(uv_solver *s, hipStream_t st, int mode)
     {
+        if (s->S_row == 2) return row_slab_launch<T, L, E, 2>(s, st, mode);
+        if (s->S_row == 4) return row_slab_launch<T, L, E, 4>(s, st, mode);
+        if (s->S_row == 8) return row_slab_launch<T, L, E, 8>(s, st, mode);
         const unsigned g = blocks_for(s->m, kWG / L);
         const double mu = s->o.mu, im = 1.0 / s->o.mu;
 #define UV_ROW_ARGS                                                                                        \
@@ -452,25 +587,45 @@ struct RowLaunch {
     }
 };
 
+// Column update (x-step, projection, delta) over all cones; LL/EE/S: lanes,
+// unroll and slab count of the A'u it uses.
+template <typename T, int LL, int EE, int S>
+void col_update_launch(uv_solver *s, hipStream_t st)
+{
+    const double mu = s->o.mu, im = 1.0 / s->o.mu;
+    if (s->n_orth > 0) {
+        const unsigned g = blocks_for(s->n_orth, kWG / LL);
+        k_col_orth<T, LL, EE, S><<<g, kWG, 0, st>>>(s->n_orth, s->cp, s->ri, (const T *)s->vc, (const T *)s->u,
+                                                    (T *)s->x, (T *)s->z, s->delta, (const T *)s->c, mu, im,
+                                                    (const T *)s->P_col, s->n, s->st);
+    }
+    if (s->ntiles > 0) {
+#define UV_SOC_ARGS                                                                                        \
+    s->tcol, s->tcone, s->soc_off, s->cp, s->ri, (const T *)s->vc, (const T *)s->u, (T *)s->x, (T *)s->z, \
+        s->delta, (const T *)s->c, mu, im, (const T *)s->P_col, s->n, s->st
+        if (s->tile_cap <= kSocTile) k_col_soc<T, LL, EE, kSocTile, S><<<s->ntiles, kWG, 0, st>>>(UV_SOC_ARGS);
+        else k_col_soc<T, LL, EE, UV_MAX_CONE, S><<<s->ntiles, kWG, 0, st>>>(UV_SOC_ARGS);
+#undef UV_SOC_ARGS
+    }
+}
+
+template <typename T, int L, int E, int S>
+void col_slab_launch(uv_solver *s, hipStream_t st)
+{
+    const unsigned g = S * blocks_for(s->n, kWG / L);
+    k_col_slab<T, L, E, S><<<g, kWG, 0, st>>>(s->n, s->scp, s->sri, (const T *)s->svc, (const T *)s->u,
+                                              (T *)s->P_col, s->st);
+    col_update_launch<T, 1, 1, S>(s, st);
+}
+
 template <typename T, int L, int E>
 struct ColLaunch {
     static void run(uv_solver *s, hipStream_t st, int)
     {
-        const double mu = s->o.mu, im = 1.0 / s->o.mu;
-        if (s->n_orth > 0) {
-            const unsigned g = blocks_for(s->n_orth, kWG / L);
-            k_col_orth<T, L, E><<<g, kWG, 0, st>>>(s->n_orth, s->cp, s->ri, (const T *)s->vc, (const T *)s->u,
-                                                   (T *)s->x, (T *)s->z, s->delta, (const T *)s->c, mu, im,
-                                                   s->st);
-        }
-        if (s->ntiles > 0) {
-#define UV_SOC_ARGS                                                                                        \
-    s->tcol, s->tcone, s->soc_off, s->cp, s->ri, (const T *)s->vc, (const T *)s->u, (T *)s->x, (T *)s->z, \
-        s->delta, (const T *)s->c, mu, im, s->st
-            if (s->tile_cap <= kSocTile) k_col_soc<T, L, E, kSocTile><<<s->ntiles, kWG, 0, st>>>(UV_SOC_ARGS);
-            else k_col_soc<T, L, E, UV_MAX_CONE><<<s->ntiles, kWG, 0, st>>>(UV_SOC_ARGS);
-#undef UV_SOC_ARGS
-        }
+        if (s->S_col == 2) return col_slab_launch<T, L, E, 2>(s, st);
+        if (s->S_col == 4) return col_slab_launch<T, L, E, 4>(s, st);
+        if (s->S_col == 8) return col_slab_launch<T, L, E, 8>(s, st);
+        col_update_launch<T, L, E, 1>(s, st);
     }
 };
 
@@ -562,7 +717,8 @@ void launch_residuals(uv_solver *s, hipStream_t st, bool row_done)
 {
     if (!row_done) dispatch_le_res<ResRowLaunch>(s, st, s->L_row);
     dispatch_le_res<ResColLaunch>(s, st, s->L_col);
-    k_finalize<<<1, kWG, 0, st>>>(s->nblk_row, s->part_row, s->nblk_rescol, s->part_col, s->o.eps_kkt, s->st);
+    const int nrow = row_done ? s->nblk_row_fused : s->nblk_row;
+    k_finalize<<<1, kWG, 0, st>>>(nrow, s->part_row, s->nblk_rescol, s->part_col, s->o.eps_kkt, s->st);
 }
 
 // One iteration; with check, the residuals of the new iterate follow it.
@@ -600,6 +756,7 @@ int validate(const uv_csr *A, const double *b, const double *c, const uv_cones *
     if (o->check_every < 1 || !(o->eps_kkt >= 0.0) || o->max_iter < 0) return UV_EINVAL;
     if (!lanes_ok(o->lanes_row) || !lanes_ok(o->lanes_col)) return UV_EINVAL;
     if (!unroll_ok(o->unroll_row) || !unroll_ok(o->unroll_col)) return UV_EINVAL;
+    if (!slabs_ok(o->slabs_row) || !slabs_ok(o->slabs_col)) return UV_EINVAL;
     if (A->nnz > 0 && (!A->col_idx || !A->val)) return UV_EINVAL;
     if (!A->row_ptr) return UV_EINVAL;
     if (A->nnz >= ((int64_t)1 << 31)) return UV_ETOOBIG;
@@ -666,13 +823,14 @@ int setup(uv_solver *s, const uv_csr *A, const double *b, const double *c, const
         s->c = s->c64;
     }
     s->nblk_row = (int)blocks_for(m, kWG / s->L_row);
+    s->nblk_row_fused = s->S_row > 1 ? (int)blocks_for(m, kWG) : s->nblk_row;
     s->nblk_rescol = (int)blocks_for(n, kWG / s->L_col);
-    s->part_row = dalloc<double>(s, 3 * (size_t)s->nblk_row);
+    s->part_row = dalloc<double>(s, 3 * (size_t)std::max(s->nblk_row, s->nblk_row_fused));
     s->part_col = dalloc<double>(s, 2 * (size_t)s->nblk_rescol);
     s->st = dalloc<DevStatus>(s, 1);
-    int *cnt = dalloc<int>(s, n);
-    const int nscan = (int)blocks_for(n, 4 * kWG);
-    int *bsum = dalloc<int>(s, nscan);
+    const size_t ncnt = std::max({(size_t)n, (size_t)s->S_row * m, (size_t)s->S_col * n});
+    int *cnt = dalloc<int>(s, ncnt);
+    int *bsum = dalloc<int>(s, blocks_for(ncnt, 4 * kWG));
     for (void *p : {(void *)s->rp, (void *)s->ci, (void *)s->va64, (void *)s->cp, (void *)s->ri,
                     (void *)s->vc64, (void *)s->b64, (void *)s->c64, (void *)s->lam, (void *)s->delta,
                     (void *)s->scratch, s->x, s->z, s->u, s->fu, s->va, s->vc, s->b, s->c,
@@ -727,6 +885,31 @@ int setup(uv_solver *s, const uv_csr *A, const double *b, const double *c, const
     // Column-major copy of A.
     if (!build_csc(m, n, nnz, s->rp, s->ci, s->va64, s->cp, s->ri, s->vc64, cnt, bsum, st)) return UV_EHIP;
 
+    // XCD slab copies: row pass split by column ranges, column pass by row ranges.
+    for (int pass = 0; pass < 2; ++pass) {
+        const int S = pass == 0 ? s->S_row : s->S_col;
+        if (S == 1) continue;
+        const int nr = pass == 0 ? m : n, width = pass == 0 ? n : m;
+        int *off = dalloc<int>(s, (size_t)S * nr + 1);
+        int *sidx = dalloc<int>(s, nnz);
+        double *sval64 = dalloc<double>(s, nnz);
+        void *part = dalloc<char>(s, ts * (size_t)(pass == 0 ? 2 * S : S) * nr);
+        if (!off || !sidx || !sval64 || !part) return UV_ENOMEM;
+        const int w = (width + S - 1) / S;
+        const bool ok = pass == 0
+                            ? build_slabs(m, nnz, s->rp, s->ci, s->va64, S, w, off, sidx, sval64, cnt, bsum, st)
+                            : build_slabs(n, nnz, s->cp, s->ri, s->vc64, S, w, off, sidx, sval64, cnt, bsum, st);
+        if (!ok) return UV_EHIP;
+        void *sval = sval64;
+        if (mixed) {
+            sval = dalloc<float>(s, nnz);
+            if (!sval) return UV_ENOMEM;
+            if (nnz > 0) k_narrow<float><<<blocks_for(nnz, kWG), kWG, 0, st>>>(nnz, sval64, (float *)sval);
+        }
+        if (pass == 0) { s->srp = off; s->sci = sidx; s->sva = sval; s->P_row = part; }
+        else { s->scp = off; s->sri = sidx; s->svc = sval; s->P_col = part; }
+    }
+
     // F_U, narrowed copies, norms.
     if (mixed) {
         k_row_factor<float><<<blocks_for(m, kWG), kWG, 0, st>>>(m, s->rp, s->va64, (float *)s->fu);
@@ -767,6 +950,8 @@ void uv_default_opts(uv_opts *o)
     o->use_graph = 1;
     o->unroll_row = 0;
     o->unroll_col = 0;
+    o->slabs_row = 0;
+    o->slabs_col = 0;
 }
 
 const char *solver_strerror(int code)
@@ -819,6 +1004,14 @@ int solver_create(const uv_csr *A, const double *b, const double *c, const uv_co
     s->L_col = o.lanes_col ? o.lanes_col : pick_lanes((double)A->nnz / A->n);
     s->E_row = o.unroll_row ? o.unroll_row : 4;
     s->E_col = o.unroll_col ? o.unroll_col : 4;
+    {
+        const size_t ts = o.precision == UV_MIXED ? 4 : 8;
+        s->S_row = o.slabs_row ? o.slabs_row : pick_slabs(ts * (size_t)A->n);
+        s->S_col = o.slabs_col ? o.slabs_col : pick_slabs(ts * (size_t)A->m);
+        // a slab needs at least one index, and slab offsets are 32-bit
+        while (s->S_row > 1 && (s->S_row > A->n || (int64_t)s->S_row * A->m >= INT32_MAX)) s->S_row >>= 1;
+        while (s->S_col > 1 && (s->S_col > A->m || (int64_t)s->S_col * A->n >= INT32_MAX)) s->S_col >>= 1;
+    }
     rc = setup(s, A, b, c, K);
     if (rc == UV_OK) rc = solver_set_start(s, nullptr, nullptr, nullptr, nullptr);
     if (rc == UV_OK && s->o.use_graph) rc = build_graph(s);
@@ -1012,6 +1205,8 @@ int solver_launch_shape(const uv_solver *s, int32_t *shape)
     shape[1] = s->E_row;
     shape[2] = s->L_col;
     shape[3] = s->E_col;
+    shape[4] = s->S_row;
+    shape[5] = s->S_col;
     return UV_OK;
 }
 

@@ -36,7 +36,8 @@ class UvOpts(ctypes.Structure):
                 ("max_iter", ctypes.c_int64), ("hip_stream", ctypes.c_void_p),
                 ("lanes_row", ctypes.c_int32), ("lanes_col", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("unroll_row", ctypes.c_int32),
-                ("unroll_col", ctypes.c_int32)]
+                ("unroll_col", ctypes.c_int32), ("slabs_row", ctypes.c_int32),
+                ("slabs_col", ctypes.c_int32)]
 
 
 class UvResiduals(ctypes.Structure):
@@ -135,8 +136,8 @@ class Solver:
 
     def __init__(self, m, n, row_ptr, col_idx, val, b, c, n_orth, soc_sizes=(), *,
                  mu=1.0, precision="fp64", check_every=10, eps=1e-4, max_iter=0,
-                 lanes_row=0, lanes_col=0, unroll_row=0, unroll_col=0, use_graph=True,
-                 stream=None):
+                 lanes_row=0, lanes_col=0, unroll_row=0, unroll_col=0, slabs_row=0, slabs_col=0,
+                 use_graph=True, stream=None):
         L = lib()
         self.m, self.n = int(m), int(n)
         rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
@@ -154,6 +155,7 @@ class Solver:
         o.hip_stream = stream
         o.lanes_row, o.lanes_col = int(lanes_row), int(lanes_col)
         o.unroll_row, o.unroll_col = int(unroll_row), int(unroll_col)
+        o.slabs_row, o.slabs_col = int(slabs_row), int(slabs_col)
         o.use_graph = 1 if use_graph else 0
         self.precision = precision
         self.nnz = csr.nnz
@@ -226,9 +228,10 @@ class Solver:
 
     def launch_shape(self) -> dict:
         """Lanes and gathers in flight per lane of the row and column passes."""
-        a = (ctypes.c_int32 * 4)()
+        a = (ctypes.c_int32 * 6)()
         _check(lib().solver_launch_shape(self._h, a), "solver_launch_shape")
-        return {"lanes_row": a[0], "unroll_row": a[1], "lanes_col": a[2], "unroll_col": a[3]}
+        return {"lanes_row": a[0], "unroll_row": a[1], "lanes_col": a[2], "unroll_col": a[3],
+                "slabs_row": a[4], "slabs_col": a[5]}
 
 
 def _bind_batch(L):

@@ -71,6 +71,39 @@ def test_launch_shapes(lanes, unroll, graph):
     assert_parity(g, o)
 
 
+@pytest.mark.parametrize("slabs", [(2, 2), (8, 4), (4, 8), (8, 1), (1, 8)])
+@pytest.mark.parametrize("prec", ["fp64"])
+def test_xcd_slabs(slabs, prec):
+    """Slab-split passes (forced on a small ragged problem) against the oracle,
+    with the fused residual check inside the chunk."""
+    inst = I.conic_instance(1003, 411, [3, 7, 50, 1, 260] + [5] * 40, 4, seed=23)
+    g, o, gr, orr = run_pair(inst, 200, mu=0.9, slabs_row=slabs[0], slabs_col=slabs[1], check_every=9,
+                             lanes_row=4, lanes_col=2)
+    assert_parity(g, o)
+    for k in ("r_prim", "r_dual", "r_gap", "pobj", "dobj", "res_ax_b"):
+        assert abs(gr[k] - orr[k]) <= 1e-9 * max(abs(orr[k]), 1e-12), k
+
+
+def test_xcd_slabs_resume_and_mixed():
+    inst = I.lp_instance(3000, 6100, 6, seed=24)
+    rng = np.random.default_rng(2)
+    st = (rng.standard_normal(inst["n"]), rng.standard_normal(inst["n"]),
+          rng.standard_normal(inst["n"]), rng.standard_normal(inst["m"]))
+    orc = oracle.Oracle.from_instance(inst)
+    orc.resume(*st)
+    orc.iterate(100)
+    with Solver.from_instance(inst, eps=0.0, slabs_row=8, slabs_col=8) as s:
+        assert s.launch_shape()["slabs_row"] == 8
+        s.resume(*st)
+        s.iterate(100)
+        assert_parity(s.solution(), orc.state())
+    with Solver.from_instance(inst, eps=1e-4, precision="mixed", slabs_row=4, slabs_col=2) as s:
+        assert s.iterate(200_000)
+        r = s.residuals()
+    assert r["status"] == "converged" and r["kkt"] <= 1e-4
+    assert abs(r["pobj"] - inst["p_star"]) <= 2e-3 * abs(inst["p_star"])
+
+
 @pytest.mark.parametrize("unroll", [1, 2, 8])
 def test_socp_unroll_shapes(unroll):
     inst = I.socp_instance(150, 8, seed=21)
@@ -202,6 +235,19 @@ def test_bitwise_reproducible():
     for o in outs[1:]:
         for k in KEYS:
             assert np.array_equal(o[k], outs[0][k])
+
+
+@pytest.mark.parametrize("name", ["lp_large", "socp_large"])
+def test_full_size_sampled_parity(name):
+    """The full-size workloads in the launch configuration the benchmark
+    times (automatic lanes, unroll and XCD slabs, graph replay): 3 iterations
+    from the zero start, every entry against the oracle."""
+    inst = I.config_instance(name)
+    say(f"{name}: m={inst['m']} n={inst['n']} nnz={inst['nnz']}")
+    g, o, gr, orr = run_pair(inst, 3, check_every=3)
+    assert_parity(g, o)
+    for k in ("r_prim", "r_dual", "r_gap", "pobj", "dobj"):
+        assert abs(gr[k] - orr[k]) <= 1e-9 * max(abs(orr[k]), 1e-12), k
 
 
 def test_mixed_precision_small_lp():
