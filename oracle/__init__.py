@@ -21,19 +21,23 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "uvadmm_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# a different build of the same source (the mutation tests point this at a
+# copy with a planted mistake)
+_LIB = os.environ.get("UVADMM_ORACLE_LIB", _LIB)
 
 _lib = None
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, src: str = _SRC, out: str | None = None) -> str:
     """Compile the oracle into ``oracle/liboracle.so`` (gcc, -O2, OpenMP)."""
+    out = out or _LIB
     cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
-           "-Wextra", "-o", _LIB + ".tmp", _SRC, "-lm"]
+           "-Wextra", "-o", out + ".tmp", src, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(_LIB + ".tmp", _LIB)
-    return _LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 def _load():

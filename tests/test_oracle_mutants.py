@@ -1,0 +1,46 @@
+"""The pins must catch plausible mistakes in the oracle: each case plants one
+(a dropped term, a wrong sign, a wrong index or factor) in a copy of the
+oracle's C source, builds it, and runs the pin suite against it in a
+subprocess; the suite has to fail."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "uvadmm_oracle.c")
+
+MUTANTS = {
+    "x-step drops delta/mu": ("+ h->z[j] + h->delta[j] / mu - h->c[j] / mu", "+ h->z[j] - h->c[j] / mu"),
+    "x-step sign of c": ("+ h->z[j] + h->delta[j] / mu - h->c[j] / mu", "+ h->z[j] + h->delta[j] / mu + h->c[j] / mu"),
+    "y-step lambda scaled by mu": ("(h->b[i] - h->lambda[i] / mu)", "(h->b[i] - h->lambda[i] * mu)"),
+    "y-step gamma sign": ("+ h->x[h->ck[k]] - h->gamma[k] / mu;", "+ h->x[h->ck[k]] + h->gamma[k] / mu;"),
+    "F_U from absolute values": ("d += h->ak[k] * h->ak[k];", "d += fabs(h->ak[k]);"),
+    "F_V off by one": ("for (int64_t p = h->col_ptr[j]; p < h->col_ptr[j + 1]; ++p) d += 1.0;",
+                       "for (int64_t p = h->col_ptr[j]; p <= h->col_ptr[j + 1]; ++p) d += 1.0;"),
+    "projection head sign": ("out[0] = w1 / 2.0 + alpha / 2.0;", "out[0] = w1 / 2.0 - alpha / 2.0;"),
+    "projection case order": ("} else if (alpha <= w1) {", "} else if (alpha <= -w1 + 1e-3) {"),
+    "lambda update sign": ("h->lambda[i] += mu * (uy - h->b[i]);", "h->lambda[i] -= mu * (uy - h->b[i]);"),
+    "gamma update uses +x": ("h->gamma[k] += mu * (h->y[k] - h->x[h->ck[k]]);",
+                             "h->gamma[k] += mu * (h->y[k] + h->x[h->ck[k]]);"),
+    "delta update sign": ("h->delta[j] += mu * (h->z[j] - h->x[j]);", "h->delta[j] += mu * (h->x[j] - h->z[j]);"),
+    "dual residual drops delta": ("double r = atl + h->c[j] - h->delta[j];", "double r = atl + h->c[j];"),
+    "U transposed in y-step sum": ("ut += h->ak[k] * h->t[k];", "ut += h->t[k];"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name, tmp_path):
+    import oracle
+    old, new = MUTANTS[name]
+    text = open(SRC).read()
+    assert text.count(old) == 1, f"mutation site not unique: {old}"
+    src = tmp_path / "mutant.c"
+    src.write_text(text.replace(old, new))
+    lib = oracle.build(src=str(src), out=str(tmp_path / "libmutant.so"))
+    env = dict(os.environ, UVADMM_ORACLE_LIB=lib, OMP_NUM_THREADS="2")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"pins did not catch: {name}\n{r.stdout[-2000:]}"
