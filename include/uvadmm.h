@@ -295,6 +295,24 @@ int family_solution_device(uv_family *h, float *dst_dev, int64_t ld);
 void family_destroy(uv_family *h);
 
 /* ------------------------------------------------------------------------
+ * Algorithm 1 as printed (FP64, orthant cone): y and gamma (one entry per
+ * stored nonzero, eq. prob_reform) are stored and updated, U, U', V, V'
+ * applied as sums over the nonzero index (eqs. UU, VV).  The ablation of the
+ * reduced form and a second GPU implementation of the same iteration; zero
+ * start, no residual checks.
+ * ------------------------------------------------------------------------ */
+typedef struct uv_literal uv_literal;
+int literal_create(const uv_csr *A, const double *b, const double *c,
+                   const uv_opts *opts, uv_literal **out);
+int literal_iterate(uv_literal *h, int64_t k);
+/* x, z, delta (n), lambda (m), y, gamma (nnz, CSR order); any may be NULL. */
+int literal_solution(uv_literal *h, double *x, double *z, double *lambda,
+                     double *delta, double *y, double *gamma);
+/* Average duration (ms) of the column and row passes over `iters` iterations. */
+int literal_time(uv_literal *h, int32_t iters, double *ms_col, double *ms_row);
+void literal_destroy(uv_literal *h);
+
+/* ------------------------------------------------------------------------
  * Learned warm start: dense kernels.  Pointers marked _dev are DEVICE
  * pointers (for instance from framework tensors); the stream argument may be
  * NULL (the default stream).  All of these wait for their work to finish.

@@ -492,3 +492,73 @@ class Family:
         """Writes FP32 rows [z ; lambda] of the current instances to device memory."""
         _check(lib().family_solution_device(self._h, ctypes.c_void_p(dev_ptr), int(ld)),
                "family_solution_device")
+
+
+class Literal:
+    """Algorithm 1 as printed on the GPU (FP64, orthant cone, y and gamma stored)."""
+
+    def __init__(self, m, n, row_ptr, col_idx, val, b, c, *, mu=1.0, stream=None):
+        L = lib()
+        if not hasattr(L, "_literal_bound"):
+            P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+            L.literal_create.argtypes = [ctypes.POINTER(UvCsr), P, P, ctypes.POINTER(UvOpts), ctypes.POINTER(P)]
+            L.literal_create.restype = ctypes.c_int
+            L.literal_iterate.argtypes = [P, i64]
+            L.literal_iterate.restype = ctypes.c_int
+            L.literal_solution.argtypes = [P, P, P, P, P, P, P]
+            L.literal_solution.restype = ctypes.c_int
+            L.literal_time.argtypes = [P, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+            L.literal_time.restype = ctypes.c_int
+            L.literal_destroy.argtypes = [P]
+            L.literal_destroy.restype = None
+            L._literal_bound = True
+        self.m, self.n = int(m), int(n)
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        va = np.ascontiguousarray(val, dtype=np.float64)
+        self.nnz = int(rp[-1])
+        csr = UvCsr(self.m, self.n, self.nnz, _ptr(rp), _ptr(ci), _ptr(va))
+        o = default_opts()
+        o.mu = float(mu)
+        o.hip_stream = stream
+        h = ctypes.c_void_p()
+        _check(L.literal_create(ctypes.byref(csr), _ptr(_f64(b, self.m)), _ptr(_f64(c, self.n)),
+                                ctypes.byref(o), ctypes.byref(h)), "literal_create")
+        self._h = h
+
+    @classmethod
+    def from_instance(cls, inst, **kw):
+        return cls(inst["m"], inst["n"], inst["row_ptr"], inst["col_idx"], inst["val"], inst["b"],
+                   inst["c"], **kw)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().literal_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def iterate(self, k: int):
+        _check(lib().literal_iterate(self._h, int(k)), "literal_iterate")
+
+    def solution(self) -> dict:
+        x, z, d = np.empty(self.n), np.empty(self.n), np.empty(self.n)
+        lam, y, g = np.empty(self.m), np.empty(self.nnz), np.empty(self.nnz)
+        _check(lib().literal_solution(self._h, _ptr(x), _ptr(z), _ptr(lam), _ptr(d), _ptr(y), _ptr(g)),
+               "literal_solution")
+        return {"x": x, "z": z, "delta": d, "lambda": lam, "y": y, "gamma": g}
+
+    def time(self, iters: int):
+        a, b = ctypes.c_double(), ctypes.c_double()
+        _check(lib().literal_time(self._h, int(iters), ctypes.byref(a), ctypes.byref(b)), "literal_time")
+        return a.value, b.value
