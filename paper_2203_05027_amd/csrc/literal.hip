@@ -88,34 +88,23 @@ k_lit_row(int m, const int *__restrict__ rp, const int *__restrict__ ci, const d
     if (lane == 0) lam[row] += mu * (uy - b[row]);
 }
 
-// kcol: the nonzero index k of each CSC position (CSR order within a column
-// is increasing row, i.e. increasing k).
+// kcol: the nonzero index k (CSR position) of each CSC position: entry p of
+// column j sits in row ri[p]; its k is found by binary search for j among
+// that row's sorted column indices.  No atomics, no sort: deterministic.
 __global__ void __launch_bounds__(kWG)
-k_lit_kcol(int m, const int *__restrict__ rp, const int *__restrict__ ci, const int *__restrict__ cp,
-           int *__restrict__ fill, int *__restrict__ kcol)
-{
-    const int i = blockIdx.x * kWG + threadIdx.x;
-    if (i >= m) return;
-    for (int k = rp[i]; k < rp[i + 1]; ++k) {
-        const int j = ci[k];
-        kcol[cp[j] + atomicAdd(&fill[j], 1)] = k;
-    }
-}
-
-__global__ void __launch_bounds__(kWG) k_lit_sort(int n, const int *__restrict__ cp, int *__restrict__ kcol)
+k_lit_kcol(int n, const int *__restrict__ cp, const int *__restrict__ ri, const int *__restrict__ rp,
+           const int *__restrict__ ci, int *__restrict__ kcol)
 {
     const int j = blockIdx.x * kWG + threadIdx.x;
     if (j >= n) return;
-    int *a = kcol + cp[j];
-    const int len = cp[j + 1] - cp[j];
-    for (int p = 1; p < len; ++p) {  // columns are short; insertion sort
-        const int v = a[p];
-        int q = p - 1;
-        while (q >= 0 && a[q] > v) {
-            a[q + 1] = a[q];
-            --q;
+    for (int p = cp[j]; p < cp[j + 1]; ++p) {
+        int lo = rp[ri[p]], hi = rp[ri[p] + 1];
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (ci[mid] < j) lo = mid + 1;
+            else hi = mid;
         }
-        a[q + 1] = v;
+        kcol[p] = lo;
     }
 }
 
@@ -262,9 +251,7 @@ int literal_create(const uv_csr *A, const double *b, const double *c, const uv_o
         hipMemcpy(h->c, c, 8 * (size_t)n, hipMemcpyHostToDevice) != hipSuccess)
         return fail(UV_EHIP);
     if (!build_csc(m, n, nnz, h->rp, h->ci, h->va, h->cp, h->ri, h->vc, cnt, bsum, st)) return fail(UV_EHIP);
-    if (hipMemsetAsync(cnt, 0, 4 * (size_t)n, st) != hipSuccess) return fail(UV_EHIP);
-    k_lit_kcol<<<blocks_for(m, kWG), kWG, 0, st>>>(m, h->rp, h->ci, h->cp, cnt, h->kcol);
-    k_lit_sort<<<blocks_for(n, kWG), kWG, 0, st>>>(n, h->cp, h->kcol);
+    k_lit_kcol<<<blocks_for(n, kWG), kWG, 0, st>>>(n, h->cp, h->ri, h->rp, h->ci, h->kcol);
     k_row_factor<double><<<blocks_for(m, kWG), kWG, 0, st>>>(m, h->rp, h->va, h->fu);
     for (void *p : {(void *)h->x, (void *)h->z, (void *)h->delta})
         if (hipMemsetAsync(p, 0, 8 * (size_t)n, st) != hipSuccess) return fail(UV_EHIP);
