@@ -107,7 +107,16 @@ typedef struct {
     int32_t slabs_row;    /* XCD slabs of x in the A x pass: 0 = automatic
                              (about 2 MiB of x per slab), 1 = none, 2, 4, 8 */
     int32_t slabs_col;    /* XCD slabs of u in the A'u pass (same values) */
+    int32_t criterion;    /* UV_CRIT_KKT or UV_CRIT_INF (see uv_residuals) */
+    double eps_abs;       /* absolute tolerance of UV_CRIT_INF */
 } uv_opts;
+
+/* Stopping tests (Section V): UV_CRIT_KKT stops when kkt <= eps_kkt (the
+ * SCS-form relative residuals of Section V-B); UV_CRIT_INF stops when
+ * prim_inf <= eps_abs + eps_kkt * scale_p and dual_inf <= eps_abs +
+ * eps_kkt * scale_d (the infinity-norm test of Section V-A1). */
+#define UV_CRIT_KKT 0
+#define UV_CRIT_INF 1
 
 /* Residuals at the last check, evaluated at (z, lambda, delta), all FP64
  * (the SCS-form test of Section V-B, with the dual residual taken for
@@ -121,6 +130,10 @@ typedef struct {
     double r_prim, r_dual, r_gap, kkt;
     double pobj, dobj;
     double res_ax_b;
+    double prim_inf;      /* ||A z - b||_inf */
+    double dual_inf;      /* ||A'lambda + c - delta||_inf */
+    double scale_p;       /* max(||A z||_inf, ||b||_inf) */
+    double scale_d;       /* max(||A'lambda||_inf, ||c||_inf) */
     int64_t iter;         /* iterations done when these were evaluated */
     int32_t status;       /* UV_STATUS_* */
 } uv_residuals;
@@ -214,7 +227,9 @@ int batch_create(int32_t count, const uv_csr *A, const double *const *b,
  * be NULL) receives the number still running afterwards. */
 int batch_iterate(uv_batch *h, int64_t k, int32_t *n_active);
 
-/* Residuals / status of instance i at its last check (see uv_residuals). */
+/* Residuals / status of instance i at its last check (see uv_residuals;
+ * the infinity-norm fields are not evaluated by the batched solver and read
+ * 0). */
 int batch_residuals(uv_batch *h, int32_t i, uv_residuals *r);
 
 /* Iterate of instance i into caller-owned host buffers (any may be NULL):
@@ -280,7 +295,8 @@ int family_set_start_predicted(uv_family *h, const float *xl_dev, int64_t ld);
 /* Up to k more iterations; *n_active = instances still running. */
 int family_iterate(uv_family *h, int64_t k, int32_t *n_active);
 
-/* Residuals of the nb current instances into r[0..nb-1]. */
+/* Residuals of the nb current instances into r[0..nb-1] (infinity-norm
+ * fields not evaluated: 0). */
 int family_residuals(uv_family *h, uv_residuals *r);
 
 /* Iterates of the nb instances into host buffers (instance-major; any may

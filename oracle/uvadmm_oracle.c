@@ -404,6 +404,10 @@ static double serial_sum(const double *v, int64_t len)
  *                                       so it enters with the opposite sign)
  *   out[6] ||A x - b||_2   (the printed primal residual, at x)
  *   out[7] ||x - z||_2
+ *   out[8] ||A z - b||_inf,  out[9] ||A'lambda + c - delta||_inf,
+ *   out[10] max(||A z||_inf, ||b||_inf), out[11] max(||A'lambda||_inf, ||c||_inf)
+ *          (the infinity-norm termination test of Section V-A1, eq.
+ *          stopcri_osqp, with the same readings: at z, delta subtracted)
  * Readings: the printed dual residual ||A'lambda + c|| is the one for free x;
  * with x in K the stationarity condition of the Lagrangian (eq. lll) in x is
  * c + A'lambda - delta = 0 with delta in the dual cone, so delta is
@@ -415,11 +419,14 @@ void orc_residuals(orc_t *h, double *out)
     const int32_t m = h->m, n = h->n;
     double *rm = h->wrk_m, *rn = h->wrk_n;
 
+    double *azv = (double *)xcalloc((size_t)m, sizeof(double));
+    double *atlv = (double *)xcalloc((size_t)n, sizeof(double));
     #pragma omp parallel for schedule(static) if (m >= ORC_PAR_MIN)
     for (int32_t i = 0; i < m; ++i) {
         double az = 0.0;
         for (int64_t k = h->row_ptr[i]; k < h->row_ptr[i + 1]; ++k) az += h->ak[k] * h->z[h->ck[k]];
         rm[i] = (az - h->b[i]) * (az - h->b[i]);
+        azv[i] = az;
     }
     double rp2 = serial_sum(rm, m);
     #pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
@@ -431,8 +438,22 @@ void orc_residuals(orc_t *h, double *out)
         }
         double r = atl + h->c[j] - h->delta[j];
         rn[j] = r * r;
+        atlv[j] = atl;
     }
     double rd2 = serial_sum(rn, n);
+    double pinf = 0.0, dinf = 0.0, azinf = 0.0, atlinf = 0.0, binf = 0.0, cinf = 0.0;
+    for (int32_t i = 0; i < m; ++i) {
+        pinf = fmax(pinf, fabs(azv[i] - h->b[i]));
+        azinf = fmax(azinf, fabs(azv[i]));
+        binf = fmax(binf, fabs(h->b[i]));
+    }
+    for (int32_t j = 0; j < n; ++j) {
+        dinf = fmax(dinf, fabs(atlv[j] + h->c[j] - h->delta[j]));
+        atlinf = fmax(atlinf, fabs(atlv[j]));
+        cinf = fmax(cinf, fabs(h->c[j]));
+    }
+    free(azv);
+    free(atlv);
     double bb = 0.0, cc = 0.0, cz = 0.0, bl = 0.0;
     for (int32_t i = 0; i < m; ++i) { bb += h->b[i] * h->b[i]; bl += h->b[i] * h->lambda[i]; }
     for (int32_t j = 0; j < n; ++j) { cc += h->c[j] * h->c[j]; cz += h->c[j] * h->z[j]; }
@@ -455,13 +476,17 @@ void orc_residuals(orc_t *h, double *out)
     out[5] = -bl;
     out[6] = sqrt(rpx2);
     out[7] = sqrt(xz2);
+    out[8] = pinf;
+    out[9] = dinf;
+    out[10] = fmax(azinf, binf);
+    out[11] = fmax(atlinf, cinf);
 }
 
 /* Runs until kkt <= eps at a check (every check_every iterations) or until
  * max_iter iterations; returns the iteration count at the stop. */
 int64_t orc_solve(orc_t *h, double eps, int64_t check_every, int64_t max_iter, double *res_out)
 {
-    double r[8];
+    double r[12];
     if (check_every < 1) check_every = 1;
     while (h->iter < max_iter) {
         int64_t k = check_every;

@@ -46,4 +46,35 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double *out, int strid
     }
 }
 
+// Workgroup reduction of KS sums and KM maxima (deterministic); thread 0
+// writes sum k to out[k * stride] and maximum k to out[(KS + k) * stride].
+template <int KS, int KM>
+__device__ __forceinline__ void block_sum_max(double (&vs)[KS], double (&vm)[KM], double *out, int stride)
+{
+    __shared__ double s[KS + KM][kWG / kWave];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) vs[k] = group_sum<kWave>(vs[k]);
+#pragma unroll
+    for (int k = 0; k < KM; ++k)
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) vm[k] = fmax(vm[k], __shfl_xor(vm[k], off, kWave));
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < KS; ++k) s[k][w] = vs[k];
+#pragma unroll
+        for (int k = 0; k < KM; ++k) s[KS + k][w] = vm[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < KS + KM; ++k) {
+            double t = s[k][0];
+#pragma unroll
+            for (int i = 1; i < kWG / kWave; ++i) t = k < KS ? t + s[k][i] : fmax(t, s[k][i]);
+            out[k * stride] = t;
+        }
+    }
+}
+
 }  // namespace uv

@@ -41,6 +41,8 @@ namespace {
 struct DevStatus {
     double r_prim, r_dual, r_gap, kkt, pobj, dobj, res_ax_b;
     double bnorm2, cnorm2;
+    double prim_inf, dual_inf, scale_p, scale_d;  // infinity-norm measures
+    double binf, cinf;
     long long iter;        // iterations done
     long long check_iter;  // iteration count at the last residual evaluation
     int done;              // 1 = stop: every sweep kernel returns at once
@@ -53,12 +55,23 @@ constexpr int kSocTile = 256;  // columns per SOC tile when cones are small
 __global__ void __launch_bounds__(kWG)
 k_norms(int m, const double *__restrict__ b, int n, const double *__restrict__ c, DevStatus *st)
 {
-    double v[2] = {0.0, 0.0};
-    for (int i = threadIdx.x; i < m; i += kWG) v[0] += b[i] * b[i];
-    for (int j = threadIdx.x; j < n; j += kWG) v[1] += c[j] * c[j];
-    double out[2];
-    uv::block_sum<2>(v, out, 1);
-    if (threadIdx.x == 0) { st->bnorm2 = out[0]; st->cnorm2 = out[1]; }
+    double v[2] = {0.0, 0.0}, w[2] = {0.0, 0.0};
+    for (int i = threadIdx.x; i < m; i += kWG) {
+        v[0] += b[i] * b[i];
+        w[0] = fmax(w[0], fabs(b[i]));
+    }
+    for (int j = threadIdx.x; j < n; j += kWG) {
+        v[1] += c[j] * c[j];
+        w[1] = fmax(w[1], fabs(c[j]));
+    }
+    double out[4];
+    uv::block_sum_max<2, 2>(v, w, out, 1);
+    if (threadIdx.x == 0) {
+        st->bnorm2 = out[0];
+        st->cnorm2 = out[1];
+        st->binf = out[2];
+        st->cinf = out[3];
+    }
 }
 
 // Start: u = -lambda/mu (see the header comment), iteration state reset.
@@ -127,7 +140,7 @@ k_row(int m, const int *__restrict__ rp, const int *__restrict__ ci, const T *__
     if (MODE != 2 && st->done) return;
     const int lane = threadIdx.x & (L - 1);
     const int row = blockIdx.x * (kWG / L) + threadIdx.x / L;
-    double acc[3] = {0.0, 0.0, 0.0};
+    double acc[3] = {0.0, 0.0, 0.0}, mx[2] = {0.0, 0.0};
     if (row < m) {
         // epilogue operands first: independent of the gathers below
         const T bi = b[row], fi = fu[row];
@@ -146,11 +159,13 @@ k_row(int m, const int *__restrict__ rp, const int *__restrict__ ci, const T *__
                 acc[0] = rz * rz;
                 acc[1] = (double)bi * li;
                 acc[2] = rx * rx;
+                mx[0] = fabs(rz);
+                mx[1] = fabs((double)qz);
             }
         }
     }
     if (MODE != 2 && blockIdx.x == 0 && threadIdx.x == 0) st->iter += 1;
-    if (MODE == 1) uv::block_sum<3>(acc, part + blockIdx.x, pstride);
+    if (MODE == 1) uv::block_sum_max<3, 2>(acc, mx, part + blockIdx.x, pstride);
 }
 
 // Residual-only row pass with FP64 values of A (same partial layout as the
@@ -163,7 +178,7 @@ k_res_row(int m, const int *__restrict__ rp, const int *__restrict__ ci, const d
 {
     const int lane = threadIdx.x & (L - 1);
     const int row = blockIdx.x * (kWG / L) + threadIdx.x / L;
-    double acc[3] = {0.0, 0.0, 0.0};
+    double acc[3] = {0.0, 0.0, 0.0}, mx[2] = {0.0, 0.0};
     if (row < m) {
         const double bi = b[row], li = lam[row];
         const int beg = rp[row], end = rp[row + 1];
@@ -179,9 +194,11 @@ k_res_row(int m, const int *__restrict__ rp, const int *__restrict__ ci, const d
             acc[0] = (qz - bi) * (qz - bi);
             acc[1] = bi * li;
             acc[2] = (qx - bi) * (qx - bi);
+            mx[0] = fabs(qz - bi);
+            mx[1] = fabs(qz);
         }
     }
-    uv::block_sum<3>(acc, part + blockIdx.x, pstride);
+    uv::block_sum_max<3, 2>(acc, mx, part + blockIdx.x, pstride);
 }
 
 // x-step (Block 1) for one column from p = N x + A'u, and the projected
@@ -338,7 +355,7 @@ k_row_combine(int m, const T *__restrict__ P, const T *__restrict__ b, const T *
 {
     if (MODE != 2 && st->done) return;
     const int row = blockIdx.x * kWG + threadIdx.x;
-    double acc[3] = {0.0, 0.0, 0.0};
+    double acc[3] = {0.0, 0.0, 0.0}, mx[2] = {0.0, 0.0};
     if (row < m) {
         const T bi = b[row], fi = fu[row];
         const double l0 = lam[row];
@@ -357,10 +374,12 @@ k_row_combine(int m, const T *__restrict__ P, const T *__restrict__ b, const T *
             acc[0] = rz * rz;
             acc[1] = (double)bi * li;
             acc[2] = rx * rx;
+            mx[0] = fabs(rz);
+            mx[1] = fabs((double)qz);
         }
     }
     if (MODE != 2 && blockIdx.x == 0 && threadIdx.x == 0) st->iter += 1;
-    if (MODE == 1) uv::block_sum<3>(acc, part + blockIdx.x, pstride);
+    if (MODE == 1) uv::block_sum_max<3, 2>(acc, mx, part + blockIdx.x, pstride);
 }
 
 template <typename T, int L, int E, int S>
@@ -387,7 +406,7 @@ k_res_col(int n, const int *__restrict__ cp, const int *__restrict__ ri, const d
 {
     const int lane = threadIdx.x & (L - 1);
     const int col = blockIdx.x * (kWG / L) + threadIdx.x / L;
-    double acc[2] = {0.0, 0.0};
+    double acc[2] = {0.0, 0.0}, mx[2] = {0.0, 0.0};
     if (col < n) {
         const double cj = c[col], dj = delta[col], zj = (double)z[col];
         const double a = seg_dot<L, 4>(cp[col], cp[col + 1], lane, ri, vc, lam);
@@ -395,50 +414,61 @@ k_res_col(int n, const int *__restrict__ cp, const int *__restrict__ ri, const d
             const double r = a + cj - dj;
             acc[0] = r * r;
             acc[1] = cj * zj;
+            mx[0] = fabs(r);
+            mx[1] = fabs(a);
         }
     }
-    uv::block_sum<2>(acc, part + blockIdx.x, pstride);
+    uv::block_sum_max<2, 2>(acc, mx, part + blockIdx.x, pstride);
 }
 
 // Adds the partials in a fixed order (eight independent loads in flight
 // per thread), forms the residuals and decides whether to stop.  Partials
-// are stored component-major: prow[k * nrow + block].
+// are stored component-major: prow[k * nrow + block], rows: sums of
+// (Az-b)^2, b'lambda, (Ax-b)^2, then maxima of |Az-b|, |Az|; columns: sums of
+// (A'lambda+c-delta)^2, c'z, then maxima of |A'lambda+c-delta|, |A'lambda|.
+// crit 0: relative KKT (SCS form) <= eps; crit 1: infinity-norm test
+// ||Az-b|| <= eps_abs + eps max(||Az||, ||b||) and
+// ||A'lambda+c-delta|| <= eps_abs + eps max(||A'lambda||, ||c||).
 __global__ void __launch_bounds__(kWG)
 k_finalize(int nrow, const double *__restrict__ prow, int ncol, const double *__restrict__ pcol,
-           double eps, DevStatus *st)
+           double eps, double eps_abs, int crit, DevStatus *st)
 {
-    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, w[4] = {0.0, 0.0, 0.0, 0.0};
     for (int base = threadIdx.x; base < nrow; base += 8 * kWG) {
-        double a[3][8];
+        double a[5][8];
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const int i = base + r * kWG;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) a[k][r] = i < nrow ? prow[k * nrow + i] : 0.0;
+            for (int k = 0; k < 5; ++k) a[k][r] = i < nrow ? prow[k * nrow + i] : 0.0;
         }
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             v[0] += a[0][r];
             v[1] += a[1][r];
             v[2] += a[2][r];
+            w[0] = fmax(w[0], a[3][r]);
+            w[1] = fmax(w[1], a[4][r]);
         }
     }
     for (int base = threadIdx.x; base < ncol; base += 8 * kWG) {
-        double a[2][8];
+        double a[4][8];
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const int i = base + r * kWG;
 #pragma unroll
-            for (int k = 0; k < 2; ++k) a[k][r] = i < ncol ? pcol[k * ncol + i] : 0.0;
+            for (int k = 0; k < 4; ++k) a[k][r] = i < ncol ? pcol[k * ncol + i] : 0.0;
         }
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             v[3] += a[0][r];
             v[4] += a[1][r];
+            w[2] = fmax(w[2], a[2][r]);
+            w[3] = fmax(w[3], a[3][r]);
         }
     }
-    double s[5];
-    uv::block_sum<5>(v, s, 1);
+    double s[9];
+    uv::block_sum_max<5, 4>(v, w, s, 1);
     if (threadIdx.x != 0) return;
     const double rp = sqrt(s[0]) / (1.0 + sqrt(st->bnorm2));
     const double rd = sqrt(s[3]) / (1.0 + sqrt(st->cnorm2));
@@ -452,11 +482,17 @@ k_finalize(int nrow, const double *__restrict__ prow, int ncol, const double *__
     st->pobj = cz;
     st->dobj = -bl;
     st->res_ax_b = sqrt(s[2]);
+    st->prim_inf = s[5];
+    st->dual_inf = s[7];
+    st->scale_p = fmax(s[6], st->binf);
+    st->scale_d = fmax(s[8], st->cinf);
     st->check_iter = st->iter;
+    const bool conv = crit == 1 ? (s[5] <= eps_abs + eps * st->scale_p && s[7] <= eps_abs + eps * st->scale_d)
+                                : kkt <= eps;
     if (!isfinite(kkt)) {
         st->status = UV_STATUS_NUMERIC;
         st->done = 1;
-    } else if (kkt <= eps) {
+    } else if (conv) {
         st->status = UV_STATUS_CONVERGED;
         st->done = 1;
     }
@@ -718,7 +754,8 @@ void launch_residuals(uv_solver *s, hipStream_t st, bool row_done)
     if (!row_done) dispatch_le_res<ResRowLaunch>(s, st, s->L_row);
     dispatch_le_res<ResColLaunch>(s, st, s->L_col);
     const int nrow = row_done ? s->nblk_row_fused : s->nblk_row;
-    k_finalize<<<1, kWG, 0, st>>>(nrow, s->part_row, s->nblk_rescol, s->part_col, s->o.eps_kkt, s->st);
+    k_finalize<<<1, kWG, 0, st>>>(nrow, s->part_row, s->nblk_rescol, s->part_col, s->o.eps_kkt, s->o.eps_abs,
+                                  s->o.criterion, s->st);
 }
 
 // One iteration; with check, the residuals of the new iterate follow it.
@@ -754,6 +791,7 @@ int validate(const uv_csr *A, const double *b, const double *c, const uv_cones *
     if (!(o->mu > 0.0) || !std::isfinite(o->mu)) return UV_EINVAL;
     if (o->precision != UV_FP64 && o->precision != UV_MIXED) return UV_EINVAL;
     if (o->check_every < 1 || !(o->eps_kkt >= 0.0) || o->max_iter < 0) return UV_EINVAL;
+    if ((o->criterion != 0 && o->criterion != 1) || !(o->eps_abs >= 0.0)) return UV_EINVAL;
     if (!lanes_ok(o->lanes_row) || !lanes_ok(o->lanes_col)) return UV_EINVAL;
     if (!unroll_ok(o->unroll_row) || !unroll_ok(o->unroll_col)) return UV_EINVAL;
     if (!slabs_ok(o->slabs_row) || !slabs_ok(o->slabs_col)) return UV_EINVAL;
@@ -825,8 +863,8 @@ int setup(uv_solver *s, const uv_csr *A, const double *b, const double *c, const
     s->nblk_row = (int)blocks_for(m, kWG / s->L_row);
     s->nblk_row_fused = s->S_row > 1 ? (int)blocks_for(m, kWG) : s->nblk_row;
     s->nblk_rescol = (int)blocks_for(n, kWG / s->L_col);
-    s->part_row = dalloc<double>(s, 3 * (size_t)std::max(s->nblk_row, s->nblk_row_fused));
-    s->part_col = dalloc<double>(s, 2 * (size_t)s->nblk_rescol);
+    s->part_row = dalloc<double>(s, 5 * (size_t)std::max(s->nblk_row, s->nblk_row_fused));
+    s->part_col = dalloc<double>(s, 4 * (size_t)s->nblk_rescol);
     s->st = dalloc<DevStatus>(s, 1);
     const size_t ncnt = std::max({(size_t)n, (size_t)s->S_row * m, (size_t)s->S_col * n});
     int *cnt = dalloc<int>(s, ncnt);
@@ -952,6 +990,8 @@ void uv_default_opts(uv_opts *o)
     o->unroll_col = 0;
     o->slabs_row = 0;
     o->slabs_col = 0;
+    o->criterion = 0;
+    o->eps_abs = 0.0;
 }
 
 const char *solver_strerror(int code)
@@ -1134,6 +1174,10 @@ int solver_residuals(uv_solver *s, uv_residuals *r)
     r->pobj = h->pobj;
     r->dobj = h->dobj;
     r->res_ax_b = h->res_ax_b;
+    r->prim_inf = h->prim_inf;
+    r->dual_inf = h->dual_inf;
+    r->scale_p = h->scale_p;
+    r->scale_d = h->scale_d;
     r->iter = h->iter;
     r->status = h->status;
     return UV_OK;

@@ -165,6 +165,48 @@ def socp_instance(n_cones: int, k: int, seed: int, size_lo: int = 3,
     }
 
 
+def paper_instance(m: int, n: int, density: float, cone: str, seed: int) -> dict:
+    """The experiments' own generator (Section V, "Problem instances"): A with
+    a fraction `density` of nonzeros at uniformly random positions, values
+    N(0,1); b = A proj_K(xdot) with xdot ~ N(0, I); c ~ N(0, I); K the
+    orthant ("lp") or a product of size-4 Lorentz cones ("socp", n a multiple
+    of 4).  Feasible by construction; unlike the families above it is not
+    guaranteed to be bounded (c is unrelated to A)."""
+    rng = np.random.default_rng(seed)
+    target = max(int(round(density * m * n)), 1)
+    pos = np.unique(rng.integers(0, m * n, size=target, dtype=np.int64))
+    while pos.size < target:
+        more = rng.integers(0, m * n, size=target - pos.size, dtype=np.int64)
+        pos = np.unique(np.concatenate([pos, more]))
+    r, cidx = pos // n, pos % n
+    val = rng.standard_normal(pos.size)
+    row_ptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(np.bincount(r, minlength=m), out=row_ptr[1:])
+    xdot = rng.standard_normal(n)
+    if cone == "lp":
+        n_orth, sizes = n, np.zeros(0, dtype=np.int32)
+        xk = np.maximum(xdot, 0.0)
+    elif cone == "socp":
+        if n % 4:
+            raise ValueError("n must be a multiple of 4 for (K_4)^(n/4)")
+        n_orth, sizes = 0, np.full(n // 4, 4, dtype=np.int32)
+        w = xdot.reshape(-1, 4)
+        t, u = w[:, 0], w[:, 1:]
+        a = np.linalg.norm(u, axis=1)
+        xk = np.where((a <= -t)[:, None], 0.0,
+                      np.where((a <= t)[:, None], w,
+                               np.concatenate([((t + a) / 2)[:, None],
+                                               u * ((1 + t / np.where(a > 0, a, 1)) / 2)[:, None]], axis=1)))
+        xk = xk.reshape(-1)
+    else:
+        raise ValueError("cone must be 'lp' or 'socp'")
+    b = np.bincount(r, weights=val * xk[cidx], minlength=m)
+    c = rng.standard_normal(n)
+    return {"m": m, "n": n, "nnz": int(pos.size), "row_ptr": row_ptr, "col_idx": cidx.astype(np.int32),
+            "val": val, "b": b, "c": c, "n_orth": n_orth, "soc_sizes": sizes, "x_feasible": xk,
+            "seed": seed}
+
+
 def batch_lp_sizes(count: int, m_lo: int = 50, m_hi: int = 5000,
                    seed_base: int = 3_000_000) -> np.ndarray:
     """m of instance i, log-uniform in [m_lo, m_hi], drawn from seed_base + i."""

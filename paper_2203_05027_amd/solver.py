@@ -37,14 +37,17 @@ class UvOpts(ctypes.Structure):
                 ("lanes_row", ctypes.c_int32), ("lanes_col", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("unroll_row", ctypes.c_int32),
                 ("unroll_col", ctypes.c_int32), ("slabs_row", ctypes.c_int32),
-                ("slabs_col", ctypes.c_int32)]
+                ("slabs_col", ctypes.c_int32), ("criterion", ctypes.c_int32),
+                ("eps_abs", ctypes.c_double)]
 
 
 class UvResiduals(ctypes.Structure):
     _fields_ = [("r_prim", ctypes.c_double), ("r_dual", ctypes.c_double),
                 ("r_gap", ctypes.c_double), ("kkt", ctypes.c_double),
                 ("pobj", ctypes.c_double), ("dobj", ctypes.c_double),
-                ("res_ax_b", ctypes.c_double), ("iter", ctypes.c_int64),
+                ("res_ax_b", ctypes.c_double), ("prim_inf", ctypes.c_double),
+                ("dual_inf", ctypes.c_double), ("scale_p", ctypes.c_double),
+                ("scale_d", ctypes.c_double), ("iter", ctypes.c_int64),
                 ("status", ctypes.c_int32)]
 
 
@@ -137,7 +140,7 @@ class Solver:
     def __init__(self, m, n, row_ptr, col_idx, val, b, c, n_orth, soc_sizes=(), *,
                  mu=1.0, precision="fp64", check_every=10, eps=1e-4, max_iter=0,
                  lanes_row=0, lanes_col=0, unroll_row=0, unroll_col=0, slabs_row=0, slabs_col=0,
-                 use_graph=True, stream=None):
+                 criterion="kkt", eps_abs=0.0, use_graph=True, stream=None):
         L = lib()
         self.m, self.n = int(m), int(n)
         rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
@@ -156,6 +159,8 @@ class Solver:
         o.lanes_row, o.lanes_col = int(lanes_row), int(lanes_col)
         o.unroll_row, o.unroll_col = int(unroll_row), int(unroll_col)
         o.slabs_row, o.slabs_col = int(slabs_row), int(slabs_col)
+        o.criterion = {"kkt": 0, "inf": 1}[criterion]
+        o.eps_abs = float(eps_abs)
         o.use_graph = 1 if use_graph else 0
         self.precision = precision
         self.nnz = csr.nnz

@@ -55,9 +55,29 @@ def assert_parity(g, o, tol=TOL64):
 def test_small_lp_200_iterations():
     g, o, gr, orr = run_pair(I.config_instance("lp_small"), 200)
     assert_parity(g, o)
-    for k in ("r_prim", "r_dual", "r_gap", "kkt", "pobj", "dobj", "res_ax_b"):
+    for k in ("r_prim", "r_dual", "r_gap", "kkt", "pobj", "dobj", "res_ax_b", "prim_inf", "dual_inf",
+              "scale_p", "scale_d"):
         assert abs(gr[k] - orr[k]) <= 1e-9 * max(abs(orr[k]), 1e-12), k
     assert gr["iter"] == 200
+
+
+def test_infinity_norm_criterion_stops_like_oracle():
+    """The infinity-norm stopping test (eps_abs 1e-4, eps_rel 1e-3) stops at
+    the same check as the same test evaluated on the oracle's iterates."""
+    inst = I.config_instance("lp_small")
+    orc = oracle.Oracle.from_instance(inst)
+    it = 0
+    while it < 60_000:
+        orc.iterate(10)
+        it += 10
+        r = orc.residuals()
+        if (r["prim_inf"] <= 1e-4 + 1e-3 * r["scale_p"] and r["dual_inf"] <= 1e-4 + 1e-3 * r["scale_d"]):
+            break
+    with Solver.from_instance(inst, eps=1e-3, eps_abs=1e-4, criterion="inf") as s:
+        assert s.iterate(60_000)
+        g = s.residuals()
+    say(f"inf criterion: gpu {g['iter']} oracle {it}")
+    assert g["status"] == "converged" and g["iter"] == it
 
 
 @pytest.mark.parametrize("lanes,unroll", [((1, 1), (1, 8)), ((2, 16), (8, 1)), ((64, 64), (2, 4)),

@@ -286,6 +286,13 @@ def test_fixed_point_at_known_optimum(oracle_mod, mu):
         np.testing.assert_allclose(s1[k], s0[k], atol=1e-12 * (1 + np.abs(s0[k]).max()))
     r = orc.residuals()
     assert r["kkt"] < 1e-13
+    # infinity-norm measures at the optimum: both residuals vanish, and the
+    # scales are the larger of the data and product norms
+    assert r["prim_inf"] < 1e-12 and r["dual_inf"] < 1e-12
+    A = _dense(inst)
+    assert r["scale_p"] == pytest.approx(np.abs(inst["b"]).max(), rel=1e-12)
+    atl = A.T @ (-inst["y0"])
+    assert r["scale_d"] == pytest.approx(max(np.abs(atl).max(), np.abs(inst["c"]).max()), rel=1e-12)
 
 
 # --------------------------------------------------------------------------
@@ -376,6 +383,21 @@ def test_socp_generator_bracket(oracle_mod):
     assert inst["d_lower"] - 1e-6 <= r["pobj"] <= inst["p_upper"] + 1e-6
 
 
+def test_infinity_norm_measures_on_a_random_state(oracle_mod):
+    """prim_inf / dual_inf against dense products of a random state."""
+    inst = I.socp_instance(10, 4, seed=19)
+    rng = np.random.default_rng(8)
+    orc = oracle_mod.Oracle.from_instance(inst)
+    x, z, d = (rng.standard_normal(inst["n"]) for _ in range(3))
+    lam = rng.standard_normal(inst["m"])
+    orc.set_start(x, z, d, lam)
+    r = orc.residuals()
+    A = _dense(inst)
+    assert r["prim_inf"] == pytest.approx(np.abs(A @ z - inst["b"]).max(), rel=1e-12)
+    assert r["dual_inf"] == pytest.approx(np.abs(A.T @ lam + inst["c"] - d).max(), rel=1e-12)
+    assert r["scale_p"] == pytest.approx(max(np.abs(A @ z).max(), np.abs(inst["b"]).max()), rel=1e-12)
+
+
 def test_small_lp_reaches_1e4(oracle_mod):
     inst = I.config_instance("lp_small")
     orc = oracle_mod.Oracle.from_instance(inst, mu=1.0)
@@ -403,3 +425,15 @@ def test_threads_do_not_change_results(oracle_mod):
         outs.append(subprocess.run([sys.executable, "-c", code], env=env, check=True,
                                    capture_output=True, text=True).stdout)
     assert outs[0] == outs[1]
+
+
+def test_paper_generator_is_feasible(oracle_mod):
+    """The experiments' own generator: b = A proj_K(xdot), so proj_K(xdot) is
+    feasible (in K and A x = b); density as requested."""
+    for cone in ("lp", "socp"):
+        inst = I.paper_instance(40, 80, 0.05, cone, seed=3)
+        A = _dense(inst)
+        x = inst["x_feasible"]
+        assert abs(inst["nnz"] / (40 * 80) - 0.05) < 1e-3
+        np.testing.assert_allclose(A @ x, inst["b"], atol=1e-12)
+        np.testing.assert_allclose(oracle_mod.project(x, inst["n_orth"], inst["soc_sizes"]), x, atol=1e-12)
