@@ -27,6 +27,38 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_lp_large_fp64.txt")
+
+
+def sources_digest() -> str:
+    """Digest of the kernel sources; a traffic measurement is only used while
+    the kernels are the ones it was taken on."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2203_05027_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(pass_name):
+    """HBM bytes per launch of a pass from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
+    when there is none or the kernels changed since it was taken."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("sources") != sources_digest():
+            return None
+        return float(kv[f"{pass_name}_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -244,6 +276,8 @@ def main():
     ap.add_argument("--train-eps", type=float, default=1e-3, help="parametric: tolerance of the training solves")
     ap.add_argument("--train-cap", type=int, default=20_000, help="parametric: iteration cap of training solves")
     ap.add_argument("--plain", type=int, default=8, help="members solved by the plain single-problem solver")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run a plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this solver runs on one GPU; multi-GPU runs are not part of this "
@@ -254,6 +288,15 @@ def main():
     from paper_2203_05027_amd import instances as I
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calib_copy_mib:
+        nel = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: 3 x {args.calib_copy_mib} MiB")
+        del src, dst
     if args.workload == "lp_parametric":
         return bench_parametric(args)
     if args.workload == "lp_batched":
@@ -328,9 +371,10 @@ def main():
         "p_star": inst.get("p_star"),
         "sweep_GBs": sweep_gbs,
         "kernels_ms": {"col": main_r["ms_col"], "row": main_r["ms_row"]},
-        "roofline": {"bound": "hbm", "kernel": f"k_col_orth" if dom == "col" else "k_row",
+        "roofline": {"bound": "hbm", "kernel": f"{dom} pass ({'A^T u, x-step, projection, delta' if dom == 'col' else 'A x, lambda, u'})",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
+                     "alg_bytes_per_launch": kern[dom][0], "ms_per_launch": kern[dom][1]},
         "mixed": extra,
         "batched": batched,
         "cpu_baseline": cpu,
