@@ -558,9 +558,10 @@ T *dalloc(uv_solver *s, size_t count)
 
 int pick_lanes(double avg)
 {
-    // about four entries per lane, whole power-of-two groups
+    // about two entries per lane (with two gathers in flight per lane, one
+    // pass covers a typical row), whole power-of-two groups
     int L = 1;
-    while (L < 64 && L * 4 < avg) L <<= 1;
+    while (L < 64 && L * 2 < avg) L <<= 1;
     return L;
 }
 
@@ -571,11 +572,12 @@ bool unroll_ok(int E) { return E == 0 || E == 1 || E == 2 || E == 4 || E == 8; }
 bool slabs_ok(int S) { return S == 0 || S == 1 || S == 2 || S == 4 || S == 8; }
 
 // Slabs for a gathered vector of `bytes`: none up to 2 MiB, else enough
-// power-of-two slabs (at most one per XCD) for about 2 MiB each.
+// power-of-two slabs for about 2 MiB each, at most 4 (measured on the 1e6 x
+// 2e6 LP: 8 slabs of x gain nothing over 4 and add partial traffic).
 int pick_slabs(size_t bytes)
 {
     int S = 1;
-    while (S < 8 && bytes > (size_t)S * (2u << 20)) S <<= 1;
+    while (S < 4 && bytes > (size_t)S * (2u << 20)) S <<= 1;
     return S;
 }
 
@@ -1040,10 +1042,6 @@ int solver_create(const uv_csr *A, const double *b, const double *c, const uv_co
     s->n_orth = K->n_orthant;
     s->n_soc = K->n_soc;
     s->o = o;
-    s->L_row = o.lanes_row ? o.lanes_row : pick_lanes((double)A->nnz / A->m);
-    s->L_col = o.lanes_col ? o.lanes_col : pick_lanes((double)A->nnz / A->n);
-    s->E_row = o.unroll_row ? o.unroll_row : 4;
-    s->E_col = o.unroll_col ? o.unroll_col : 4;
     {
         const size_t ts = o.precision == UV_MIXED ? 4 : 8;
         s->S_row = o.slabs_row ? o.slabs_row : pick_slabs(ts * (size_t)A->n);
@@ -1052,6 +1050,11 @@ int solver_create(const uv_csr *A, const double *b, const double *c, const uv_co
         while (s->S_row > 1 && (s->S_row > A->n || (int64_t)s->S_row * A->m >= INT32_MAX)) s->S_row >>= 1;
         while (s->S_col > 1 && (s->S_col > A->m || (int64_t)s->S_col * A->n >= INT32_MAX)) s->S_col >>= 1;
     }
+    // lanes from the entries a lane group actually sums (a slab holds 1/S of a row)
+    s->L_row = o.lanes_row ? o.lanes_row : pick_lanes((double)A->nnz / A->m / s->S_row);
+    s->L_col = o.lanes_col ? o.lanes_col : pick_lanes((double)A->nnz / A->n / s->S_col);
+    s->E_row = o.unroll_row ? o.unroll_row : 2;
+    s->E_col = o.unroll_col ? o.unroll_col : 2;
     rc = setup(s, A, b, c, K);
     if (rc == UV_OK) rc = solver_set_start(s, nullptr, nullptr, nullptr, nullptr);
     if (rc == UV_OK && s->o.use_graph) rc = build_graph(s);
