@@ -289,8 +289,11 @@ int family_set_start(uv_family *h, const double *x, const double *z,
 /* Start from predicted primal-dual points held on the DEVICE: row l of
  * xl_dev (FP32, row stride ld >= n + m) is [x (n) ; lambda (m)].  Sets
  * z = max(x, 0) and delta = max(c + A'lambda, 0) (the stationarity
- * condition c + A'lambda - delta = 0 projected on the dual cone). */
-int family_set_start_predicted(uv_family *h, const float *xl_dev, int64_t ld);
+ * condition c + A'lambda - delta = 0 projected on the dual cone).  parts:
+ * 1 = use the predicted x only (lambda = 0), 2 = lambda only (x = 0),
+ * 3 = both. */
+int family_set_start_predicted(uv_family *h, const float *xl_dev, int64_t ld,
+                               int32_t parts);
 
 /* Up to k more iterations; *n_active = instances still running. */
 int family_iterate(uv_family *h, int64_t k, int32_t *n_active);

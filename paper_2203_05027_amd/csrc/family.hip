@@ -592,16 +592,22 @@ int family_set_start(uv_family *h, const double *x, const double *z, const doubl
     return fam_sync(h);
 }
 
-int family_set_start_predicted(uv_family *h, const float *xl_dev, int64_t ld)
+int family_set_start_predicted(uv_family *h, const float *xl_dev, int64_t ld, int32_t parts)
 {
     // xl_dev: device, instance-major rows [x (n) ; lambda (m)] with row stride ld
-    if (!h || !xl_dev || h->nb < 1 || ld < (int64_t)h->n + h->m) return UV_EINVAL;
+    if (!h || !xl_dev || h->nb < 1 || ld < (int64_t)h->n + h->m || parts < 1 || parts > 3) return UV_EINVAL;
     hipStream_t st = h->stream;
     const int B = h->B, nb = h->nb;
     const size_t Bm = (size_t)B * h->m;
     // x then lambda: pack the rows into the staging buffer, then transpose
     // into the instance-fastest layout (instances >= nb get 0)
     for (int part = 0; part < 2; ++part) {
+        if (!(parts & (1 << part))) {  // this half of the prediction is not used: zero
+            const size_t ts = h->o.precision == UV_MIXED ? 4 : 8;
+            if (part == 0) UV_FTRY(hipMemsetAsync(h->X, 0, ts * (size_t)B * h->n, st));
+            else UV_FTRY(hipMemsetAsync(h->LAM, 0, 8 * (size_t)B * h->m, st));
+            continue;
+        }
         const int len = part == 0 ? h->n : h->m;
         const int off = part == 0 ? 0 : h->n;
         float *stg = (float *)h->stage;

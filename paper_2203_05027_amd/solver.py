@@ -385,7 +385,7 @@ def _bind_family(L):
     L.family_set_rhs.restype = ctypes.c_int
     L.family_set_start.argtypes = [P, P, P, P, P]
     L.family_set_start.restype = ctypes.c_int
-    L.family_set_start_predicted.argtypes = [P, P, i64]
+    L.family_set_start_predicted.argtypes = [P, P, i64, i32]
     L.family_set_start_predicted.restype = ctypes.c_int
     L.family_iterate.argtypes = [P, i64, ctypes.POINTER(i32)]
     L.family_iterate.restype = ctypes.c_int
@@ -467,9 +467,11 @@ class Family:
                 self._mat(lam, self.m))
         _check(lib().family_set_start(self._h, *[_ptr(a) for a in args]), "family_set_start")
 
-    def set_start_predicted(self, dev_ptr: int, ld: int):
-        """Start from a device FP32 matrix whose row l is [x ; lambda]."""
-        _check(lib().family_set_start_predicted(self._h, ctypes.c_void_p(dev_ptr), int(ld)),
+    def set_start_predicted(self, dev_ptr: int, ld: int, parts: str = "both"):
+        """Start from a device FP32 matrix whose row l is [x ; lambda];
+        parts: "primal", "dual" or "both" of the prediction are used."""
+        code = {"primal": 1, "dual": 2, "both": 3}[parts]
+        _check(lib().family_set_start_predicted(self._h, ctypes.c_void_p(dev_ptr), int(ld), code),
                "family_set_start_predicted")
 
     def iterate(self, k: int) -> int:

@@ -126,7 +126,7 @@ class WarmStart:
         return float(d.median())
 
     # 4. warm vs cold ---------------------------------------------------
-    def compare(self, thetas, eps=1e-4, max_iter=100_000):
+    def compare(self, thetas, eps=1e-4, max_iter=100_000, parts="both"):
         """Iterations and time to eps from cold and from learned starts for
         the same members; a warm start that fails to converge falls back to
         a cold solve (counted in its time and iterations)."""
@@ -155,7 +155,7 @@ class WarmStart:
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 Yhat = self.predict(th)
-                F.set_start_predicted(Yhat.data_ptr(), self.D)
+                F.set_start_predicted(Yhat.data_ptr(), self.D, parts)
                 torch.cuda.synchronize()
                 t_pred += time.perf_counter() - t0
                 while F.iterate(2000):

@@ -85,7 +85,7 @@ def test_warm_start_at_solution_is_converged(small_family):
         xl = np.concatenate([sol["z"], sol["lambda"]], axis=1).astype(np.float32)
         dev = torch.from_numpy(xl).cuda()
         F.set_rhs(b)
-        F.set_start_predicted(dev.data_ptr(), xl.shape[1])
+        F.set_start_predicted(dev.data_ptr(), xl.shape[1], "both")
         torch.cuda.synchronize()
         s0 = F.solution()
         np.testing.assert_allclose(s0["z"], np.maximum(xl[:, :fam.n], 0), rtol=1e-6, atol=1e-6)
