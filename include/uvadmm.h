@@ -109,6 +109,8 @@ typedef struct {
     int32_t slabs_col;    /* XCD slabs of u in the A'u pass (same values) */
     int32_t criterion;    /* UV_CRIT_KKT or UV_CRIT_INF (see uv_residuals) */
     double eps_abs;       /* absolute tolerance of UV_CRIT_INF */
+    int32_t slab_kernel;  /* slab passes: 0 = automatic (= 1), 1 = 64-segment
+                             chunks per wavefront, 2 = lane group per segment */
 } uv_opts;
 
 /* Stopping tests (Section V): UV_CRIT_KKT stops when kkt <= eps_kkt (the

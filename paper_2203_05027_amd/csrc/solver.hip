@@ -346,6 +346,68 @@ k_row_slab(int m, const int *__restrict__ srp, const int *__restrict__ sci, cons
     }
 }
 
+// Chunked segment sums for the slab passes: out[s * nseg + g] = sum over the
+// entries k of segment g in slab s of val[k] * vec[idx[k]].  A wavefront owns
+// 64 consecutive segments (one per lane for the final sum): it streams their
+// contiguous entries with coalesced loads, four 64-entry steps in flight per
+// round, parks the products in LDS, and each lane then adds its own
+// segment's products in entry order.  Unlike one lane group per segment this
+// needs no per-segment pointer before the stream starts and keeps every lane
+// busy however short the segments are.  Deterministic.
+constexpr int kChunkCap = 512;  // LDS products per wavefront and round
+
+template <typename T, typename TV, int S>
+__global__ void __launch_bounds__(kWG)
+k_seg_chunk(int nseg, const int *__restrict__ ptr, const int *__restrict__ idx, const TV *__restrict__ val,
+            const T *__restrict__ vec, T *__restrict__ out, int ignore_done, const DevStatus *st)
+{
+    if (!ignore_done && st->done) return;
+    __shared__ T buf[kWG / 64][kChunkCap];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int sl = blockIdx.x % S;
+    const int g0 = ((blockIdx.x / S) * (kWG / 64) + w) * 64;
+    if (g0 >= nseg) return;  // the whole wavefront leaves
+    const int *p = ptr + (size_t)sl * nseg;  // p[nseg] is the slab's end
+    const int gl = g0 + lane;
+    const int beg = p[gl < nseg ? gl : nseg];
+    const int e_last = p[min(g0 + 64, nseg)];
+    int end = __shfl_down(beg, 1);
+    if (lane == 63) end = e_last;
+    const int E0 = __shfl(beg, 0), E1 = e_last;
+    T acc = 0;
+    for (int P0 = E0; P0 < E1; P0 += kChunkCap) {
+        const int P1 = min(P0 + kChunkCap, E1);
+        for (int b = P0; b < P1; b += 256) {
+            int j[4];
+            TV v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = b + u * 64 + lane;
+                const int kk = k < P1 ? k : P1 - 1;
+                j[u] = __builtin_nontemporal_load(idx + kk);
+                v[u] = __builtin_nontemporal_load(val + kk);
+            }
+            T g[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) g[u] = vec[j[u]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = b + u * 64 + lane;
+                if (k < P1) buf[w][k - P0] = (T)v[u] * g[u];
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int a = max(beg, P0), z = min(end, P1);
+        for (int k = a; k < z; ++k) acc += buf[w][k - P0];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (gl < nseg) out[(size_t)sl * nseg + gl] = acc;
+}
+
 // Row update from slab partials; the MODEs of k_row.
 template <typename T, int S, int MODE>
 __global__ void __launch_bounds__(kWG)
@@ -529,6 +591,7 @@ struct uv_solver {
     int L_row = 8, L_col = 4;   // lanes per row / column
     int E_row = 4, E_col = 4;   // gathers in flight per lane
     int S_row = 1, S_col = 1;   // XCD slabs of x (row pass) and of u (column pass)
+    bool chunked = true;        // slab passes by 64-segment chunks (else lane groups)
     int *srp = nullptr, *sci = nullptr;  // row-pass slab copy (S_row * m + 1 offsets)
     void *sva = nullptr;
     int *scp = nullptr, *sri = nullptr;  // column-pass slab copy (S_col * n + 1 offsets)
@@ -588,18 +651,27 @@ void row_slab_launch(uv_solver *s, hipStream_t st, int mode)
 {
     const unsigned g = S * blocks_for(s->m, kWG / L), gc = blocks_for(s->m, kWG);
     const double mu = s->o.mu, im = 1.0 / s->o.mu;
+    if (s->chunked) {
+        const unsigned gk = S * blocks_for(s->m, kWG);
+        const int ign = mode == 2 ? 1 : 0;
+        k_seg_chunk<T, T, S><<<gk, kWG, 0, st>>>(s->m, s->srp, s->sci, (const T *)s->sva, (const T *)s->x,
+                                                 (T *)s->P_row, ign, s->st);
+        if (mode == 1)
+            k_seg_chunk<T, T, S><<<gk, kWG, 0, st>>>(s->m, s->srp, s->sci, (const T *)s->sva, (const T *)s->z,
+                                                     (T *)s->P_row + (size_t)S * s->m, 0, s->st);
+    }
 #define UV_SLAB_ARGS s->m, s->srp, s->sci, (const T *)s->sva, (const T *)s->x, (const T *)s->z, (T *)s->P_row
 #define UV_COMB_ARGS                                                                                       \
     s->m, (const T *)s->P_row, (const T *)s->b, (const T *)s->fu, s->lam, (T *)s->u, mu, im, s->part_row,  \
         s->nblk_row_fused, s->st
     if (mode == 1) {
-        k_row_slab<T, L, E, S, true><<<g, kWG, 0, st>>>(UV_SLAB_ARGS, 0, s->st);
+        if (!s->chunked) k_row_slab<T, L, E, S, true><<<g, kWG, 0, st>>>(UV_SLAB_ARGS, 0, s->st);
         k_row_combine<T, S, 1><<<gc, kWG, 0, st>>>(UV_COMB_ARGS);
     } else if (mode == 2) {
-        k_row_slab<T, L, E, S, false><<<g, kWG, 0, st>>>(UV_SLAB_ARGS, 1, s->st);
+        if (!s->chunked) k_row_slab<T, L, E, S, false><<<g, kWG, 0, st>>>(UV_SLAB_ARGS, 1, s->st);
         k_row_combine<T, S, 2><<<gc, kWG, 0, st>>>(UV_COMB_ARGS);
     } else {
-        k_row_slab<T, L, E, S, false><<<g, kWG, 0, st>>>(UV_SLAB_ARGS, 0, s->st);
+        if (!s->chunked) k_row_slab<T, L, E, S, false><<<g, kWG, 0, st>>>(UV_SLAB_ARGS, 0, s->st);
         k_row_combine<T, S, 0><<<gc, kWG, 0, st>>>(UV_COMB_ARGS);
     }
 #undef UV_SLAB_ARGS
@@ -650,9 +722,14 @@ void col_update_launch(uv_solver *s, hipStream_t st)
 template <typename T, int L, int E, int S>
 void col_slab_launch(uv_solver *s, hipStream_t st)
 {
-    const unsigned g = S * blocks_for(s->n, kWG / L);
-    k_col_slab<T, L, E, S><<<g, kWG, 0, st>>>(s->n, s->scp, s->sri, (const T *)s->svc, (const T *)s->u,
-                                              (T *)s->P_col, s->st);
+    if (s->chunked) {
+        k_seg_chunk<T, T, S><<<S * blocks_for(s->n, kWG), kWG, 0, st>>>(
+            s->n, s->scp, s->sri, (const T *)s->svc, (const T *)s->u, (T *)s->P_col, 0, s->st);
+    } else {
+        const unsigned g = S * blocks_for(s->n, kWG / L);
+        k_col_slab<T, L, E, S><<<g, kWG, 0, st>>>(s->n, s->scp, s->sri, (const T *)s->svc, (const T *)s->u,
+                                                  (T *)s->P_col, s->st);
+    }
     col_update_launch<T, 1, 1, S>(s, st);
 }
 
@@ -797,6 +874,7 @@ int validate(const uv_csr *A, const double *b, const double *c, const uv_cones *
     if (!lanes_ok(o->lanes_row) || !lanes_ok(o->lanes_col)) return UV_EINVAL;
     if (!unroll_ok(o->unroll_row) || !unroll_ok(o->unroll_col)) return UV_EINVAL;
     if (!slabs_ok(o->slabs_row) || !slabs_ok(o->slabs_col)) return UV_EINVAL;
+    if (o->slab_kernel < 0 || o->slab_kernel > 2) return UV_EINVAL;
     if (A->nnz > 0 && (!A->col_idx || !A->val)) return UV_EINVAL;
     if (!A->row_ptr) return UV_EINVAL;
     if (A->nnz >= ((int64_t)1 << 31)) return UV_ETOOBIG;
@@ -994,6 +1072,7 @@ void uv_default_opts(uv_opts *o)
     o->slabs_col = 0;
     o->criterion = 0;
     o->eps_abs = 0.0;
+    o->slab_kernel = 0;
 }
 
 const char *solver_strerror(int code)
@@ -1055,6 +1134,7 @@ int solver_create(const uv_csr *A, const double *b, const double *c, const uv_co
     s->L_col = o.lanes_col ? o.lanes_col : pick_lanes((double)A->nnz / A->n / s->S_col);
     s->E_row = o.unroll_row ? o.unroll_row : 2;
     s->E_col = o.unroll_col ? o.unroll_col : 2;
+    s->chunked = o.slab_kernel != 2;
     rc = setup(s, A, b, c, K);
     if (rc == UV_OK) rc = solver_set_start(s, nullptr, nullptr, nullptr, nullptr);
     if (rc == UV_OK && s->o.use_graph) rc = build_graph(s);

@@ -92,16 +92,36 @@ def test_launch_shapes(lanes, unroll, graph):
 
 
 @pytest.mark.parametrize("slabs", [(2, 2), (8, 4), (4, 8), (8, 1), (1, 8)])
-@pytest.mark.parametrize("prec", ["fp64"])
-def test_xcd_slabs(slabs, prec):
+@pytest.mark.parametrize("kernel", ["chunked", "lanes"])
+def test_xcd_slabs(slabs, kernel):
     """Slab-split passes (forced on a small ragged problem) against the oracle,
     with the fused residual check inside the chunk."""
     inst = I.conic_instance(1003, 411, [3, 7, 50, 1, 260] + [5] * 40, 4, seed=23)
     g, o, gr, orr = run_pair(inst, 200, mu=0.9, slabs_row=slabs[0], slabs_col=slabs[1], check_every=9,
-                             lanes_row=4, lanes_col=2)
+                             lanes_row=4, lanes_col=2, slab_kernel=kernel)
     assert_parity(g, o)
     for k in ("r_prim", "r_dual", "r_gap", "pobj", "dobj", "res_ax_b"):
         assert abs(gr[k] - orr[k]) <= 1e-9 * max(abs(orr[k]), 1e-12), k
+
+
+def test_chunked_long_segments():
+    """Segments longer than a wavefront's LDS round (dense rows and columns)
+    and empty ones, through the chunked slab kernel."""
+    base = I.lp_instance(700, 1500, 3, seed=25)
+    A = np.zeros((700, 1500))
+    rows = np.repeat(np.arange(700), np.diff(base["row_ptr"]))
+    A[rows, base["col_idx"]] = base["val"]
+    rng = np.random.default_rng(4)
+    A[5, :] = rng.standard_normal(1500)          # a dense row (1500 entries)
+    A[:, 7] = rng.standard_normal(700)           # a dense column
+    A[100:140, :] = 0.0                          # empty rows
+    rr, cc = np.nonzero(A)
+    row_ptr = np.zeros(701, np.int64)
+    np.cumsum(np.bincount(rr, minlength=700), out=row_ptr[1:])
+    inst = dict(base, row_ptr=row_ptr, col_idx=cc.astype(np.int32), val=A[rr, cc], nnz=int(rr.size),
+                b=A @ base["x0"])
+    g, o, _, _ = run_pair(inst, 200, slabs_row=4, slabs_col=2, check_every=6)
+    assert_parity(g, o)
 
 
 def test_xcd_slabs_resume_and_mixed():
