@@ -483,6 +483,29 @@ k_res_col(int n, const int *__restrict__ cp, const int *__restrict__ ri, const d
     uv::block_sum_max<2, 2>(acc, mx, part + blockIdx.x, pstride);
 }
 
+// Column residual partials from the slab partials of A'lambda (FP64 slab
+// copy): the layout of k_res_col, one thread per column.
+template <typename T, int S>
+__global__ void __launch_bounds__(kWG)
+k_res_col_slab(int n, const double *__restrict__ P, const double *__restrict__ c, const double *__restrict__ delta,
+               const T *__restrict__ z, double *__restrict__ part, int pstride)
+{
+    const int col = blockIdx.x * kWG + threadIdx.x;
+    double acc[2] = {0.0, 0.0}, mx[2] = {0.0, 0.0};
+    if (col < n) {
+        double a = 0.0;
+#pragma unroll
+        for (int sl = 0; sl < S; ++sl) a += P[(size_t)sl * n + col];
+        const double cj = c[col];
+        const double r = a + cj - delta[col];
+        acc[0] = r * r;
+        acc[1] = cj * (double)z[col];
+        mx[0] = fabs(r);
+        mx[1] = fabs(a);
+    }
+    uv::block_sum_max<2, 2>(acc, mx, part + blockIdx.x, pstride);
+}
+
 // Adds the partials in a fixed order (eight independent loads in flight
 // per thread), forms the residuals and decides whether to stop.  Partials
 // are stored component-major: prow[k * nrow + block], rows: sums of
@@ -634,13 +657,15 @@ bool unroll_ok(int E) { return E == 0 || E == 1 || E == 2 || E == 4 || E == 8; }
 
 bool slabs_ok(int S) { return S == 0 || S == 1 || S == 2 || S == 4 || S == 8; }
 
-// Slabs for a gathered vector of `bytes`: none up to 2 MiB, else enough
-// power-of-two slabs for about 2 MiB each, at most 4 (measured on the 1e6 x
-// 2e6 LP: 8 slabs of x gain nothing over 4 and add partial traffic).
+// Slabs for a gathered vector of `bytes`: none up to 2 MiB, else at least
+// two and about 4 MiB each, at most 4 (measured on the 1e6 x 2e6 LP: FP64
+// best at 4 slabs of x and 2 of u, FP32 at 2 and 2; more slabs add partial
+// traffic faster than they save gathers).
 int pick_slabs(size_t bytes)
 {
-    int S = 1;
-    while (S < 4 && bytes > (size_t)S * (2u << 20)) S <<= 1;
+    if (bytes <= (2u << 20)) return 1;
+    int S = 2;
+    while (S < 4 && bytes > (size_t)S * (4u << 20)) S <<= 1;
     return S;
 }
 
@@ -828,12 +853,32 @@ void launch_row(uv_solver *s, hipStream_t st, int mode)
 // MODE 1 row pass only the column residuals remain.  The residual kernels
 // take one fixed unroll; their lane counts follow the sweep's so the
 // partial arrays are sized once.
+template <int S>
+void res_col_slab_launch(uv_solver *s, hipStream_t st)
+{
+    const unsigned g = blocks_for(s->n, kWG);
+    k_seg_chunk<double, double, S><<<S * g, kWG, 0, st>>>(s->n, s->scp, s->sri, (const double *)s->svc, s->lam,
+                                                          (double *)s->P_col, 1, s->st);
+    k_res_col_slab<double, S><<<g, kWG, 0, st>>>(s->n, (const double *)s->P_col, s->c64, s->delta,
+                                                 (const double *)s->z, s->part_col, (int)g);
+}
+
 void launch_residuals(uv_solver *s, hipStream_t st, bool row_done)
 {
     if (!row_done) dispatch_le_res<ResRowLaunch>(s, st, s->L_row);
-    dispatch_le_res<ResColLaunch>(s, st, s->L_col);
+    // FP64 with column slabs and chunked passes: A'lambda through the slab copy
+    // (its values are the FP64 ones), else the plain column residual pass
+    const bool slab = s->o.precision == UV_FP64 && s->S_col > 1 && s->chunked;
+    if (slab) {
+        if (s->S_col == 2) res_col_slab_launch<2>(s, st);
+        else if (s->S_col == 4) res_col_slab_launch<4>(s, st);
+        else res_col_slab_launch<8>(s, st);
+    } else {
+        dispatch_le_res<ResColLaunch>(s, st, s->L_col);
+    }
     const int nrow = row_done ? s->nblk_row_fused : s->nblk_row;
-    k_finalize<<<1, kWG, 0, st>>>(nrow, s->part_row, s->nblk_rescol, s->part_col, s->o.eps_kkt, s->o.eps_abs,
+    const int ncol = slab ? (int)blocks_for(s->n, kWG) : s->nblk_rescol;
+    k_finalize<<<1, kWG, 0, st>>>(nrow, s->part_row, ncol, s->part_col, s->o.eps_kkt, s->o.eps_abs,
                                   s->o.criterion, s->st);
 }
 
@@ -944,7 +989,7 @@ int setup(uv_solver *s, const uv_csr *A, const double *b, const double *c, const
     s->nblk_row_fused = s->S_row > 1 ? (int)blocks_for(m, kWG) : s->nblk_row;
     s->nblk_rescol = (int)blocks_for(n, kWG / s->L_col);
     s->part_row = dalloc<double>(s, 5 * (size_t)std::max(s->nblk_row, s->nblk_row_fused));
-    s->part_col = dalloc<double>(s, 4 * (size_t)s->nblk_rescol);
+    s->part_col = dalloc<double>(s, 4 * std::max((size_t)s->nblk_rescol, (size_t)blocks_for(n, kWG)));
     s->st = dalloc<DevStatus>(s, 1);
     const size_t ncnt = std::max({(size_t)n, (size_t)s->S_row * m, (size_t)s->S_col * n});
     int *cnt = dalloc<int>(s, ncnt);
