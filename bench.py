@@ -65,6 +65,17 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def describe(inst) -> str:
+    """Problem class, sizes and cone of a single-instance workload."""
+    m, n, nnz = inst["m"], inst["n"], inst["nnz"]
+    soc = inst.get("soc_sizes")
+    if soc is not None and len(soc):
+        soc = np.asarray(soc)
+        return (f"SOCP m={m} n={n} nnz={nnz}, {len(soc)} second-order cones of sizes "
+                f"{int(soc.min())}..{int(soc.max())} (sum {int(soc.sum())}), orthant part {inst.get('n_orth', 0)}")
+    return f"LP m={m} n={n} nnz={nnz}, unit-norm rows, orthant cone"
+
+
 def alg_bytes(m, n, nnz, precision):
     """Algorithmic bytes per launch of the row and column passes: every array
     counted once, gathered vectors at their compulsory size, int32 indices."""
@@ -360,8 +371,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: LP m={m} n={n} nnz={nnz}, unit-norm rows, "
-                               f"orthant cone, mu={args.mu}, check_every={args.check_every}",
+        "config": {"workload": f"{args.workload}: {describe(inst)}, mu={args.mu}, check_every={args.check_every}",
                    "launch": {k: main_r[k] for k in ("lanes_row", "unroll_row", "lanes_col", "slabs_row", "slabs_col",
                                                      "unroll_col")}},
         "time_to_1e-4_s": main_r["ttk_s"],
