@@ -44,3 +44,35 @@ def test_pins_catch_mutant(name, tmp_path):
                         os.path.join(ROOT, "tests", "test_oracle_pins.py")],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"pins did not catch: {name}\n{r.stdout[-2000:]}"
+
+
+STD_SRC = os.path.join(ROOT, "oracle", "standard_oracle.c")
+
+STD_MUTANTS = {
+    "x1 step sign of lam": ("const double a = h->x2[j] - h->lam[j] / mu;", "const double a = h->x2[j] + h->lam[j] / mu;"),
+    "v drops c/mu": ("h->v[j] = h->x1[j] + h->lam[j] / mu - h->c[j] / mu;", "h->v[j] = h->x1[j] + h->lam[j] / mu;"),
+    "delta from the new x2": ("h->delta[j] = h->lam[j] + mu * (h->x1[j] - h->x2[j]);", "h->delta[j] = h->lam[j];"),
+    "CG beta inverted": ("const double beta = rr_new / rr;", "const double beta = rr / rr_new;"),
+    "CG residual update sign": ("h->r[i] -= alpha * h->q[i];", "h->r[i] += alpha * h->q[i];"),
+    "CG ignores the warm start": ("h->r[i] = h->g[i] - h->q[i];", "h->r[i] = h->g[i];"),
+    "x2 sign of A'nu": ("h->x2[j] = h->v[j] - h->tn[j];", "h->x2[j] = h->v[j] + h->tn[j];"),
+    "lam update sign": ("h->lam[j] += mu * (h->x1[j] - h->x2[j]);", "h->lam[j] -= mu * (h->x1[j] - h->x2[j]);"),
+    "residual multiplier not scaled by mu": ("la[i] = h->mu * h->nu[i];", "la[i] = h->nu[i];"),
+    "rhs drops b": ("for (int32_t i = 0; i < m; ++i) h->g[i] -= h->b[i];", ""),
+}
+
+
+@pytest.mark.parametrize("name", sorted(STD_MUTANTS))
+def test_standard_pins_catch_mutant(name, tmp_path):
+    from oracle import standard
+    old, new = STD_MUTANTS[name]
+    text = open(STD_SRC).read()
+    assert text.count(old) == 1, f"mutation site not unique: {old}"
+    src = tmp_path / "mutant.c"
+    src.write_text(text.replace(old, new))
+    lib = standard.build(src=str(src), out=str(tmp_path / "libmutant.so"))
+    env = dict(os.environ, UVADMM_STD_ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_standard_pins.py")],
+                       env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"pins did not catch: {name}\n{r.stdout[-2000:]}"
