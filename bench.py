@@ -30,13 +30,15 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_lp_large_fp64.txt")
 
 
+SWEEP_SOURCES = ("solver.hip", "common.hpp", "setup.hpp", "spmv.hpp")
+
+
 def sources_digest() -> str:
-    """Digest of the kernel sources; a traffic measurement is only used while
-    the kernels are the ones it was taken on."""
-    import glob
+    """Digest of the single-problem solver's kernel sources; a traffic
+    measurement is only used while the kernels are the ones it was taken on."""
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2203_05027_amd", "csrc", "*"))):
+    for f in (os.path.join(ROOT, "paper_2203_05027_amd", "csrc", name) for name in SWEEP_SOURCES):
         with open(f, "rb") as fh:
             h.update(os.path.basename(f).encode())
             h.update(fh.read())
@@ -148,6 +150,34 @@ def cpu_baseline(inst, mu, seconds):
             "kind": "oracle",
             "sample": f"{k} FP64 iterations of the literal Algorithm 1 oracle on the full "
                       f"workload (timed {dt:.1f} s after one untimed iteration)"}
+
+
+def standard_block(inst, mu, cg_iters, cg_tol, check_every, cap_s, uv_ttk_s=None):
+    """Standard two-block ADMM with a warm-started CG solve of the block
+    system (the baseline the decomposition replaces) on the same instance and
+    product kernels: wall time, iterations and CG steps to 1e-4 KKT."""
+    import torch
+    from paper_2203_05027_amd.solver import Standard
+
+    with Standard.from_instance(inst, mu=mu, cg_iters=cg_iters, cg_tol=cg_tol, eps=1e-4,
+                                check_every=check_every) as s:
+        shape = s.launch_shape()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = False
+        while not done and time.perf_counter() - t0 < cap_s:
+            done = s.iterate(100)
+        dt = time.perf_counter() - t0
+        r = s.residuals()
+    it = max(int(r["iter"]), 1)
+    out = {"cg_iters": cg_iters, "cg_tol": cg_tol, "mu": mu, "launch": shape, "status": r["status"],
+           "iters": int(r["iter"]), "cg_steps": int(r["cg_steps"]), "seconds": dt, "kkt": r["kkt"],
+           "pobj": r["pobj"], "ms_per_iter": dt * 1e3 / it,
+           "products_per_iter": 1 + 2 * r["cg_steps"] / it + 2.0 / check_every,
+           "cap_s": cap_s}
+    if uv_ttk_s and r["status"] == "converged":
+        out["uv_speedup_time_to_1e-4"] = dt / uv_ttk_s
+    return out
 
 
 def batched_block(steps_sweep=100, ttk_cap=60_000, plain_sample=8, count=4096, log_fn=log):
@@ -281,6 +311,10 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-ttk", action="store_true", help="skip the time-to-1e-4 runs")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-workload block")
+    ap.add_argument("--no-standard", action="store_true", help="skip the standard ADMM + CG baseline")
+    ap.add_argument("--std-cg-iters", type=int, default=10, help="baseline: CG steps per iteration at most")
+    ap.add_argument("--std-cg-tol", type=float, default=1e-7, help="baseline: CG stop, ||r|| <= tol (1 + ||b||)")
+    ap.add_argument("--std-cap-s", type=float, default=60.0, help="baseline: wall-time cap of its solve")
     ap.add_argument("--train", type=int, default=20_000, help="parametric: training members")
     ap.add_argument("--eval", type=int, default=1000, help="parametric: held-out members")
     ap.add_argument("--epochs", type=int, default=60, help="parametric: training epochs")
@@ -336,6 +370,13 @@ def main():
     achieved = kern[dom][0] / (kern[dom][1] * 1e-3) / 1e9
     sweep_gbs = (row_b + col_b) / ((main_r["ms_col"] + main_r["ms_row"]) * 1e-3) / 1e9
 
+    standard = None
+    if not args.no_standard and not args.no_ttk and not len(inst.get("soc_sizes", ())):
+        log("standard ADMM + CG baseline")
+        standard = standard_block(inst, args.mu, args.std_cg_iters, args.std_cg_tol, args.check_every,
+                                  args.std_cap_s, main_r["ttk_s"])
+        log(f"standard: {json.dumps(standard)}")
+
     batched = None
     if not args.no_batched and args.workload == "lp_large":
         log("batched workload")
@@ -387,6 +428,7 @@ def main():
                      "alg_bytes_per_launch": kern[dom][0], "ms_per_launch": kern[dom][1]},
         "mixed": extra,
         "batched": batched,
+        "standard_admm_cg": standard,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -334,6 +334,47 @@ int literal_time(uv_literal *h, int32_t iters, double *ms_col, double *ms_row);
 void literal_destroy(uv_literal *h);
 
 /* ------------------------------------------------------------------------
+ * Baseline: standard two-block ADMM on the splitting x1 = x2 (Section II-B:
+ * f the cone indicator, g the objective on {A x = b}) with the block system
+ * eq. lin solved indirectly every iteration (Section III-B): conjugate
+ * gradients on (A A') nu = A (w0 - c/mu) - b, warm-started from the previous
+ * nu.  FP64, nonnegative orthant only.  Per iteration:
+ *   x1 = max(x2 - lam/mu, 0);  delta = lam + mu (x1 - x2)
+ *   CG: at most cg_iters steps, stopping once ||r||_2 <= cg_tol (1 + ||b||_2)
+ *       or when p'A A'p is not positive
+ *   x2 = x1 + lam/mu - c/mu - A'nu;  lam += mu (x1 - x2)
+ * Residuals (uv_residuals, SCS form as for solver_residuals) at z = x1 with
+ * the multiplier lambda_A = mu nu of A x = b and delta of the cone; the
+ * fields r_prim, r_dual, r_gap, kkt, pobj, dobj, iter, status are set, the
+ * others are zero.
+ *
+ * standard_create: A, b, c as for solver_create (host, copied; invalid CSR
+ *   -> UV_EBADCSR); opts: mu, check_every, eps_kkt, max_iter, hip_stream,
+ *   use_graph, slabs_row / slabs_col (0, 1, 2 or 4; 0 = the solver's rule);
+ *   precision must be UV_FP64 (else UV_EINVAL); cg_iters >= 0,
+ *   cg_tol >= 0 (else UV_EINVAL).  Zero start.
+ * standard_set_state: x2, lam (n) and the CG start nu (m), host, any NULL =
+ *   zero; resets the iteration count and status.
+ * standard_iterate / standard_residuals: as solver_iterate /
+ *   solver_residuals; *cg_steps (may be NULL) receives the CG steps taken.
+ * standard_solution: x1, x2, lam, delta (n), nu (m) into host buffers; any
+ *   may be NULL.
+ * ------------------------------------------------------------------------ */
+typedef struct uv_standard uv_standard;
+int standard_create(const uv_csr *A, const double *b, const double *c,
+                    const uv_opts *opts, int32_t cg_iters, double cg_tol,
+                    uv_standard **out);
+int standard_set_state(uv_standard *h, const double *x2, const double *lam,
+                       const double *nu);
+int standard_iterate(uv_standard *h, int64_t k, int32_t *done);
+int standard_residuals(uv_standard *h, uv_residuals *r, int64_t *cg_steps);
+int standard_solution(uv_standard *h, double *x1, double *x2, double *lam,
+                      double *nu, double *delta);
+/* Slab counts of the row and column products (either may be NULL). */
+int standard_launch_shape(uv_standard *h, int32_t *slabs_row, int32_t *slabs_col);
+void standard_destroy(uv_standard *h);
+
+/* ------------------------------------------------------------------------
  * Learned warm start: dense kernels.  Pointers marked _dev are DEVICE
  * pointers (for instance from framework tensors); the stream argument may be
  * NULL (the default stream).  All of these wait for their work to finish.

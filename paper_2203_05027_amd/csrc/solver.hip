@@ -32,6 +32,7 @@
 #include "../../include/uvadmm.h"
 #include "common.hpp"
 #include "setup.hpp"
+#include "spmv.hpp"
 
 using uv::kWG;
 
@@ -346,68 +347,6 @@ k_row_slab(int m, const int *__restrict__ srp, const int *__restrict__ sci, cons
     }
 }
 
-// Chunked segment sums for the slab passes: out[s * nseg + g] = sum over the
-// entries k of segment g in slab s of val[k] * vec[idx[k]].  A wavefront owns
-// 64 consecutive segments (one per lane for the final sum): it streams their
-// contiguous entries with coalesced loads, four 64-entry steps in flight per
-// round, parks the products in LDS, and each lane then adds its own
-// segment's products in entry order.  Unlike one lane group per segment this
-// needs no per-segment pointer before the stream starts and keeps every lane
-// busy however short the segments are.  Deterministic.
-constexpr int kChunkCap = 512;  // LDS products per wavefront and round
-
-template <typename T, typename TV, int S>
-__global__ void __launch_bounds__(kWG)
-k_seg_chunk(int nseg, const int *__restrict__ ptr, const int *__restrict__ idx, const TV *__restrict__ val,
-            const T *__restrict__ vec, T *__restrict__ out, int ignore_done, const DevStatus *st)
-{
-    if (!ignore_done && st->done) return;
-    __shared__ T buf[kWG / 64][kChunkCap];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int sl = blockIdx.x % S;
-    const int g0 = ((blockIdx.x / S) * (kWG / 64) + w) * 64;
-    if (g0 >= nseg) return;  // the whole wavefront leaves
-    const int *p = ptr + (size_t)sl * nseg;  // p[nseg] is the slab's end
-    const int gl = g0 + lane;
-    const int beg = p[gl < nseg ? gl : nseg];
-    const int e_last = p[min(g0 + 64, nseg)];
-    int end = __shfl_down(beg, 1);
-    if (lane == 63) end = e_last;
-    const int E0 = __shfl(beg, 0), E1 = e_last;
-    T acc = 0;
-    for (int P0 = E0; P0 < E1; P0 += kChunkCap) {
-        const int P1 = min(P0 + kChunkCap, E1);
-        for (int b = P0; b < P1; b += 256) {
-            int j[4];
-            TV v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int k = b + u * 64 + lane;
-                const int kk = k < P1 ? k : P1 - 1;
-                j[u] = __builtin_nontemporal_load(idx + kk);
-                v[u] = __builtin_nontemporal_load(val + kk);
-            }
-            T g[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) g[u] = vec[j[u]];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int k = b + u * 64 + lane;
-                if (k < P1) buf[w][k - P0] = (T)v[u] * g[u];
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int a = max(beg, P0), z = min(end, P1);
-        for (int k = a; k < z; ++k) acc += buf[w][k - P0];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-    if (gl < nseg) out[(size_t)sl * nseg + gl] = acc;
-}
-
 // Row update from slab partials; the MODEs of k_row.
 template <typename T, int S, int MODE>
 __global__ void __launch_bounds__(kWG)
@@ -657,17 +596,6 @@ bool unroll_ok(int E) { return E == 0 || E == 1 || E == 2 || E == 4 || E == 8; }
 
 bool slabs_ok(int S) { return S == 0 || S == 1 || S == 2 || S == 4 || S == 8; }
 
-// Slabs for a gathered vector of `bytes`: none up to 2 MiB, else at least
-// two and about 4 MiB each, at most 4 (measured on the 1e6 x 2e6 LP: FP64
-// best at 4 slabs of x and 2 of u, FP32 at 2 and 2; more slabs add partial
-// traffic faster than they save gathers).
-int pick_slabs(size_t bytes)
-{
-    if (bytes <= (2u << 20)) return 1;
-    int S = 2;
-    while (S < 4 && bytes > (size_t)S * (4u << 20)) S <<= 1;
-    return S;
-}
 
 // ---- launch helpers (dispatch on precision, lanes L and unroll E) ----
 
@@ -678,12 +606,12 @@ void row_slab_launch(uv_solver *s, hipStream_t st, int mode)
     const double mu = s->o.mu, im = 1.0 / s->o.mu;
     if (s->chunked) {
         const unsigned gk = S * blocks_for(s->m, kWG);
-        const int ign = mode == 2 ? 1 : 0;
+        const bool ign = mode == 2;
         k_seg_chunk<T, T, S><<<gk, kWG, 0, st>>>(s->m, s->srp, s->sci, (const T *)s->sva, (const T *)s->x,
-                                                 (T *)s->P_row, ign, s->st);
+                                                 (T *)s->P_row, ign ? nullptr : &s->st->done);
         if (mode == 1)
             k_seg_chunk<T, T, S><<<gk, kWG, 0, st>>>(s->m, s->srp, s->sci, (const T *)s->sva, (const T *)s->z,
-                                                     (T *)s->P_row + (size_t)S * s->m, 0, s->st);
+                                                     (T *)s->P_row + (size_t)S * s->m, &s->st->done);
     }
 #define UV_SLAB_ARGS s->m, s->srp, s->sci, (const T *)s->sva, (const T *)s->x, (const T *)s->z, (T *)s->P_row
 #define UV_COMB_ARGS                                                                                       \
@@ -749,7 +677,7 @@ void col_slab_launch(uv_solver *s, hipStream_t st)
 {
     if (s->chunked) {
         k_seg_chunk<T, T, S><<<S * blocks_for(s->n, kWG), kWG, 0, st>>>(
-            s->n, s->scp, s->sri, (const T *)s->svc, (const T *)s->u, (T *)s->P_col, 0, s->st);
+            s->n, s->scp, s->sri, (const T *)s->svc, (const T *)s->u, (T *)s->P_col, &s->st->done);
     } else {
         const unsigned g = S * blocks_for(s->n, kWG / L);
         k_col_slab<T, L, E, S><<<g, kWG, 0, st>>>(s->n, s->scp, s->sri, (const T *)s->svc, (const T *)s->u,
@@ -858,7 +786,7 @@ void res_col_slab_launch(uv_solver *s, hipStream_t st)
 {
     const unsigned g = blocks_for(s->n, kWG);
     k_seg_chunk<double, double, S><<<S * g, kWG, 0, st>>>(s->n, s->scp, s->sri, (const double *)s->svc, s->lam,
-                                                          (double *)s->P_col, 1, s->st);
+                                                          (double *)s->P_col, nullptr);
     k_res_col_slab<double, S><<<g, kWG, 0, st>>>(s->n, (const double *)s->P_col, s->c64, s->delta,
                                                  (const double *)s->z, s->part_col, (int)g);
 }

@@ -1,0 +1,89 @@
+// spmv.hpp -- the sparse product kernel of the slab passes, shared by the
+// UV-decomposition solver and the standard-ADMM baseline.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace {
+
+using uv::kWG;
+
+// Chunked segment sums for the slab passes: out[s * nseg + g] = sum over the
+// entries k of segment g in slab s of val[k] * vec[idx[k]].  A wavefront owns
+// 64 consecutive segments (one per lane for the final sum): it streams their
+// contiguous entries with coalesced loads, four 64-entry steps in flight per
+// round, parks the products in LDS, and each lane then adds its own
+// segment's products in entry order.  Unlike one lane group per segment this
+// needs no per-segment pointer before the stream starts and keeps every lane
+// busy however short the segments are.  Deterministic.  With S = 1 the
+// arguments are a plain compressed-row (or -column) matrix.  The grid is
+// S * ceil(nseg / kWG) workgroups; workgroup w works on slab w % S.
+constexpr int kChunkCap = 512;  // LDS products per wavefront and round
+
+template <typename T, typename TV, int S>
+__global__ void __launch_bounds__(kWG)
+k_seg_chunk(int nseg, const int *__restrict__ ptr, const int *__restrict__ idx, const TV *__restrict__ val,
+            const T *__restrict__ vec, T *__restrict__ out, const int *skip)
+{
+    if (skip && *skip) return;  // a device flag (stop, or nothing left to do)
+    __shared__ T buf[kWG / 64][kChunkCap];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int sl = blockIdx.x % S;
+    const int g0 = ((blockIdx.x / S) * (kWG / 64) + w) * 64;
+    if (g0 >= nseg) return;  // the whole wavefront leaves
+    const int *p = ptr + (size_t)sl * nseg;  // p[nseg] is the slab's end
+    const int gl = g0 + lane;
+    const int beg = p[gl < nseg ? gl : nseg];
+    const int e_last = p[min(g0 + 64, nseg)];
+    int end = __shfl_down(beg, 1);
+    if (lane == 63) end = e_last;
+    const int E0 = __shfl(beg, 0), E1 = e_last;
+    T acc = 0;
+    for (int P0 = E0; P0 < E1; P0 += kChunkCap) {
+        const int P1 = min(P0 + kChunkCap, E1);
+        for (int b = P0; b < P1; b += 256) {
+            int j[4];
+            TV v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = b + u * 64 + lane;
+                const int kk = k < P1 ? k : P1 - 1;
+                j[u] = __builtin_nontemporal_load(idx + kk);
+                v[u] = __builtin_nontemporal_load(val + kk);
+            }
+            T g[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) g[u] = vec[j[u]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = b + u * 64 + lane;
+                if (k < P1) buf[w][k - P0] = (T)v[u] * g[u];
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int a = max(beg, P0), z = min(end, P1);
+        for (int k = a; k < z; ++k) acc += buf[w][k - P0];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (gl < nseg) out[(size_t)sl * nseg + gl] = acc;
+}
+
+// Slabs for a gathered vector of `bytes`: none up to 2 MiB, else at least
+// two and about 4 MiB each, at most 4 (measured on the 1e6 x 2e6 LP: FP64
+// best at 4 slabs of x and 2 of u, FP32 at 2 and 2; more slabs add partial
+// traffic faster than they save gathers).
+inline int pick_slabs(size_t bytes)
+{
+    if (bytes <= (2u << 20)) return 1;
+    int S = 2;
+    while (S < 4 && bytes > (size_t)S * (4u << 20)) S <<= 1;
+    return S;
+}
+
+}  // namespace

@@ -570,3 +570,108 @@ class Literal:
         a, b = ctypes.c_double(), ctypes.c_double()
         _check(lib().literal_time(self._h, int(iters), ctypes.byref(a), ctypes.byref(b)), "literal_time")
         return a.value, b.value
+
+
+class Standard:
+    """Baseline: standard two-block ADMM with a warm-started CG solve of the
+    block system every iteration (FP64, orthant cone), on the same sparse
+    product kernels as the UV solver."""
+
+    def __init__(self, m, n, row_ptr, col_idx, val, b, c, *, mu=1.0, cg_iters=10, cg_tol=0.0,
+                 check_every=10, eps=1e-4, max_iter=0, slabs_row=0, slabs_col=0, use_graph=True,
+                 stream=None):
+        L = lib()
+        if not hasattr(L, "_standard_bound"):
+            P, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+            L.standard_create.argtypes = [ctypes.POINTER(UvCsr), P, P, ctypes.POINTER(UvOpts), i32, f64,
+                                          ctypes.POINTER(P)]
+            L.standard_create.restype = ctypes.c_int
+            L.standard_set_state.argtypes = [P, P, P, P]
+            L.standard_set_state.restype = ctypes.c_int
+            L.standard_iterate.argtypes = [P, i64, ctypes.POINTER(i32)]
+            L.standard_iterate.restype = ctypes.c_int
+            L.standard_residuals.argtypes = [P, ctypes.POINTER(UvResiduals), ctypes.POINTER(i64)]
+            L.standard_residuals.restype = ctypes.c_int
+            L.standard_solution.argtypes = [P, P, P, P, P, P]
+            L.standard_solution.restype = ctypes.c_int
+            L.standard_launch_shape.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+            L.standard_launch_shape.restype = ctypes.c_int
+            L.standard_destroy.argtypes = [P]
+            L.standard_destroy.restype = None
+            L._standard_bound = True
+        self.m, self.n = int(m), int(n)
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        va = np.ascontiguousarray(val, dtype=np.float64)
+        self.nnz = int(rp[-1])
+        csr = UvCsr(self.m, self.n, self.nnz, _ptr(rp), _ptr(ci), _ptr(va))
+        o = default_opts()
+        o.mu = float(mu)
+        o.check_every = int(check_every)
+        o.eps_kkt = float(eps)
+        o.max_iter = int(max_iter)
+        o.slabs_row = int(slabs_row)
+        o.slabs_col = int(slabs_col)
+        o.use_graph = 1 if use_graph else 0
+        o.hip_stream = stream
+        h = ctypes.c_void_p()
+        _check(L.standard_create(ctypes.byref(csr), _ptr(_f64(b, self.m)), _ptr(_f64(c, self.n)),
+                                 ctypes.byref(o), int(cg_iters), float(cg_tol), ctypes.byref(h)),
+               "standard_create")
+        self._h = h
+
+    @classmethod
+    def from_instance(cls, inst, **kw):
+        if inst.get("soc_sizes") is not None and len(inst["soc_sizes"]):
+            raise ValueError("the standard-ADMM baseline takes the orthant cone only")
+        return cls(inst["m"], inst["n"], inst["row_ptr"], inst["col_idx"], inst["val"], inst["b"],
+                   inst["c"], **kw)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().standard_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_state(self, x2=None, lam=None, nu=None):
+        args = (_f64(x2, self.n), _f64(lam, self.n), _f64(nu, self.m))
+        _check(lib().standard_set_state(self._h, *[_ptr(a) for a in args]), "standard_set_state")
+
+    def iterate(self, k: int) -> bool:
+        done = ctypes.c_int32(0)
+        rc = lib().standard_iterate(self._h, int(k), ctypes.byref(done))
+        if rc not in (UV_OK, UV_ENUMERIC):
+            _check(rc, "standard_iterate")
+        return bool(done.value)
+
+    def residuals(self) -> dict:
+        r = UvResiduals()
+        steps = ctypes.c_int64()
+        _check(lib().standard_residuals(self._h, ctypes.byref(r), ctypes.byref(steps)), "standard_residuals")
+        d = {k: getattr(r, k) for k in ("r_prim", "r_dual", "r_gap", "kkt", "pobj", "dobj", "iter", "status")}
+        d["status"] = STATUS.get(d["status"], d["status"])
+        d["cg_steps"] = steps.value
+        return d
+
+    def solution(self) -> dict:
+        x1, x2, lam, d = (np.empty(self.n) for _ in range(4))
+        nu = np.empty(self.m)
+        _check(lib().standard_solution(self._h, _ptr(x1), _ptr(x2), _ptr(lam), _ptr(nu), _ptr(d)),
+               "standard_solution")
+        return {"x1": x1, "x2": x2, "lam": lam, "nu": nu, "delta": d}
+
+    def launch_shape(self) -> dict:
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().standard_launch_shape(self._h, ctypes.byref(a), ctypes.byref(b)), "standard_launch_shape")
+        return {"slabs_row": a.value, "slabs_col": b.value}

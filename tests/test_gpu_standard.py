@@ -1,0 +1,121 @@
+"""The standard-ADMM + CG baseline on the GPU against its CPU oracle (same
+iteration, same CG decisions in FP64; only summation orders differ)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import standard as std_oracle
+from paper_2203_05027_amd import instances as I
+from paper_2203_05027_amd.solver import Standard
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("x1", "x2", "lam", "nu", "delta")
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)) if b.size else 0.0
+
+
+def _say(msg):
+    sys.__stderr__.write(f"[gpu-test] {msg}\n")
+    sys.__stderr__.flush()
+
+
+def _compare(inst, iters, mu=1.0, cg_iters=5, cg_tol=0.0, state=None, **kw):
+    orc = std_oracle.StandardADMM.from_instance(inst, mu=mu, cg_iters=cg_iters, cg_tol=cg_tol)
+    if state:
+        orc.set_state(**state)
+    orc.iterate(iters)
+    o = orc.state()
+    ro = orc.residuals()
+    with Standard.from_instance(inst, mu=mu, cg_iters=cg_iters, cg_tol=cg_tol, eps=0.0, **kw) as s:
+        if state:
+            s.set_state(**state)
+        s.iterate(iters)
+        g = s.solution()
+        rg = s.residuals()
+        shape = s.launch_shape()
+    errs = {k: rel(g[k], o[k]) for k in KEYS}
+    _say(f"standard m={inst['m']} n={inst['n']} {shape} cg={cg_iters}/{cg_tol}: {errs}")
+    return errs, ro, rg
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_small_lp_matches_oracle(use_graph):
+    inst = I.lp_instance(500, 1000, 5, seed=0)
+    errs, ro, rg = _compare(inst, 100, use_graph=use_graph)
+    assert max(errs.values()) <= 1e-9, errs
+    assert rg["iter"] == 100 and rg["cg_steps"] == 500 == ro["cg_steps"]
+    for k in ("r_prim", "r_dual", "r_gap", "pobj", "dobj"):
+        assert rg[k] == pytest.approx(ro[k], rel=1e-9, abs=1e-15), k
+
+
+@pytest.mark.parametrize("slabs", [(2, 2), (4, 2), (2, 4), (4, 4)])
+def test_slab_layouts_match_oracle(slabs):
+    inst = I.lp_instance(3001, 7003, 6, seed=41)
+    errs, _, _ = _compare(inst, 40, mu=0.7, cg_iters=3, slabs_row=slabs[0], slabs_col=slabs[1],
+                          check_every=7)
+    assert max(errs.values()) <= 1e-9, errs
+
+
+def test_given_state_matches_oracle():
+    inst = I.lp_instance(700, 1500, 5, seed=42)
+    rng = np.random.default_rng(3)
+    state = {"x2": rng.standard_normal(inst["n"]), "lam": rng.standard_normal(inst["n"]),
+             "nu": rng.standard_normal(inst["m"])}
+    errs, _, _ = _compare(inst, 60, mu=1.6, cg_iters=4, state=state)
+    assert max(errs.values()) <= 1e-9, errs
+
+
+def test_tolerance_mode_matches_oracle():
+    inst = I.lp_instance(500, 1000, 5, seed=43)
+    errs, ro, rg = _compare(inst, 150, cg_iters=25, cg_tol=1e-7)
+    assert max(errs.values()) <= 1e-9, errs
+    # the stop decisions are taken in FP64 on both sides; sums differ only in order
+    assert abs(rg["cg_steps"] - ro["cg_steps"]) <= 0.01 * ro["cg_steps"]
+    assert rg["cg_steps"] < 150 * 25
+
+
+def test_known_optimum_is_a_fixed_point():
+    inst = I.lp_instance(400, 800, 4, seed=7)
+    mu = 0.6
+    with Standard.from_instance(inst, mu=mu, cg_iters=3, eps=0.0) as s:
+        s.set_state(x2=inst["x0"], lam=inst["s0"], nu=-inst["y0"] / mu)
+        s.iterate(20)
+        g = s.solution()
+        r = s.residuals()
+    for k, ref in (("x1", inst["x0"]), ("x2", inst["x0"]), ("lam", inst["s0"]), ("nu", -inst["y0"] / mu)):
+        assert np.abs(g[k] - ref).max() <= 1e-10 * (1 + np.abs(ref).max()), k
+    assert r["kkt"] < 1e-11
+
+
+def test_reaches_1e4_and_stops():
+    inst = I.lp_instance(500, 1000, 5, seed=0)
+    with Standard.from_instance(inst, cg_iters=20, cg_tol=1e-8, eps=1e-4, check_every=10) as s:
+        while not s.iterate(1000):
+            pass
+        r = s.residuals()
+        it = r["iter"]
+        s.iterate(50)                         # no-op once converged
+        assert s.residuals()["iter"] == it
+    _say(f"standard small LP: {it} iterations, {r['cg_steps']} CG steps, kkt {r['kkt']:.3e}")
+    assert r["status"] == "converged" and r["kkt"] <= 1e-4 and it % 10 == 0
+    assert r["pobj"] == pytest.approx(inst["p_star"], rel=1e-3)
+
+
+def test_max_iter_status():
+    inst = I.lp_instance(300, 600, 4, seed=44)
+    with Standard.from_instance(inst, cg_iters=2, eps=1e-12, max_iter=25) as s:
+        assert s.iterate(100)
+        r = s.residuals()
+    assert r["status"] == "max_iter" and r["iter"] == 25
+
+
+def test_full_size_lp_matches_oracle():
+    """The 1e6 x 2e6 LP in the benchmark's launch shape: 3 iterations, every
+    entry against the oracle."""
+    inst = I.config_instance("lp_large")
+    errs, _, _ = _compare(inst, 3, cg_iters=2)
+    assert max(errs.values()) <= 1e-9, errs
