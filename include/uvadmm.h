@@ -110,7 +110,9 @@ typedef struct {
     int32_t criterion;    /* UV_CRIT_KKT or UV_CRIT_INF (see uv_residuals) */
     double eps_abs;       /* absolute tolerance of UV_CRIT_INF */
     int32_t slab_kernel;  /* slab passes: 0 = automatic (= 1), 1 = 64-segment
-                             chunks per wavefront, 2 = lane group per segment */
+                             chunks per wavefront (four 64-entry steps in
+                             flight), 2 = lane group per segment, 3 = chunks
+                             with eight steps in flight */
 } uv_opts;
 
 /* Stopping tests (Section V): UV_CRIT_KKT stops when kkt <= eps_kkt (the

@@ -554,6 +554,7 @@ struct uv_solver {
     int E_row = 4, E_col = 4;   // gathers in flight per lane
     int S_row = 1, S_col = 1;   // XCD slabs of x (row pass) and of u (column pass)
     bool chunked = true;        // slab passes by 64-segment chunks (else lane groups)
+    bool batch8 = false;        // chunk batches of eight 64-entry steps (else four)
     int *srp = nullptr, *sci = nullptr;  // row-pass slab copy (S_row * m + 1 offsets)
     void *sva = nullptr;
     int *scp = nullptr, *sri = nullptr;  // column-pass slab copy (S_col * n + 1 offsets)
@@ -599,6 +600,15 @@ bool slabs_ok(int S) { return S == 0 || S == 1 || S == 2 || S == 4 || S == 8; }
 
 // ---- launch helpers (dispatch on precision, lanes L and unroll E) ----
 
+// Chunked slab product with the batch depth chosen at create time.
+template <typename T, int S>
+void seg_chunk_launch(const uv_solver *s, unsigned grid, hipStream_t st, int nseg, const int *ptr, const int *idx,
+                      const T *val, const T *vec, T *out, const int *skip)
+{
+    if (s->batch8) k_seg_chunk<T, T, S, 8><<<grid, kWG, 0, st>>>(nseg, ptr, idx, val, vec, out, skip);
+    else k_seg_chunk<T, T, S, 4><<<grid, kWG, 0, st>>>(nseg, ptr, idx, val, vec, out, skip);
+}
+
 template <typename T, int L, int E, int S>
 void row_slab_launch(uv_solver *s, hipStream_t st, int mode)
 {
@@ -607,11 +617,11 @@ void row_slab_launch(uv_solver *s, hipStream_t st, int mode)
     if (s->chunked) {
         const unsigned gk = S * blocks_for(s->m, kWG);
         const bool ign = mode == 2;
-        k_seg_chunk<T, T, S><<<gk, kWG, 0, st>>>(s->m, s->srp, s->sci, (const T *)s->sva, (const T *)s->x,
-                                                 (T *)s->P_row, ign ? nullptr : &s->st->done);
+        seg_chunk_launch<T, S>(s, gk, st, s->m, s->srp, s->sci, (const T *)s->sva, (const T *)s->x, (T *)s->P_row,
+                               ign ? nullptr : &s->st->done);
         if (mode == 1)
-            k_seg_chunk<T, T, S><<<gk, kWG, 0, st>>>(s->m, s->srp, s->sci, (const T *)s->sva, (const T *)s->z,
-                                                     (T *)s->P_row + (size_t)S * s->m, &s->st->done);
+            seg_chunk_launch<T, S>(s, gk, st, s->m, s->srp, s->sci, (const T *)s->sva, (const T *)s->z,
+                                   (T *)s->P_row + (size_t)S * s->m, &s->st->done);
     }
 #define UV_SLAB_ARGS s->m, s->srp, s->sci, (const T *)s->sva, (const T *)s->x, (const T *)s->z, (T *)s->P_row
 #define UV_COMB_ARGS                                                                                       \
@@ -676,8 +686,8 @@ template <typename T, int L, int E, int S>
 void col_slab_launch(uv_solver *s, hipStream_t st)
 {
     if (s->chunked) {
-        k_seg_chunk<T, T, S><<<S * blocks_for(s->n, kWG), kWG, 0, st>>>(
-            s->n, s->scp, s->sri, (const T *)s->svc, (const T *)s->u, (T *)s->P_col, &s->st->done);
+        seg_chunk_launch<T, S>(s, S * blocks_for(s->n, kWG), st, s->n, s->scp, s->sri, (const T *)s->svc,
+                               (const T *)s->u, (T *)s->P_col, &s->st->done);
     } else {
         const unsigned g = S * blocks_for(s->n, kWG / L);
         k_col_slab<T, L, E, S><<<g, kWG, 0, st>>>(s->n, s->scp, s->sri, (const T *)s->svc, (const T *)s->u,
@@ -785,8 +795,8 @@ template <int S>
 void res_col_slab_launch(uv_solver *s, hipStream_t st)
 {
     const unsigned g = blocks_for(s->n, kWG);
-    k_seg_chunk<double, double, S><<<S * g, kWG, 0, st>>>(s->n, s->scp, s->sri, (const double *)s->svc, s->lam,
-                                                          (double *)s->P_col, nullptr);
+    seg_chunk_launch<double, S>(s, S * g, st, s->n, s->scp, s->sri, (const double *)s->svc, s->lam,
+                                (double *)s->P_col, nullptr);
     k_res_col_slab<double, S><<<g, kWG, 0, st>>>(s->n, (const double *)s->P_col, s->c64, s->delta,
                                                  (const double *)s->z, s->part_col, (int)g);
 }
@@ -847,7 +857,7 @@ int validate(const uv_csr *A, const double *b, const double *c, const uv_cones *
     if (!lanes_ok(o->lanes_row) || !lanes_ok(o->lanes_col)) return UV_EINVAL;
     if (!unroll_ok(o->unroll_row) || !unroll_ok(o->unroll_col)) return UV_EINVAL;
     if (!slabs_ok(o->slabs_row) || !slabs_ok(o->slabs_col)) return UV_EINVAL;
-    if (o->slab_kernel < 0 || o->slab_kernel > 2) return UV_EINVAL;
+    if (o->slab_kernel < 0 || o->slab_kernel > 3) return UV_EINVAL;
     if (A->nnz > 0 && (!A->col_idx || !A->val)) return UV_EINVAL;
     if (!A->row_ptr) return UV_EINVAL;
     if (A->nnz >= ((int64_t)1 << 31)) return UV_ETOOBIG;
@@ -1108,6 +1118,7 @@ int solver_create(const uv_csr *A, const double *b, const double *c, const uv_co
     s->E_row = o.unroll_row ? o.unroll_row : 2;
     s->E_col = o.unroll_col ? o.unroll_col : 2;
     s->chunked = o.slab_kernel != 2;
+    s->batch8 = o.slab_kernel == 3;
     rc = setup(s, A, b, c, K);
     if (rc == UV_OK) rc = solver_set_start(s, nullptr, nullptr, nullptr, nullptr);
     if (rc == UV_OK && s->o.use_graph) rc = build_graph(s);

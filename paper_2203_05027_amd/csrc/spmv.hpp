@@ -22,11 +22,12 @@ using uv::kWG;
 // S * ceil(nseg / kWG) workgroups; workgroup w works on slab w % S.
 constexpr int kChunkCap = 512;  // LDS products per wavefront and round
 
-template <typename T, typename TV, int S>
+template <typename T, typename TV, int S, int U = 4>
 __global__ void __launch_bounds__(kWG)
 k_seg_chunk(int nseg, const int *__restrict__ ptr, const int *__restrict__ idx, const TV *__restrict__ val,
             const T *__restrict__ vec, T *__restrict__ out, const int *skip)
 {
+    static_assert(kChunkCap % (64 * U) == 0, "a round holds whole batches");
     if (skip && *skip) return;  // a device flag (stop, or nothing left to do)
     __shared__ T buf[kWG / 64][kChunkCap];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -43,21 +44,21 @@ k_seg_chunk(int nseg, const int *__restrict__ ptr, const int *__restrict__ idx, 
     T acc = 0;
     for (int P0 = E0; P0 < E1; P0 += kChunkCap) {
         const int P1 = min(P0 + kChunkCap, E1);
-        for (int b = P0; b < P1; b += 256) {
-            int j[4];
-            TV v[4];
+        for (int b = P0; b < P1; b += 64 * U) {  // U coalesced 64-entry steps in flight
+            int j[U];
+            TV v[U];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < U; ++u) {
                 const int k = b + u * 64 + lane;
                 const int kk = k < P1 ? k : P1 - 1;
                 j[u] = __builtin_nontemporal_load(idx + kk);
                 v[u] = __builtin_nontemporal_load(val + kk);
             }
-            T g[4];
+            T g[U];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) g[u] = vec[j[u]];
+            for (int u = 0; u < U; ++u) g[u] = vec[j[u]];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < U; ++u) {
                 const int k = b + u * 64 + lane;
                 if (k < P1) buf[w][k - P0] = (T)v[u] * g[u];
             }

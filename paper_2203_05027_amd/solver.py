@@ -160,7 +160,7 @@ class Solver:
         o.unroll_row, o.unroll_col = int(unroll_row), int(unroll_col)
         o.slabs_row, o.slabs_col = int(slabs_row), int(slabs_col)
         o.criterion = {"kkt": 0, "inf": 1}[criterion]
-        o.slab_kernel = {"auto": 0, "chunked": 1, "lanes": 2}[slab_kernel]
+        o.slab_kernel = {"auto": 0, "chunked": 1, "lanes": 2, "chunked8": 3}[slab_kernel]
         o.eps_abs = float(eps_abs)
         o.use_graph = 1 if use_graph else 0
         self.precision = precision

@@ -92,7 +92,7 @@ def test_launch_shapes(lanes, unroll, graph):
 
 
 @pytest.mark.parametrize("slabs", [(2, 2), (8, 4), (4, 8), (8, 1), (1, 8)])
-@pytest.mark.parametrize("kernel", ["chunked", "lanes"])
+@pytest.mark.parametrize("kernel", ["chunked", "chunked8", "lanes"])
 def test_xcd_slabs(slabs, kernel):
     """Slab-split passes (forced on a small ragged problem) against the oracle,
     with the fused residual check inside the chunk."""
@@ -104,7 +104,8 @@ def test_xcd_slabs(slabs, kernel):
         assert abs(gr[k] - orr[k]) <= 1e-9 * max(abs(orr[k]), 1e-12), k
 
 
-def test_chunked_long_segments():
+@pytest.mark.parametrize("kernel", ["chunked", "chunked8"])
+def test_chunked_long_segments(kernel):
     """Segments longer than a wavefront's LDS round (dense rows and columns)
     and empty ones, through the chunked slab kernel."""
     base = I.lp_instance(700, 1500, 3, seed=25)
@@ -120,7 +121,7 @@ def test_chunked_long_segments():
     np.cumsum(np.bincount(rr, minlength=700), out=row_ptr[1:])
     inst = dict(base, row_ptr=row_ptr, col_idx=cc.astype(np.int32), val=A[rr, cc], nnz=int(rr.size),
                 b=A @ base["x0"])
-    g, o, _, _ = run_pair(inst, 200, slabs_row=4, slabs_col=2, check_every=6)
+    g, o, _, _ = run_pair(inst, 200, slabs_row=4, slabs_col=2, check_every=6, slab_kernel=kernel)
     assert_parity(g, o)
 
 
