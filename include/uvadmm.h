@@ -110,9 +110,9 @@ typedef struct {
     int32_t criterion;    /* UV_CRIT_KKT or UV_CRIT_INF (see uv_residuals) */
     double eps_abs;       /* absolute tolerance of UV_CRIT_INF */
     int32_t slab_kernel;  /* slab passes: 0 = automatic (= 1), 1 = 64-segment
-                             chunks per wavefront (four 64-entry steps in
+                             chunks per wavefront (eight 64-entry steps in
                              flight), 2 = lane group per segment, 3 = chunks
-                             with eight steps in flight */
+                             with four steps in flight */
 } uv_opts;
 
 /* Stopping tests (Section V): UV_CRIT_KKT stops when kkt <= eps_kkt (the
@@ -375,6 +375,21 @@ int standard_solution(uv_standard *h, double *x1, double *x2, double *lam,
 /* Slab counts of the row and column products (either may be NULL). */
 int standard_launch_shape(uv_standard *h, int32_t *slabs_row, int32_t *slabs_col);
 void standard_destroy(uv_standard *h);
+
+/* ------------------------------------------------------------------------
+ * Measurement: random-gather rate of the chip, the practical bound of the
+ * sweep's sparse products (each stored entry of A is one gather of a vector
+ * entry at an address no cache line is shared with).  Streams nnz
+ * (int32 index, value) pairs, gathers a table of table_len entries
+ * (fp64 != 0: FP64, else FP32) at uniform random positions, workgroup w
+ * confined to table part w % slabs (slabs in 1..8, table_len / slabs
+ * entries each), eight pairs per thread, one sum stored per thread.  *ms
+ * receives the average kernel duration over reps launches after one
+ * warm-up.  Allocates and frees its own device buffers (about
+ * 12 nnz + 8 table_len bytes); nnz in [1, 2^31), else UV_EINVAL.
+ * ------------------------------------------------------------------------ */
+int probe_gather(int64_t nnz, int64_t table_len, int32_t slabs, int32_t fp64,
+                 int32_t reps, uint64_t seed, double *ms);
 
 /* ------------------------------------------------------------------------
  * Learned warm start: dense kernels.  Pointers marked _dev are DEVICE

@@ -554,7 +554,7 @@ struct uv_solver {
     int E_row = 4, E_col = 4;   // gathers in flight per lane
     int S_row = 1, S_col = 1;   // XCD slabs of x (row pass) and of u (column pass)
     bool chunked = true;        // slab passes by 64-segment chunks (else lane groups)
-    bool batch8 = false;        // chunk batches of eight 64-entry steps (else four)
+    bool batch8 = true;         // chunk batches of eight 64-entry steps (else four)
     int *srp = nullptr, *sci = nullptr;  // row-pass slab copy (S_row * m + 1 offsets)
     void *sva = nullptr;
     int *scp = nullptr, *sri = nullptr;  // column-pass slab copy (S_col * n + 1 offsets)
@@ -1118,7 +1118,7 @@ int solver_create(const uv_csr *A, const double *b, const double *c, const uv_co
     s->E_row = o.unroll_row ? o.unroll_row : 2;
     s->E_col = o.unroll_col ? o.unroll_col : 2;
     s->chunked = o.slab_kernel != 2;
-    s->batch8 = o.slab_kernel == 3;
+    s->batch8 = o.slab_kernel != 3;
     rc = setup(s, A, b, c, K);
     if (rc == UV_OK) rc = solver_set_start(s, nullptr, nullptr, nullptr, nullptr);
     if (rc == UV_OK && s->o.use_graph) rc = build_graph(s);

@@ -160,7 +160,7 @@ class Solver:
         o.unroll_row, o.unroll_col = int(unroll_row), int(unroll_col)
         o.slabs_row, o.slabs_col = int(slabs_row), int(slabs_col)
         o.criterion = {"kkt": 0, "inf": 1}[criterion]
-        o.slab_kernel = {"auto": 0, "chunked": 1, "lanes": 2, "chunked8": 3}[slab_kernel]
+        o.slab_kernel = {"auto": 0, "chunked": 1, "lanes": 2, "chunked4": 3}[slab_kernel]
         o.eps_abs = float(eps_abs)
         o.use_graph = 1 if use_graph else 0
         self.precision = precision
@@ -675,3 +675,20 @@ class Standard:
         a, b = ctypes.c_int32(), ctypes.c_int32()
         _check(lib().standard_launch_shape(self._h, ctypes.byref(a), ctypes.byref(b)), "standard_launch_shape")
         return {"slabs_row": a.value, "slabs_col": b.value}
+
+
+def probe_gather(nnz: int, table_len: int, slabs: int = 1, fp64: bool = True, reps: int = 20,
+                 seed: int = 1) -> float:
+    """Average duration (ms) of the random-gather probe kernel: nnz streamed
+    (index, value) pairs, each gathering a table entry at a random position,
+    workgroups confined to one of `slabs` table parts."""
+    L = lib()
+    if not hasattr(L, "_probe_bound"):
+        L.probe_gather.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
+        L.probe_gather.restype = ctypes.c_int
+        L._probe_bound = True
+    ms = ctypes.c_double()
+    _check(L.probe_gather(int(nnz), int(table_len), int(slabs), 1 if fp64 else 0, int(reps), int(seed),
+                          ctypes.byref(ms)), "probe_gather")
+    return ms.value

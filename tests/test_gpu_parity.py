@@ -92,7 +92,7 @@ def test_launch_shapes(lanes, unroll, graph):
 
 
 @pytest.mark.parametrize("slabs", [(2, 2), (8, 4), (4, 8), (8, 1), (1, 8)])
-@pytest.mark.parametrize("kernel", ["chunked", "chunked8", "lanes"])
+@pytest.mark.parametrize("kernel", ["chunked", "chunked4", "lanes"])
 def test_xcd_slabs(slabs, kernel):
     """Slab-split passes (forced on a small ragged problem) against the oracle,
     with the fused residual check inside the chunk."""
@@ -104,7 +104,7 @@ def test_xcd_slabs(slabs, kernel):
         assert abs(gr[k] - orr[k]) <= 1e-9 * max(abs(orr[k]), 1e-12), k
 
 
-@pytest.mark.parametrize("kernel", ["chunked", "chunked8"])
+@pytest.mark.parametrize("kernel", ["chunked", "chunked4"])
 def test_chunked_long_segments(kernel):
     """Segments longer than a wavefront's LDS round (dense rows and columns)
     and empty ones, through the chunked slab kernel."""

@@ -71,7 +71,7 @@ def test_given_state_matches_oracle():
 
 def test_tolerance_mode_matches_oracle():
     inst = I.lp_instance(500, 1000, 5, seed=43)
-    errs, ro, rg = _compare(inst, 150, cg_iters=25, cg_tol=1e-7)
+    errs, ro, rg = _compare(inst, 150, cg_iters=25, cg_tol=1e-3)
     assert max(errs.values()) <= 1e-9, errs
     # the stop decisions are taken in FP64 on both sides; sums differ only in order
     assert abs(rg["cg_steps"] - ro["cg_steps"]) <= 0.01 * ro["cg_steps"]
