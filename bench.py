@@ -160,6 +160,22 @@ def gather_floor(m, n, nnz, slabs_row, slabs_col, fp64=True):
     return {"row": probe_gather(nnz, n, slabs_row, fp64), "col": probe_gather(nnz, m, slabs_col, fp64)}
 
 
+def gather_sweep(nnz=20_000_000):
+    """The gather probe over table sizes (FP64 and FP32 entries) and slab
+    counts, 2e7 pairs each: where the gather rate falls off with the table
+    part a workgroup reads (the per-XCD L2 holds 4 MiB)."""
+    from paper_2203_05027_amd.solver import probe_gather
+    print(f"# random-gather probe: {nnz} (int32 index, value) pairs, one random table read each; ms per launch")
+    print(f"# {'table_MiB_f64':>13s} {'slabs':>5s} {'part_MiB':>8s} {'ms_f64':>8s} {'Ggather/s':>9s} {'ms_f32':>8s} {'Ggather/s':>9s}")
+    for mib in (2, 4, 8, 16, 32, 128):
+        for S in (1, 2, 4, 8):
+            tl = mib * (1 << 20) // 8
+            a = probe_gather(nnz, tl, S, True)
+            b = probe_gather(nnz, tl, S, False)
+            print(f"  {mib:13d} {S:5d} {mib / S:8.2f} {a:8.4f} {nnz / a / 1e6:9.1f} {b:8.4f} {nnz / b / 1e6:9.1f}",
+                  flush=True)
+
+
 def standard_block(inst, mu, cg_iters, cg_tol, check_every, cap_s, uv_ttk_s=None):
     """Standard two-block ADMM with a warm-started CG solve of the block
     system (the baseline the decomposition replaces) on the same instance and
@@ -320,7 +336,7 @@ def main():
     ap.add_argument("--no-ttk", action="store_true", help="skip the time-to-1e-4 runs")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-workload block")
     ap.add_argument("--no-standard", action="store_true", help="skip the standard ADMM + CG baseline")
-    ap.add_argument("--std-cg-iters", type=int, default=3, help="baseline: CG steps per iteration at most")
+    ap.add_argument("--std-cg-iters", type=int, default=2, help="baseline: CG steps per iteration at most")
     ap.add_argument("--std-cg-tol", type=float, default=0.0, help="baseline: CG stop, ||r|| <= tol (1 + ||b||)")
     ap.add_argument("--std-cap-s", type=float, default=60.0, help="baseline: wall-time cap of its solve")
     ap.add_argument("--train", type=int, default=20_000, help="parametric: training members")
@@ -329,6 +345,8 @@ def main():
     ap.add_argument("--train-eps", type=float, default=1e-3, help="parametric: tolerance of the training solves")
     ap.add_argument("--train-cap", type=int, default=20_000, help="parametric: iteration cap of training solves")
     ap.add_argument("--plain", type=int, default=8, help="members solved by the plain single-problem solver")
+    ap.add_argument("--gather-sweep", action="store_true",
+                    help="only print the random-gather probe over table sizes and slab counts")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -350,6 +368,8 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: 3 x {args.calib_copy_mib} MiB")
         del src, dst
+    if args.gather_sweep:
+        return gather_sweep()
     if args.workload == "lp_parametric":
         return bench_parametric(args)
     if args.workload == "lp_batched":
