@@ -105,7 +105,8 @@ typedef struct {
                              (0 = automatic; else 1, 2, 4 or 8) */
     int32_t unroll_col;   /* same for the A'u pass */
     int32_t slabs_row;    /* XCD slabs of x in the A x pass: 0 = automatic
-                             (about 2 MiB of x per slab), 1 = none, 2, 4, 8 */
+                             (none up to 2 MiB of x, two up to 12 MiB, else
+                             four), 1 = none, 2, 4, 8 */
     int32_t slabs_col;    /* XCD slabs of u in the A'u pass (same values) */
     int32_t criterion;    /* UV_CRIT_KKT or UV_CRIT_INF (see uv_residuals) */
     double eps_abs;       /* absolute tolerance of UV_CRIT_INF */

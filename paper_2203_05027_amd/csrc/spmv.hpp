@@ -75,16 +75,15 @@ k_seg_chunk(int nseg, const int *__restrict__ ptr, const int *__restrict__ idx, 
     if (gl < nseg) out[(size_t)sl * nseg + gl] = acc;
 }
 
-// Slabs for a gathered vector of `bytes`: none up to 2 MiB, else at least
-// two and about 4 MiB each, at most 4 (measured on the 1e6 x 2e6 LP: FP64
-// best at 4 slabs of x and 2 of u, FP32 at 2 and 2; more slabs add partial
-// traffic faster than they save gathers).
+// Slabs for a gathered vector of `bytes`: none up to 2 MiB, two up to
+// 12 MiB, else four (measured with the eight-step chunk kernel: on the
+// 1e6 x 2e6 LP, FP64 x (16 MiB) best in 4 slabs and u (8 MiB) in 2; on the
+// 1e5-cone SOCP, x (21 MiB) in 4 and u (10.6 MiB) in 2; more slabs add
+// partial traffic and shorter segments faster than they save gathers).
 inline int pick_slabs(size_t bytes)
 {
     if (bytes <= (2u << 20)) return 1;
-    int S = 2;
-    while (S < 4 && bytes > (size_t)S * (4u << 20)) S <<= 1;
-    return S;
+    return bytes <= (12u << 20) ? 2 : 4;
 }
 
 }  // namespace
