@@ -409,6 +409,11 @@ int gemm_f32(int32_t M, int32_t N, int32_t K, const float *A_dev, int64_t a_rs,
 int add_row_vector(int64_t N, int64_t D, float *Y_dev, int64_t ld,
                    const float *v_dev, void *stream);
 
+/* Y (N x D, leading dimension ld, device) *= v (D, device) column-wise on
+ * every row (the standardisation of PCA coefficients). */
+int mul_row_vector(int64_t N, int64_t D, float *Y_dev, int64_t ld,
+                   const float *v_dev, void *stream);
+
 /* Principal components of the rows of Y (N x D, leading dimension ld,
  * device; CENTERED IN PLACE): mean_dev (D), basis_dev (k x D, orthonormal
  * rows, the top-k right singular vectors of the centered Y) and sv (k

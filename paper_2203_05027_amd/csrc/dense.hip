@@ -118,6 +118,15 @@ k_add_row(int64_t N, int64_t D, float *__restrict__ Y, int64_t ld, const float *
     Y[i * ld + j] += v[j];
 }
 
+__global__ void __launch_bounds__(256)
+k_mul_row(int64_t N, int64_t D, float *__restrict__ Y, int64_t ld, const float *__restrict__ v)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= N * D) return;
+    const int64_t i = t / D, j = t % D;
+    Y[i * ld + j] *= v[j];
+}
+
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 int gemm(hipStream_t st, int M, int N, int K, const float *A, int64_t a_rs, int64_t a_cs, const float *B,
@@ -240,6 +249,15 @@ int add_row_vector(int64_t N, int64_t D, float *Y, int64_t ld, const float *v, v
     if (!Y || !v || N < 0 || D < 0) return UV_EINVAL;
     if (N * D == 0) return UV_OK;
     k_add_row<<<nblk(N * D, 256), 256, 0, (hipStream_t)stream>>>(N, D, Y, ld, v);
+    if (hipGetLastError() != hipSuccess) return UV_EHIP;
+    return hipStreamSynchronize((hipStream_t)stream) == hipSuccess ? UV_OK : UV_EHIP;
+}
+
+int mul_row_vector(int64_t N, int64_t D, float *Y, int64_t ld, const float *v, void *stream)
+{
+    if (!Y || !v || N < 0 || D < 0 || (N > 0 && ld < D)) return UV_EINVAL;
+    if (N * D == 0) return UV_OK;
+    k_mul_row<<<nblk(N * D, 256), 256, 0, (hipStream_t)stream>>>(N, D, Y, ld, v);
     if (hipGetLastError() != hipSuccess) return UV_EHIP;
     return hipStreamSynchronize((hipStream_t)stream) == hipSuccess ? UV_OK : UV_EHIP;
 }

@@ -24,6 +24,8 @@ def _bind():
     L.gemm_f32.restype = ctypes.c_int
     L.add_row_vector.argtypes = [i64, i64, P, i64, P, P]
     L.add_row_vector.restype = ctypes.c_int
+    L.mul_row_vector.argtypes = [i64, i64, P, i64, P, P]
+    L.mul_row_vector.restype = ctypes.c_int
     L.pca_fit.argtypes = [P, i64, i64, i64, i32, i32, i32, ctypes.c_uint64, P, P, P, P]
     L.pca_fit.restype = ctypes.c_int
     L.uvla_sym_eig.argtypes = [i32, P, P, P]
@@ -86,6 +88,12 @@ def gemm(A, B, C=None, alpha=1.0, beta=0.0, transA=False, transB=False):
 def add_row_vector(Y, v):
     L = _bind()
     _check(L.add_row_vector(Y.shape[0], Y.shape[1], _dp(Y), Y.shape[1], _dp(v), None), "add_row_vector")
+
+
+def mul_row_vector(Y, v):
+    """Y[i, j] *= v[j] on every row (contiguous FP32 GPU tensors)."""
+    L = _bind()
+    _check(L.mul_row_vector(Y.shape[0], Y.shape[1], _dp(Y), Y.shape[1], _dp(v), None), "mul_row_vector")
 
 
 def pca_fit(Y, k: int, oversample: int = 32, power_iters: int = 2, seed: int = 0):

@@ -77,8 +77,10 @@ class WarmStart:
         self.mean, self.basis, self.sv = learn.pca_fit(Y, self.k, oversample, power_iters, self.seed)
         coef = learn.gemm(Y, self.basis, transB=True)             # (Y - mean) basis'
         # standardize: each coefficient has variance sv^2 / N
-        self.scale = torch.from_numpy(np.maximum(self.sv / np.sqrt(Y.shape[0]), 1e-12).astype(np.float32)).cuda()
-        return coef / self.scale
+        scale = np.maximum(self.sv / np.sqrt(Y.shape[0]), 1e-12).astype(np.float32)
+        self.scale = torch.from_numpy(scale).cuda()
+        learn.mul_row_vector(coef, torch.from_numpy((1.0 / scale).astype(np.float32)).cuda())
+        return coef
 
     # 3. network --------------------------------------------------------
     def train(self, thetas, targets, epochs=200, batch=256, lr=1e-3, lr_min=1e-5):
@@ -115,67 +117,102 @@ class WarmStart:
         outs = []
         for g in range(0, len(X), self.net.max_batch):
             outs.append(self.net.forward(X[g: g + self.net.max_batch].contiguous()))
-        coef = (torch.cat(outs)[:n] * self.scale).contiguous()
+        coef = torch.cat(outs)[:n].contiguous()
+        learn.mul_row_vector(coef, self.scale)
         Yhat = learn.gemm(coef, self.basis)                        # coef basis
         learn.add_row_vector(Yhat, self.mean)
         return Yhat
 
     def model_error(self, Yhat, Ytrue):
-        """Relative error of predictions against solutions (per row, median)."""
-        d = (Yhat - Ytrue).norm(dim=1) / Ytrue.norm(dim=1).clamp_min(1e-30)
-        return float(d.median())
+        """Relative error of predictions against solutions (per row, median;
+        evaluated on the host)."""
+        a, t = Yhat.cpu().numpy().astype(np.float64), Ytrue.cpu().numpy().astype(np.float64)
+        d = np.linalg.norm(a - t, axis=1) / np.maximum(np.linalg.norm(t, axis=1), 1e-30)
+        return float(np.median(d))
 
     # 4. warm vs cold ---------------------------------------------------
-    def compare(self, thetas, eps=1e-4, max_iter=100_000, parts="both"):
-        """Iterations and time to eps from cold and from learned starts for
-        the same members; a warm start that fails to converge falls back to
-        a cold solve (counted in its time and iterations)."""
+    def _solve_group(self, F, b, stats, g0, fallback_b=None):
+        """Iterate the family solver to its stop; record iterations and
+        convergence into stats[...][g0:g0+nb]; a member left unconverged is
+        re-solved cold when fallback_b is given (its iterations added)."""
+        torch = self.torch
+        nb = len(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while F.iterate(2000):
+            pass
+        r = F.residuals()
+        stats["iters"][g0:g0 + nb] = [x["iter"] for x in r]
+        stats["converged"][g0:g0 + nb] = [x["status"] == "converged" for x in r]
+        ok = stats["converged"][g0:g0 + nb]
+        if fallback_b is not None and not ok.all():
+            F.set_rhs(fallback_b)
+            while F.iterate(2000):
+                pass
+            r = F.residuals()
+            for q in np.nonzero(~ok)[0]:
+                stats["iters"][g0 + q] += r[q]["iter"]
+                stats["converged"][g0 + q] = r[q]["status"] == "converged"
+        torch.cuda.synchronize()
+        stats["seconds"] += time.perf_counter() - t0
+
+    def compare(self, thetas, eps=1e-4, max_iter=100_000, parts=("both",), projection=False):
+        """Iterations and time to eps for the same members from the cold
+        start and from learned starts (one per entry of parts: "both",
+        "primal" or "dual" halves of the prediction used); a warm start that
+        fails to converge falls back to a cold solve (counted in its time and
+        iterations).  projection=True adds the start a perfect network would
+        give with this basis: the cold solution projected on the PCA basis.
+        Returns {variant: {"iters", "converged", "seconds"}} plus
+        "predict_seconds"."""
         torch = self.torch
         N = len(thetas)
-        cold_it = np.zeros(N, np.int64)
-        warm_it = np.zeros(N, np.int64)
-        cold_ok = np.zeros(N, bool)
-        warm_ok = np.zeros(N, bool)
-        t_cold = t_warm = t_pred = 0.0
+
+        def new():
+            return {"iters": np.zeros(N, np.int64), "converged": np.zeros(N, bool), "seconds": 0.0}
+
+        out = {"cold": new()}
+        for p in parts:
+            out[p] = new()
+        if projection:
+            out["projection"] = new()
+        t_pred = 0.0
+        if projection:
+            mb = learn.gemm(self.mean.reshape(1, -1).contiguous(), self.basis, transB=True)
+            neg_mb = torch.from_numpy(-mb.cpu().numpy().reshape(-1)).cuda()
         with self._family(eps, max_iter) as F:
+            Ysol = torch.empty((self.B, self.D), dtype=torch.float32, device="cuda")
             for g0 in range(0, N, self.B):
                 th = thetas[g0: g0 + self.B]
                 nb = len(th)
                 b = self.fam.b_many(th)
                 F.set_rhs(b)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                while F.iterate(2000):
-                    pass
-                t_cold += time.perf_counter() - t0
-                r = F.residuals()
-                cold_it[g0:g0 + nb] = [x["iter"] for x in r]
-                cold_ok[g0:g0 + nb] = [x["status"] == "converged" for x in r]
-                F.set_rhs(b)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                Yhat = self.predict(th)
-                F.set_start_predicted(Yhat.data_ptr(), self.D, parts)
-                torch.cuda.synchronize()
-                t_pred += time.perf_counter() - t0
-                while F.iterate(2000):
-                    pass
-                t_warm += time.perf_counter() - t0
-                r = F.residuals()
-                warm_it[g0:g0 + nb] = [x["iter"] for x in r]
-                warm_ok[g0:g0 + nb] = [x["status"] == "converged" for x in r]
-                if not warm_ok[g0:g0 + nb].all():           # fallback: cold solve
+                self._solve_group(F, b, out["cold"], g0)
+                if projection:
+                    F.solution_device(Ysol.data_ptr(), self.D)
+                Yhat = None
+                for p in parts:
                     F.set_rhs(b)
+                    torch.cuda.synchronize()
                     t0 = time.perf_counter()
-                    while F.iterate(2000):
-                        pass
-                    t_warm += time.perf_counter() - t0
-                    r = F.residuals()
-                    for q in np.nonzero(~warm_ok[g0:g0 + nb])[0]:
-                        warm_it[g0 + q] += r[q]["iter"]
-                        warm_ok[g0 + q] = r[q]["status"] == "converged"
-                self.log(f"compare {g0 + nb}/{N}: cold median {int(np.median(cold_it[g0:g0+nb]))} "
-                         f"warm median {int(np.median(warm_it[g0:g0+nb]))}")
-        return {"cold_iters": cold_it, "warm_iters": warm_it, "cold_converged": cold_ok,
-                "warm_converged": warm_ok, "cold_seconds": t_cold, "warm_seconds": t_warm,
-                "predict_seconds": t_pred}
+                    if Yhat is None:
+                        Yhat = self.predict(th)
+                    F.set_start_predicted(Yhat.data_ptr(), self.D, p)
+                    torch.cuda.synchronize()
+                    dt = time.perf_counter() - t0
+                    t_pred += dt
+                    out[p]["seconds"] += dt
+                    self._solve_group(F, b, out[p], g0, fallback_b=b)
+                if projection:
+                    # coefficients (Y - mean) basis' = Y basis' - mean basis', then back
+                    coef = learn.gemm(Ysol[:nb].contiguous(), self.basis, transB=True)
+                    learn.add_row_vector(coef, neg_mb)
+                    Yp = learn.gemm(coef, self.basis)
+                    learn.add_row_vector(Yp, self.mean)
+                    F.set_rhs(b)
+                    F.set_start_predicted(Yp.data_ptr(), self.D, "both")
+                    self._solve_group(F, b, out["projection"], g0, fallback_b=b)
+                self.log(f"compare {g0 + nb}/{N}: " + ", ".join(
+                    f"{k} median {int(np.median(v['iters'][g0:g0 + nb]))}" for k, v in out.items()))
+        out["predict_seconds"] = t_pred
+        return out

@@ -32,9 +32,14 @@ def test_learned_start_beats_cold_start():
     assert hist[-1] < 0.5 * hist[0]
     err = ws.model_error(ws.predict(train[:128]), Yt[:128])
     say(f"train-set reconstruction error (median rel) {err:.3f}")
-    cmp = ws.compare(test, eps=1e-4, max_iter=200_000)
-    cm, wm = np.median(cmp["cold_iters"]), np.median(cmp["warm_iters"])
-    say(f"held-out: cold median {cm}, warm median {wm}, cold {cmp['cold_seconds']:.2f} s, "
-        f"warm {cmp['warm_seconds']:.2f} s")
-    assert cmp["cold_converged"].all() and cmp["warm_converged"].all()
+    cmp = ws.compare(test, eps=1e-4, max_iter=200_000, parts=("both", "dual"), projection=True)
+    cold, warm = cmp["cold"], cmp["both"]
+    cm, wm = np.median(cold["iters"]), np.median(warm["iters"])
+    say(f"held-out: cold median {cm}, warm median {wm}, dual-only median {np.median(cmp['dual']['iters'])}, "
+        f"basis projection of the solution median {np.median(cmp['projection']['iters'])}; "
+        f"cold {cold['seconds']:.2f} s, warm {warm['seconds']:.2f} s")
+    for v in ("cold", "both", "dual", "projection"):
+        assert cmp[v]["converged"].all(), v
     assert wm < cm
+    # the start a perfect network would give with this basis is at least as good
+    assert np.median(cmp["projection"]["iters"]) <= cm
