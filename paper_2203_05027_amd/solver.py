@@ -572,6 +572,30 @@ class Literal:
         return a.value, b.value
 
 
+def _bind_standard():
+    """Argument types of the standard-ADMM entry points (once)."""
+    L = lib()
+    if not hasattr(L, "_standard_bound"):
+        P, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.standard_create.argtypes = [ctypes.POINTER(UvCsr), P, P, ctypes.POINTER(UvOpts), i32, f64,
+                                      ctypes.POINTER(P)]
+        L.standard_create.restype = ctypes.c_int
+        L.standard_set_state.argtypes = [P, P, P, P]
+        L.standard_set_state.restype = ctypes.c_int
+        L.standard_iterate.argtypes = [P, i64, ctypes.POINTER(i32)]
+        L.standard_iterate.restype = ctypes.c_int
+        L.standard_residuals.argtypes = [P, ctypes.POINTER(UvResiduals), ctypes.POINTER(i64)]
+        L.standard_residuals.restype = ctypes.c_int
+        L.standard_solution.argtypes = [P, P, P, P, P, P]
+        L.standard_solution.restype = ctypes.c_int
+        L.standard_launch_shape.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.standard_launch_shape.restype = ctypes.c_int
+        L.standard_destroy.argtypes = [P]
+        L.standard_destroy.restype = None
+        L._standard_bound = True
+    return L
+
+
 class Standard:
     """Baseline: standard two-block ADMM with a warm-started CG solve of the
     block system every iteration (FP64, orthant cone), on the same sparse
@@ -580,25 +604,7 @@ class Standard:
     def __init__(self, m, n, row_ptr, col_idx, val, b, c, *, mu=1.0, cg_iters=10, cg_tol=0.0,
                  check_every=10, eps=1e-4, max_iter=0, slabs_row=0, slabs_col=0, use_graph=True,
                  stream=None):
-        L = lib()
-        if not hasattr(L, "_standard_bound"):
-            P, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
-            L.standard_create.argtypes = [ctypes.POINTER(UvCsr), P, P, ctypes.POINTER(UvOpts), i32, f64,
-                                          ctypes.POINTER(P)]
-            L.standard_create.restype = ctypes.c_int
-            L.standard_set_state.argtypes = [P, P, P, P]
-            L.standard_set_state.restype = ctypes.c_int
-            L.standard_iterate.argtypes = [P, i64, ctypes.POINTER(i32)]
-            L.standard_iterate.restype = ctypes.c_int
-            L.standard_residuals.argtypes = [P, ctypes.POINTER(UvResiduals), ctypes.POINTER(i64)]
-            L.standard_residuals.restype = ctypes.c_int
-            L.standard_solution.argtypes = [P, P, P, P, P, P]
-            L.standard_solution.restype = ctypes.c_int
-            L.standard_launch_shape.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
-            L.standard_launch_shape.restype = ctypes.c_int
-            L.standard_destroy.argtypes = [P]
-            L.standard_destroy.restype = None
-            L._standard_bound = True
+        L = _bind_standard()
         self.m, self.n = int(m), int(n)
         rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
         ci = np.ascontiguousarray(col_idx, dtype=np.int32)

@@ -146,3 +146,64 @@ def test_batch_rejects_bad_input():
     wide = dict(m=1, n=n, row_ptr=[0, 1], col_idx=[0], val=[1.0], b=[1.0], c=np.ones(n))
     assert _batch_err([good, wide], precision="mixed") == S.UV_ETOOBIG
     assert _batch_err([dict(wide, n=20_500, c=np.ones(20_500))], precision="fp64") == S.UV_ETOOBIG
+
+
+def _std_err(**kw):
+    a = dict(GOOD)
+    args = {k: kw.pop(k) for k in list(kw) if k in a}
+    a.update(args)
+    with pytest.raises(S.UvError) as ei:
+        S.Standard(a["m"], a["n"], a["rp"], a["ci"], a["va"], a["b"], a["c"], **kw)
+    return ei.value.code
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(rp=[1, 2, 3]), S.UV_EBADCSR),
+    (dict(ci=[2, 0, 1]), S.UV_EBADCSR),
+    (dict(ci=[0, 3, 1]), S.UV_EBADCSR),
+    (dict(mu=0.0), S.UV_EINVAL),
+    (dict(cg_iters=-1), S.UV_EINVAL),
+    (dict(cg_tol=-1e-3), S.UV_EINVAL),
+    (dict(cg_tol=float("inf")), S.UV_EINVAL),
+    (dict(check_every=0), S.UV_EINVAL),
+    (dict(slabs_row=3), S.UV_EINVAL),
+    (dict(slabs_col=8), S.UV_EINVAL),
+])
+def test_standard_rejects_bad_input(kw, code):
+    """The standard-ADMM baseline validates on the host before any device call."""
+    assert _std_err(**kw) == code
+
+
+def test_standard_rejects_mixed_precision():
+    rp = np.array([0, 2, 3], np.int64)
+    ci = np.array([0, 2, 1], np.int32)
+    va = np.array([1.0, 2.0, 3.0])
+    b, c = np.ones(2), np.ones(3)
+    csr = S.UvCsr(2, 3, 3, S._ptr(rp), S._ptr(ci), S._ptr(va))
+    o = S.default_opts()
+    o.precision = S.UV_MIXED
+    h = ctypes.c_void_p()
+    L = S._bind_standard()
+    assert L.standard_create(ctypes.byref(csr), S._ptr(b), S._ptr(c), ctypes.byref(o), 2, 0.0,
+                             ctypes.byref(h)) == S.UV_EINVAL and not h.value
+    assert L.standard_create(None, None, None, None, 2, 0.0, ctypes.byref(h)) == S.UV_EINVAL
+    assert L.standard_iterate(None, 1, None) == S.UV_EINVAL
+    assert L.standard_residuals(None, None, None) == S.UV_EINVAL
+    assert L.standard_solution(None, None, None, None, None, None) == S.UV_EINVAL
+    L.standard_destroy(None)
+
+
+@pytest.mark.parametrize("args", [(0, 100, 1, 1, 5), (1 << 31, 100, 1, 1, 5), (100, 100, 0, 1, 5),
+                                  (100, 100, 9, 1, 5), (100, 4, 8, 1, 5), (100, 100, 1, 1, 0)])
+def test_probe_rejects_bad_arguments(args):
+    with pytest.raises(S.UvError) as ei:
+        S.probe_gather(*args)
+    assert ei.value.code == S.UV_EINVAL
+
+
+def test_mul_row_vector_rejects_bad_arguments():
+    from paper_2203_05027_amd import learn
+    L = learn._bind()
+    assert L.mul_row_vector(2, 3, None, 3, None, None) == S.UV_EINVAL
+    assert L.mul_row_vector(-1, 3, ctypes.c_void_p(8), 3, ctypes.c_void_p(8), None) == S.UV_EINVAL
+    assert L.mul_row_vector(2, 3, ctypes.c_void_p(8), 2, ctypes.c_void_p(8), None) == S.UV_EINVAL
