@@ -605,17 +605,8 @@ template <typename T, int S>
 void seg_chunk_launch(const uv_solver *s, unsigned grid, hipStream_t st, int nseg, const int *ptr, const int *idx,
                       const T *val, const T *vec, T *out, const int *skip)
 {
-    if (s->batch8) k_seg_chunk<T, T, S, 8, 1><<<grid, kWG, 0, st>>>(nseg, ptr, idx, val, vec, nullptr, out, nullptr, skip);
-    else k_seg_chunk<T, T, S, 4, 1><<<grid, kWG, 0, st>>>(nseg, ptr, idx, val, vec, nullptr, out, nullptr, skip);
-}
-
-// Two products (vec -> out, vec2 -> out2) from one stream of the entries.
-template <typename T, int S>
-void seg_chunk2_launch(const uv_solver *s, unsigned grid, hipStream_t st, int nseg, const int *ptr, const int *idx,
-                       const T *val, const T *vec, const T *vec2, T *out, T *out2, const int *skip)
-{
-    if (s->batch8) k_seg_chunk<T, T, S, 8, 2><<<grid, kWG, 0, st>>>(nseg, ptr, idx, val, vec, vec2, out, out2, skip);
-    else k_seg_chunk<T, T, S, 4, 2><<<grid, kWG, 0, st>>>(nseg, ptr, idx, val, vec, vec2, out, out2, skip);
+    if (s->batch8) k_seg_chunk<T, T, S, 8><<<grid, kWG, 0, st>>>(nseg, ptr, idx, val, vec, out, skip);
+    else k_seg_chunk<T, T, S, 4><<<grid, kWG, 0, st>>>(nseg, ptr, idx, val, vec, out, skip);
 }
 
 template <typename T, int L, int E, int S>
@@ -626,13 +617,11 @@ void row_slab_launch(uv_solver *s, hipStream_t st, int mode)
     if (s->chunked) {
         const unsigned gk = S * blocks_for(s->m, kWG);
         const bool ign = mode == 2;
-        if (mode == 1)  // A x and the residual's A z from one stream of the entries
-            seg_chunk2_launch<T, S>(s, gk, st, s->m, s->srp, s->sci, (const T *)s->sva, (const T *)s->x,
-                                    (const T *)s->z, (T *)s->P_row, (T *)s->P_row + (size_t)S * s->m,
-                                    &s->st->done);
-        else
-            seg_chunk_launch<T, S>(s, gk, st, s->m, s->srp, s->sci, (const T *)s->sva, (const T *)s->x,
-                                   (T *)s->P_row, ign ? nullptr : &s->st->done);
+        seg_chunk_launch<T, S>(s, gk, st, s->m, s->srp, s->sci, (const T *)s->sva, (const T *)s->x, (T *)s->P_row,
+                               ign ? nullptr : &s->st->done);
+        if (mode == 1)
+            seg_chunk_launch<T, S>(s, gk, st, s->m, s->srp, s->sci, (const T *)s->sva, (const T *)s->z,
+                                   (T *)s->P_row + (size_t)S * s->m, &s->st->done);
     }
 #define UV_SLAB_ARGS s->m, s->srp, s->sci, (const T *)s->sva, (const T *)s->x, (const T *)s->z, (T *)s->P_row
 #define UV_COMB_ARGS                                                                                       \

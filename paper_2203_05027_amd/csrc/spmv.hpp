@@ -11,29 +11,25 @@ namespace {
 using uv::kWG;
 
 // Chunked segment sums for the slab passes: out[s * nseg + g] = sum over the
-// entries k of segment g in slab s of val[k] * vec[idx[k]] (and, with NV = 2,
-// out2 the same with vec2: both products from one stream of the entries).
-// A wavefront owns 64 consecutive segments (one per lane for the final sum):
-// it streams their contiguous entries with coalesced loads, U 64-entry steps
-// in flight per batch, parks the products in LDS, and each lane then adds
-// its own segment's products in entry order.  Unlike one lane group per
-// segment this needs no per-segment pointer before the stream starts and
-// keeps every lane busy however short the segments are.  Deterministic.
-// With S = 1 the arguments are a plain compressed-row (or -column) matrix.
-// The grid is S * ceil(nseg / kWG) workgroups; workgroup w works on slab
-// w % S.
+// entries k of segment g in slab s of val[k] * vec[idx[k]].  A wavefront owns
+// 64 consecutive segments (one per lane for the final sum): it streams their
+// contiguous entries with coalesced loads, four 64-entry steps in flight per
+// round, parks the products in LDS, and each lane then adds its own
+// segment's products in entry order.  Unlike one lane group per segment this
+// needs no per-segment pointer before the stream starts and keeps every lane
+// busy however short the segments are.  Deterministic.  With S = 1 the
+// arguments are a plain compressed-row (or -column) matrix.  The grid is
+// S * ceil(nseg / kWG) workgroups; workgroup w works on slab w % S.
 constexpr int kChunkCap = 512;  // LDS products per wavefront and round
 
-template <typename T, typename TV, int S, int U, int NV>
+template <typename T, typename TV, int S, int U = 4>
 __global__ void __launch_bounds__(kWG)
 k_seg_chunk(int nseg, const int *__restrict__ ptr, const int *__restrict__ idx, const TV *__restrict__ val,
-            const T *__restrict__ vec, const T *__restrict__ vec2, T *__restrict__ out, T *__restrict__ out2,
-            const int *skip)
+            const T *__restrict__ vec, T *__restrict__ out, const int *skip)
 {
     static_assert(kChunkCap % (64 * U) == 0, "a round holds whole batches");
-    static_assert(NV == 1 || NV == 2, "one or two gathered vectors");
     if (skip && *skip) return;  // a device flag (stop, or nothing left to do)
-    __shared__ T buf[NV][kWG / 64][kChunkCap];
+    __shared__ T buf[kWG / 64][kChunkCap];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int sl = blockIdx.x % S;
     const int g0 = ((blockIdx.x / S) * (kWG / 64) + w) * 64;
@@ -45,7 +41,7 @@ k_seg_chunk(int nseg, const int *__restrict__ ptr, const int *__restrict__ idx, 
     int end = __shfl_down(beg, 1);
     if (lane == 63) end = e_last;
     const int E0 = __shfl(beg, 0), E1 = e_last;
-    T acc = 0, acc2 = 0;
+    T acc = 0;
     for (int P0 = E0; P0 < E1; P0 += kChunkCap) {
         const int P1 = min(P0 + kChunkCap, E1);
         for (int b = P0; b < P1; b += 64 * U) {  // U coalesced 64-entry steps in flight
@@ -58,37 +54,25 @@ k_seg_chunk(int nseg, const int *__restrict__ ptr, const int *__restrict__ idx, 
                 j[u] = __builtin_nontemporal_load(idx + kk);
                 v[u] = __builtin_nontemporal_load(val + kk);
             }
-            T g[U], h[NV == 2 ? U : 1];
+            T g[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                g[u] = vec[j[u]];
-                if (NV == 2) h[u] = vec2[j[u]];
-            }
+            for (int u = 0; u < U; ++u) g[u] = vec[j[u]];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int k = b + u * 64 + lane;
-                if (k < P1) {
-                    buf[0][w][k - P0] = (T)v[u] * g[u];
-                    if (NV == 2) buf[NV - 1][w][k - P0] = (T)v[u] * h[u];
-                }
+                if (k < P1) buf[w][k - P0] = (T)v[u] * g[u];
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const int a = max(beg, P0), z = min(end, P1);
-        for (int k = a; k < z; ++k) {
-            acc += buf[0][w][k - P0];
-            if (NV == 2) acc2 += buf[NV - 1][w][k - P0];
-        }
+        for (int k = a; k < z; ++k) acc += buf[w][k - P0];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    if (gl < nseg) {
-        out[(size_t)sl * nseg + gl] = acc;
-        if (NV == 2) out2[(size_t)sl * nseg + gl] = acc2;
-    }
+    if (gl < nseg) out[(size_t)sl * nseg + gl] = acc;
 }
 
 // Slabs for a gathered vector of `bytes`: none up to 2 MiB, two up to

@@ -346,15 +346,15 @@ T *salloc(uv_standard *h, size_t count)
 template <int S>
 void prod_col(uv_standard *h, hipStream_t st, const double *vec, const int *skip)
 {
-    k_seg_chunk<double, double, S, 8, 1><<<S * blocks_for(h->n, kWG), kWG, 0, st>>>(h->n, h->scp, h->sri, h->svc,
-                                                                               vec, nullptr, h->P_col, nullptr, skip);
+    k_seg_chunk<double, double, S, 8><<<S * blocks_for(h->n, kWG), kWG, 0, st>>>(h->n, h->scp, h->sri, h->svc, vec,
+                                                                            h->P_col, skip);
 }
 
 template <int S>
 void prod_row(uv_standard *h, hipStream_t st, const double *vec, const int *skip)
 {
-    k_seg_chunk<double, double, S, 8, 1><<<S * blocks_for(h->m, kWG), kWG, 0, st>>>(h->m, h->srp, h->sci, h->sva,
-                                                                               vec, nullptr, h->P_row, nullptr, skip);
+    k_seg_chunk<double, double, S, 8><<<S * blocks_for(h->m, kWG), kWG, 0, st>>>(h->m, h->srp, h->sci, h->sva, vec,
+                                                                            h->P_row, skip);
 }
 
 template <int SR, int SC>
