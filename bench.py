@@ -152,6 +152,35 @@ def cpu_baseline(inst, mu, seconds):
                       f"workload (timed {dt:.1f} s after one untimed iteration)"}
 
 
+def small_block(mu, check_every, iters=2000):
+    """The small LP (m = 500, n = 1000, 5 per column): `iters` FP64
+    iterations from the zero start on the GPU (graph replays, launch-bound)
+    and in the CPU oracle (serial at this size), with the KKT residual."""
+    import torch
+    import oracle
+    from paper_2203_05027_amd import instances as I
+    from paper_2203_05027_amd.solver import Solver
+
+    inst = I.config_instance("lp_small")
+    with Solver.from_instance(inst, mu=mu, eps=0.0, check_every=check_every) as s:
+        s.iterate(iters)                      # warm-up run (graph instantiation, caches)
+    with Solver.from_instance(inst, mu=mu, eps=0.0, check_every=check_every) as s:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.iterate(iters)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        r = s.residuals()
+    orc = oracle.Oracle.from_instance(inst, mu=mu)
+    t1 = time.perf_counter()
+    orc.iterate(iters)
+    dto = time.perf_counter() - t1
+    ro = orc.residuals()
+    return {"workload": f"lp_small: {describe(inst)}, {iters} iterations from the zero start",
+            "gpu_iters_per_s": iters / dt, "gpu_kkt": r["kkt"], "oracle_iters_per_s": iters / dto,
+            "oracle_threads": 1, "oracle_kkt": ro["kkt"]}
+
+
 def gather_floor(m, n, nnz, slabs_row, slabs_col, fp64=True):
     """Duration (ms) of the random-gather probe with each pass's pair count,
     gathered table and slab split: the practical floor of the row pass
@@ -339,6 +368,7 @@ def main():
     ap.add_argument("--no-ttk", action="store_true", help="skip the time-to-1e-4 runs")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-workload block")
     ap.add_argument("--no-standard", action="store_true", help="skip the standard ADMM + CG baseline")
+    ap.add_argument("--no-small", action="store_true", help="skip the small-LP block")
     ap.add_argument("--std-cg-iters", type=int, default=2, help="baseline: CG steps per iteration at most")
     ap.add_argument("--std-cg-tol", type=float, default=0.0, help="baseline: CG stop, ||r|| <= tol (1 + ||b||)")
     ap.add_argument("--std-cap-s", type=float, default=60.0, help="baseline: wall-time cap of its solve")
@@ -403,6 +433,12 @@ def main():
     achieved = kern[dom][0] / (kern[dom][1] * 1e-3) / 1e9
     sweep_gbs = (row_b + col_b) / ((main_r["ms_col"] + main_r["ms_row"]) * 1e-3) / 1e9
 
+    small = None
+    if args.workload == "lp_large" and not args.no_small:
+        log("small LP block")
+        small = small_block(args.mu, args.check_every)
+        log(f"small: {json.dumps(small)}")
+
     standard = None
     if not args.no_standard and not args.no_ttk and not len(inst.get("soc_sizes", ())):
         log("standard ADMM + CG baseline")
@@ -464,6 +500,7 @@ def main():
         "mixed": extra,
         "batched": batched,
         "standard_admm_cg": standard,
+        "small_lp": small,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -105,9 +105,11 @@ typedef struct {
                              (0 = automatic; else 1, 2, 4 or 8) */
     int32_t unroll_col;   /* same for the A'u pass */
     int32_t slabs_row;    /* XCD slabs of x in the A x pass: 0 = automatic
-                             (none up to 2 MiB of x, two up to 12 MiB, else
+                             (none up to 2 MiB of x, two up to 6 MiB, else
                              four), 1 = none, 2, 4, 8 */
-    int32_t slabs_col;    /* XCD slabs of u in the A'u pass (same values) */
+    int32_t slabs_col;    /* XCD slabs of u in the A'u pass: 0 = automatic
+                             (none up to 2 MiB of u, two up to 16 MiB, else
+                             four), 1 = none, 2, 4, 8 */
     int32_t criterion;    /* UV_CRIT_KKT or UV_CRIT_INF (see uv_residuals) */
     double eps_abs;       /* absolute tolerance of UV_CRIT_INF */
     int32_t slab_kernel;  /* slab passes: 0 = automatic (= 1), 1 = 64-segment

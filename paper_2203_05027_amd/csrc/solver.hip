@@ -1106,8 +1106,8 @@ int solver_create(const uv_csr *A, const double *b, const double *c, const uv_co
     s->o = o;
     {
         const size_t ts = o.precision == UV_MIXED ? 4 : 8;
-        s->S_row = o.slabs_row ? o.slabs_row : pick_slabs(ts * (size_t)A->n);
-        s->S_col = o.slabs_col ? o.slabs_col : pick_slabs(ts * (size_t)A->m);
+        s->S_row = o.slabs_row ? o.slabs_row : pick_slabs_row(ts * (size_t)A->n);
+        s->S_col = o.slabs_col ? o.slabs_col : pick_slabs_col(ts * (size_t)A->m);
         // a slab needs at least one index, and slab offsets are 32-bit
         while (s->S_row > 1 && (s->S_row > A->n || (int64_t)s->S_row * A->m >= INT32_MAX)) s->S_row >>= 1;
         while (s->S_col > 1 && (s->S_col > A->m || (int64_t)s->S_col * A->n >= INT32_MAX)) s->S_col >>= 1;

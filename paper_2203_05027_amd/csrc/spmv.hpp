@@ -75,15 +75,24 @@ k_seg_chunk(int nseg, const int *__restrict__ ptr, const int *__restrict__ idx, 
     if (gl < nseg) out[(size_t)sl * nseg + gl] = acc;
 }
 
-// Slabs for a gathered vector of `bytes`: none up to 2 MiB, two up to
-// 12 MiB, else four (measured with the eight-step chunk kernel: on the
-// 1e6 x 2e6 LP, FP64 x (16 MiB) best in 4 slabs and u (8 MiB) in 2; on the
-// 1e5-cone SOCP, x (21 MiB) in 4 and u (10.6 MiB) in 2; more slabs add
-// partial traffic and shorter segments faster than they save gathers).
-inline int pick_slabs(size_t bytes)
+// Slabs of the gathered vector (`bytes` long) for the row pass (x gathered,
+// one partial per row) and the column pass (u gathered, one partial per
+// column, about twice as many).  A slab part of at most 2-4 MiB keeps the
+// gathers in an XCD's L2 (random-gather probe: 150-170 G/s against 70 G/s
+// from 16 MiB), and every slab adds a partial per segment; measured with the
+// eight-step chunk kernel on the 1e6 x 2e6 LP and the 1e5-cone SOCP: row
+// pass best in 4 slabs from x of 8 MiB (FP32) up, column pass best in 2
+// slabs for u of 4-11 MiB.
+inline int pick_slabs_row(size_t bytes)
 {
     if (bytes <= (2u << 20)) return 1;
-    return bytes <= (12u << 20) ? 2 : 4;
+    return bytes <= (6u << 20) ? 2 : 4;
+}
+
+inline int pick_slabs_col(size_t bytes)
+{
+    if (bytes <= (2u << 20)) return 1;
+    return bytes <= (16u << 20) ? 2 : 4;
 }
 
 }  // namespace

@@ -492,8 +492,8 @@ int standard_create(const uv_csr *A, const double *b, const double *c, const uv_
     h->check_every = o.check_every;
     h->max_iter = o.max_iter;
     h->cg_iters = cg_iters;
-    h->S_row = o.slabs_row ? o.slabs_row : pick_slabs(8 * (size_t)n);
-    h->S_col = o.slabs_col ? o.slabs_col : pick_slabs(8 * (size_t)m);
+    h->S_row = o.slabs_row ? o.slabs_row : pick_slabs_row(8 * (size_t)n);
+    h->S_col = o.slabs_col ? o.slabs_col : pick_slabs_col(8 * (size_t)m);
     while (h->S_row > 1 && (h->S_row > n || (int64_t)h->S_row * m >= INT32_MAX)) h->S_row >>= 1;
     while (h->S_col > 1 && (h->S_col > m || (int64_t)h->S_col * n >= INT32_MAX)) h->S_col >>= 1;
     if (o.hip_stream) h->stream = (hipStream_t)o.hip_stream;
