@@ -75,7 +75,8 @@ def describe(inst) -> str:
         soc = np.asarray(soc)
         return (f"SOCP m={m} n={n} nnz={nnz}, {len(soc)} second-order cones of sizes "
                 f"{int(soc.min())}..{int(soc.max())} (sum {int(soc.sum())}), orthant part {inst.get('n_orth', 0)}")
-    return f"LP m={m} n={n} nnz={nnz}, unit-norm rows, orthant cone"
+    rows = ", unit-norm rows" if inst.get("unit_rows") else ""
+    return f"LP m={m} n={n} nnz={nnz}{rows}, orthant cone"
 
 
 def alg_bytes(m, n, nnz, precision):

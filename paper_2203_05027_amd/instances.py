@@ -113,7 +113,7 @@ def lp_instance(m: int, n: int, k: int, seed: int, unit_rows: bool = False) -> d
         "m": m, "n": n, "nnz": int(row_ptr[-1]), "row_ptr": row_ptr,
         "col_idx": col_idx, "val": val, "b": b, "c": c, "n_orth": n,
         "soc_sizes": np.zeros(0, dtype=np.int32), "x0": x0, "y0": y0, "s0": s0,
-        "p_star": float(c @ x0), "d_star": float(b @ y0), "seed": seed,
+        "p_star": float(c @ x0), "d_star": float(b @ y0), "seed": seed, "unit_rows": bool(unit_rows),
     }
 
 
