@@ -257,7 +257,6 @@ def batched_block(steps_sweep=100, ttk_cap=60_000, plain_sample=8, count=4096, l
         out["sweep_ms"] = ms / steps_sweep
         out["instance_iters_per_s"] = count * steps_sweep / (ms * 1e-3)
         out["sweep_GBs"] = (rb + cb) * steps_sweep / (ms * 1e-3) / 1e9
-        out["sweep_frac_of_hbm_peak"] = out["sweep_GBs"] / HBM_PEAK_GBS
         t0 = time.perf_counter()
         left = count
         while left:
