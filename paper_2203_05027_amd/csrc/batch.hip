@@ -72,6 +72,35 @@ __device__ __forceinline__ void block_sum_rt(double (&v)[K])
     }
 }
 
+// sum over the entries k = beg + lane, beg + lane + L, ... < end of
+// val[k] * vs[idx[k] - off]: U entries per lane have their index and value
+// loads in flight together (the entries are added in the same order as one
+// at a time, so the result does not depend on U).
+template <int U, typename T, typename TV, typename TS>
+__device__ __forceinline__ T seg_sum(int beg, int end, int lane, int L, const int *__restrict__ idx,
+                                     const TV *__restrict__ val, const TS *vs, int off)
+{
+    T acc = 0;
+    for (int k0 = beg + lane; k0 < end; k0 += L * U) {
+        int j[U];
+        TV v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u * L;
+            j[u] = off;
+            v[u] = (TV)0;
+            if (k < end) {
+                j[u] = idx[k];
+                v[u] = val[k];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u * L < end) acc += (T)v[u] * (T)vs[j[u] - off];
+    }
+    return acc;
+}
+
 // ||b_i||^2, ||c_i||^2 per instance (one workgroup each).
 __global__ void __launch_bounds__(256)
 k_batch_norms(BInst *inst, const double *__restrict__ b64, const double *__restrict__ c64)
@@ -136,20 +165,25 @@ k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__
             // column pass: p = N x + A'u, x-step, projection onto R_+, delta
             for (int jb = 0; jb < n; jb += Gc) {
                 const int j = jb + gc;
-                T atu = 0;
+                T atu = 0, zj = 0, cj = 0;
+                double d = 0.0;
                 int beg = 0, end = 0;
                 if (j < n) {
                     beg = cp[c0 + j];
                     end = cp[c0 + j + 1];
-                    for (int kk = beg + lc; kk < end; kk += Lc) atu += vc[kk] * us[ri[kk] - r0];
+                    if (lc == 0) {  // the update's own loads, in flight with the sum's
+                        d = delta[c0 + j];
+                        zj = z[c0 + j];
+                        cj = c[c0 + j];
+                    }
+                    atu = seg_sum<4, T>(beg, end, lc, Lc, ri, vc, us, r0);
                 }
                 atu = group_sum_rt(atu, Lc);
                 if (j < n && lc == 0) {
-                    const double d = delta[c0 + j];
                     const T dm = (T)(d * inv_mu);
                     const int cnt = end - beg;
                     const T p = (T)cnt * xs[j] + atu;
-                    const T xn = (p + z[c0 + j] + dm - c[c0 + j] * (T)inv_mu) / (T)(1 + cnt);
+                    const T xn = (p + zj + dm - cj * (T)inv_mu) / (T)(1 + cnt);
                     const T v = xn - dm;
                     const T zn = v > (T)0 ? v : (T)0;
                     xs[j] = xn;
@@ -161,15 +195,21 @@ k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__
             // row pass: q = A x, lambda update, u
             for (int ib = 0; ib < m; ib += Gr) {
                 const int i = ib + gr;
-                T q = 0;
+                T q = 0, fi = 0, bi = 0;
+                double l0 = 0.0;
                 if (i < m) {
                     const int beg = rp[r0 + i], end = rp[r0 + i + 1];
-                    for (int kk = beg + lr; kk < end; kk += Lr) q += va[kk] * xs[ci[kk] - c0];
+                    if (lr == 0) {
+                        fi = fu[r0 + i];
+                        bi = b[r0 + i];
+                        l0 = lam[r0 + i];
+                    }
+                    q = seg_sum<4, T>(beg, end, lr, Lr, ci, va, xs, c0);
                 }
                 q = group_sum_rt(q, Lr);
                 if (i < m && lr == 0) {
-                    const T e = fu[r0 + i] * (b[r0 + i] - q);
-                    const double li = lam[r0 + i] - mu * (double)e;
+                    const T e = fi * (bi - q);
+                    const double li = l0 - mu * (double)e;
                     lam[r0 + i] = li;
                     us[i] = (T)((double)e - li * inv_mu);
                 }
@@ -183,10 +223,9 @@ k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__
                     const int i = ib + gr;
                     double qz = 0.0, qx = 0.0;
                     if (i < m) {
-                        for (int kk = rp[r0 + i] + lr; kk < rp[r0 + i + 1]; kk += Lr) {
-                            qz += va64[kk] * (double)z[ci[kk]];
-                            qx += va64[kk] * (double)xs[ci[kk] - c0];
-                        }
+                        const int beg = rp[r0 + i], end = rp[r0 + i + 1];
+                        qz = seg_sum<4, double>(beg, end, lr, Lr, ci, va64, z, 0);
+                        qx = seg_sum<4, double>(beg, end, lr, Lr, ci, va64, xs, c0);
                     }
                     qz = group_sum_rt(qz, Lr);
                     qx = group_sum_rt(qx, Lr);
@@ -200,8 +239,7 @@ k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__
                 for (int jb = 0; jb < n; jb += Gc) {
                     const int j = jb + gc;
                     double atl = 0.0;
-                    if (j < n)
-                        for (int kk = cp[c0 + j] + lc; kk < cp[c0 + j + 1]; kk += Lc) atl += vc64[kk] * lam[ri[kk]];
+                    if (j < n) atl = seg_sum<4, double>(cp[c0 + j], cp[c0 + j + 1], lc, Lc, ri, vc64, lam, 0);
                     atl = group_sum_rt(atl, Lc);
                     if (j < n && lc == 0) {
                         const double r = atl + c64[c0 + j] - delta[c0 + j];
