@@ -96,8 +96,10 @@ typedef struct {
     double eps_kkt;       /* stop when kkt <= eps_kkt at a check (0 = never) */
     int64_t max_iter;     /* cap on the total iteration count (0 = none) */
     void *hip_stream;     /* hipStream_t to order all device work on, or NULL */
-    int32_t lanes_row;    /* lanes per row in the A x pass (0 = automatic;
-                             else 1, 2, 4, 8, 16, 32 or 64) */
+    int32_t lanes_row;    /* lanes per row in the A x pass without slabs or
+                             with slab_kernel 2 (0 = automatic; else 1, 2,
+                             4, 8, 16, 32 or 64); the chunked slab passes do
+                             not use lanes_* or unroll_* */
     int32_t lanes_col;    /* lanes per column in the A'u pass (same values) */
     int32_t use_graph;    /* 1 = replay check_every iterations as one captured
                              HIP graph; 0 = launch kernels one by one */
