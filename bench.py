@@ -182,6 +182,24 @@ def small_block(mu, check_every, iters=2000):
             "oracle_threads": 1, "oracle_kkt": ro["kkt"]}
 
 
+def literal_block(inst, iters=20):
+    """Ablation: Algorithm 1 as printed (o-space y and gamma stored, FP64,
+    plain lane-group kernels) on the same instance: time per iteration and
+    its algorithmic bytes (every array once: 56 nnz + 60 n + 36 m) against
+    the reduced form's 24 nnz + 68 n + 52 m."""
+    from paper_2203_05027_amd.solver import Literal
+
+    m, n, nnz = inst["m"], inst["n"], inst["nnz"]
+    with Literal.from_instance(inst) as L:
+        L.iterate(2)
+        ms_col, ms_row = L.time(iters)
+    alg = 56 * nnz + 60 * n + 36 * m
+    ms = ms_col + ms_row
+    return {"ms_per_iter": ms, "ms_col": ms_col, "ms_row": ms_row, "alg_bytes_per_iter": alg,
+            "alg_GBs": alg / (ms * 1e-3) / 1e9,
+            "reduced_alg_bytes_per_iter": 24 * nnz + 68 * n + 52 * m}
+
+
 def gather_floor(m, n, nnz, slabs_row, slabs_col, fp64=True):
     """Duration (ms) of the random-gather probe with each pass's pair count,
     gathered table and slab split: the practical floor of the row pass
@@ -370,6 +388,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-workload block")
     ap.add_argument("--no-standard", action="store_true", help="skip the standard ADMM + CG baseline")
     ap.add_argument("--no-small", action="store_true", help="skip the small-LP block")
+    ap.add_argument("--no-literal", action="store_true", help="skip the literal Algorithm 1 ablation")
     ap.add_argument("--std-cg-iters", type=int, default=2, help="baseline: CG steps per iteration at most")
     ap.add_argument("--std-cg-tol", type=float, default=0.0, help="baseline: CG stop, ||r|| <= tol (1 + ||b||)")
     ap.add_argument("--std-cap-s", type=float, default=60.0, help="baseline: wall-time cap of its solve")
@@ -433,6 +452,13 @@ def main():
     dom = max(kern, key=lambda k: kern[k][1])
     achieved = kern[dom][0] / (kern[dom][1] * 1e-3) / 1e9
     sweep_gbs = (row_b + col_b) / ((main_r["ms_col"] + main_r["ms_row"]) * 1e-3) / 1e9
+
+    literal = None
+    if not args.no_literal and not len(inst.get("soc_sizes", ())):
+        log("literal Algorithm 1 ablation")
+        literal = literal_block(inst)
+        literal["reduced_ms_per_iter"] = main_r["ms_col"] + main_r["ms_row"]
+        log(f"literal: {json.dumps(literal)}")
 
     small = None
     if args.workload == "lp_large" and not args.no_small:
@@ -502,6 +528,7 @@ def main():
         "batched": batched,
         "standard_admm_cg": standard,
         "small_lp": small,
+        "literal_algorithm1": literal,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
