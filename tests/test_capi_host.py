@@ -207,3 +207,21 @@ def test_mul_row_vector_rejects_bad_arguments():
     assert L.mul_row_vector(2, 3, None, 3, None, None) == S.UV_EINVAL
     assert L.mul_row_vector(-1, 3, ctypes.c_void_p(8), 3, ctypes.c_void_p(8), None) == S.UV_EINVAL
     assert L.mul_row_vector(2, 3, ctypes.c_void_p(8), 2, ctypes.c_void_p(8), None) == S.UV_EINVAL
+
+
+def test_rejects_nnz_beyond_32bit_indices():
+    """Device indices are 32-bit: a declared nnz of 2^31 is refused before
+    any array is read past its first entries."""
+    rp = np.array([0, 1], np.int64)
+    ci = np.array([0], np.int32)
+    va = np.array([1.0])
+    b, c = np.ones(1), np.ones(1)
+    csr = S.UvCsr(1, 1, 1 << 31, S._ptr(rp), S._ptr(ci), S._ptr(va))
+    cones = S.UvCones(1, 0, None)
+    h = ctypes.c_void_p()
+    L = S.lib()
+    assert L.solver_create(ctypes.byref(csr), S._ptr(b), S._ptr(c), ctypes.byref(cones), None,
+                           ctypes.byref(h)) == S.UV_ETOOBIG and not h.value
+    L = S._bind_standard()
+    assert L.standard_create(ctypes.byref(csr), S._ptr(b), S._ptr(c), None, 2, 0.0,
+                             ctypes.byref(h)) == S.UV_ETOOBIG and not h.value
