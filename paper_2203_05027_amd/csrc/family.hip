@@ -118,7 +118,11 @@ k_fam_row(int m, int B, const int *__restrict__ rp, const int *__restrict__ ci, 
 }
 
 // Residual partials over rows: per instance ||A z - b||^2, b'lambda,
-// ||A x - b||^2 (FP64 values of A).  part[(blk * 3 + k) * B + l].
+// ||A x - b||^2 (FP64 values of A).  part[(blk * 3 + k) * B + l].  The grid
+// is kResBlocks * (B / 64): workgroup w takes the 64-instance group
+// w / kResBlocks and the row chunk blk = w % kResBlocks (rows blk * 4 + wave,
+// then every kResBlocks * 4-th); each wavefront sums a row's entries four at
+// a time with their gathers in flight together.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_fam_res_row(int m, int B, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ va,
@@ -126,32 +130,46 @@ k_fam_res_row(int m, int B, const int *__restrict__ rp, const int *__restrict__ 
               const double *__restrict__ LAM, double *__restrict__ part)
 {
     __shared__ double s[3][4][64];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, ng = B >> 6;
-    for (int g = 0; g < ng; ++g) {
-        const int l = g * 64 + lane;
-        double a[3] = {0.0, 0.0, 0.0};
-        for (int i = blockIdx.x * 4 + w; i < m; i += gridDim.x * 4) {
-            double qz = 0.0, qx = 0.0;
-            for (int k = rp[i]; k < rp[i + 1]; ++k) {
-                const size_t o = (size_t)ci[k] * B + l;
-                qz += va[k] * (double)Z[o];
-                qx += va[k] * (double)X[o];
-            }
-            const double bi = BV[(size_t)i * B + l];
-            a[0] += (qz - bi) * (qz - bi);
-            a[1] += bi * LAM[(size_t)i * B + l];
-            a[2] += (qx - bi) * (qx - bi);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int blk = blockIdx.x % kResBlocks, l = (blockIdx.x / kResBlocks) * 64 + lane;
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int i = blk * 4 + w; i < m; i += kResBlocks * 4) {
+        const int beg = rp[i], end = rp[i + 1];
+        double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0, x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0;
+        int k = beg;
+        for (; k + 3 < end; k += 4) {
+            const size_t o0 = (size_t)ci[k] * B + l, o1 = (size_t)ci[k + 1] * B + l;
+            const size_t o2 = (size_t)ci[k + 2] * B + l, o3 = (size_t)ci[k + 3] * B + l;
+            const double v0 = va[k], v1 = va[k + 1], v2 = va[k + 2], v3 = va[k + 3];
+            z0 += v0 * (double)Z[o0];
+            z1 += v1 * (double)Z[o1];
+            z2 += v2 * (double)Z[o2];
+            z3 += v3 * (double)Z[o3];
+            x0 += v0 * (double)X[o0];
+            x1 += v1 * (double)X[o1];
+            x2 += v2 * (double)X[o2];
+            x3 += v3 * (double)X[o3];
         }
-        for (int k = 0; k < 3; ++k) s[k][w][lane] = a[k];
-        __syncthreads();
-        if (w == 0)
-            for (int k = 0; k < 3; ++k)
-                part[((size_t)blockIdx.x * 3 + k) * B + l] = ((s[k][0][lane] + s[k][1][lane]) + s[k][2][lane]) + s[k][3][lane];
-        __syncthreads();
+        for (; k < end; ++k) {
+            const size_t o = (size_t)ci[k] * B + l;
+            z0 += va[k] * (double)Z[o];
+            x0 += va[k] * (double)X[o];
+        }
+        const double qz = (z0 + z1) + (z2 + z3), qx = (x0 + x1) + (x2 + x3);
+        const double bi = BV[(size_t)i * B + l];
+        a[0] += (qz - bi) * (qz - bi);
+        a[1] += bi * LAM[(size_t)i * B + l];
+        a[2] += (qx - bi) * (qx - bi);
     }
+    for (int k = 0; k < 3; ++k) s[k][w][lane] = a[k];
+    __syncthreads();
+    if (w == 0)
+        for (int k = 0; k < 3; ++k)
+            part[((size_t)blk * 3 + k) * B + l] = ((s[k][0][lane] + s[k][1][lane]) + s[k][2][lane]) + s[k][3][lane];
 }
 
-// Residual partials over columns: ||A'lambda + c - delta||^2, c'z.
+// Residual partials over columns: ||A'lambda + c - delta||^2, c'z (same
+// grid and order as the row partials).
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_fam_res_col(int n, int B, const int *__restrict__ cp, const int *__restrict__ ri, const double *__restrict__ vc,
@@ -159,25 +177,31 @@ k_fam_res_col(int n, int B, const int *__restrict__ cp, const int *__restrict__ 
               const T *__restrict__ Z, double *__restrict__ part)
 {
     __shared__ double s[2][4][64];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, ng = B >> 6;
-    for (int g = 0; g < ng; ++g) {
-        const int l = g * 64 + lane;
-        double a[2] = {0.0, 0.0};
-        for (int j = blockIdx.x * 4 + w; j < n; j += gridDim.x * 4) {
-            double t = 0.0;
-            for (int k = cp[j]; k < cp[j + 1]; ++k) t += vc[k] * LAM[(size_t)ri[k] * B + l];
-            const size_t o = (size_t)j * B + l;
-            const double r = t + c[j] - D[o];
-            a[0] += r * r;
-            a[1] += c[j] * (double)Z[o];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int blk = blockIdx.x % kResBlocks, l = (blockIdx.x / kResBlocks) * 64 + lane;
+    double a[2] = {0.0, 0.0};
+    for (int j = blk * 4 + w; j < n; j += kResBlocks * 4) {
+        const int beg = cp[j], end = cp[j + 1];
+        double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+        int k = beg;
+        for (; k + 3 < end; k += 4) {
+            t0 += vc[k] * LAM[(size_t)ri[k] * B + l];
+            t1 += vc[k + 1] * LAM[(size_t)ri[k + 1] * B + l];
+            t2 += vc[k + 2] * LAM[(size_t)ri[k + 2] * B + l];
+            t3 += vc[k + 3] * LAM[(size_t)ri[k + 3] * B + l];
         }
-        for (int k = 0; k < 2; ++k) s[k][w][lane] = a[k];
-        __syncthreads();
-        if (w == 0)
-            for (int k = 0; k < 2; ++k)
-                part[((size_t)blockIdx.x * 2 + k) * B + l] = ((s[k][0][lane] + s[k][1][lane]) + s[k][2][lane]) + s[k][3][lane];
-        __syncthreads();
+        for (; k < end; ++k) t0 += vc[k] * LAM[(size_t)ri[k] * B + l];
+        const double t = (t0 + t1) + (t2 + t3);
+        const size_t o = (size_t)j * B + l;
+        const double r = t + c[j] - D[o];
+        a[0] += r * r;
+        a[1] += c[j] * (double)Z[o];
     }
+    for (int k = 0; k < 2; ++k) s[k][w][lane] = a[k];
+    __syncthreads();
+    if (w == 0)
+        for (int k = 0; k < 2; ++k)
+            part[((size_t)blk * 2 + k) * B + l] = ((s[k][0][lane] + s[k][1][lane]) + s[k][2][lane]) + s[k][3][lane];
 }
 
 // One thread per instance: add the partials in block order, decide.
@@ -192,9 +216,18 @@ k_fam_finalize(int B, int nblk, const double *__restrict__ prow, const double *_
         FInst &I = inst[l];
         if (I.status == UV_STATUS_RUNNING) {
             double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-            for (int b = 0; b < nblk; ++b) {
-                for (int k = 0; k < 3; ++k) a[k] += prow[((size_t)b * 3 + k) * B + l];
-                for (int k = 0; k < 2; ++k) a[3 + k] += pcol[((size_t)b * 2 + k) * B + l];
+            for (int b0 = 0; b0 < nblk; b0 += 8) {  // eight blocks' loads in flight, added in block order
+                double t[8][5];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int b = b0 + r < nblk ? b0 + r : nblk - 1;
+                    for (int k = 0; k < 3; ++k) t[r][k] = prow[((size_t)b * 3 + k) * B + l];
+                    for (int k = 0; k < 2; ++k) t[r][3 + k] = pcol[((size_t)b * 2 + k) * B + l];
+                }
+#pragma unroll
+                for (int r = 0; r < 8; ++r)
+                    if (b0 + r < nblk)
+                        for (int k = 0; k < 5; ++k) a[k] += t[r][k];
             }
             const double rpr = sqrt(a[0]) / (1.0 + sqrt(I.bnorm2));
             const double rdu = sqrt(a[3]) / (1.0 + sqrt(sh->cnorm2));
@@ -353,9 +386,9 @@ void fam_iteration_t(uv_family *h, hipStream_t st, bool check)
         h->m, h->B, h->rp, h->ci, (const T *)h->va, (const T *)h->X, (const T *)h->BV, (const T *)h->fu, h->LAM,
         (T *)h->U, h->inst, mu, im, h->sh);
     if (check) {
-        k_fam_res_row<T><<<kResBlocks, 256, 0, st>>>(h->m, h->B, h->rp, h->ci, h->va64, (const T *)h->X,
+        k_fam_res_row<T><<<kResBlocks * (h->B / 64), 256, 0, st>>>(h->m, h->B, h->rp, h->ci, h->va64, (const T *)h->X,
                                                      (const T *)h->Z, h->BV64, h->LAM, h->prow);
-        k_fam_res_col<T><<<kResBlocks, 256, 0, st>>>(h->n, h->B, h->cp, h->ri, h->vc64, h->LAM, h->c64, h->D,
+        k_fam_res_col<T><<<kResBlocks * (h->B / 64), 256, 0, st>>>(h->n, h->B, h->cp, h->ri, h->vc64, h->LAM, h->c64, h->D,
                                                      (const T *)h->Z, h->pcol);
         k_fam_finalize<<<1, 1024, 0, st>>>(h->B, kResBlocks, h->prow, h->pcol, h->o.eps_kkt,
                                            (long long)h->o.max_iter, h->inst, h->sh);
