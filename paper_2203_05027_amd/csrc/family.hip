@@ -23,7 +23,7 @@
 
 namespace {
 
-constexpr int kResBlocks = 2048;  // row / column chunks of the residual passes
+constexpr int kResBlocks = 512;  // fixed grid of the residual passes
 
 struct FInst {
     long long iter;  // iterations when stopped (or last check)
@@ -204,66 +204,56 @@ k_fam_res_col(int n, int B, const int *__restrict__ cp, const int *__restrict__ 
             part[((size_t)blk * 2 + k) * B + l] = ((s[k][0][lane] + s[k][1][lane]) + s[k][2][lane]) + s[k][3][lane];
 }
 
-// Per instance, add the partials of every block and decide.  tpi = 1024 / B
-// threads share an instance: thread t adds blocks t, t + tpi, ... in order
-// (eight loads in flight), then the first thread adds the tpi sums in order.
+// One thread per instance: add the partials in block order, decide.
 __global__ void __launch_bounds__(1024)
 k_fam_finalize(int B, int nblk, const double *__restrict__ prow, const double *__restrict__ pcol, double eps,
                long long max_iter, FInst *inst, FShared *sh)
 {
-    __shared__ double s_part[1024][5];
     __shared__ int s_active[1024];
-    const int tid = threadIdx.x, tpi = max(1, (int)blockDim.x / B);
-    const int l = tid / tpi, t = tid % tpi;
-    const bool mine = l < B && inst[l].status == UV_STATUS_RUNNING;
-    double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (mine) {
-        for (int b0 = t; b0 < nblk; b0 += 8 * tpi) {
-            double v[8][5];
+    const int l = threadIdx.x;
+    int running = 0;
+    if (l < B) {
+        FInst &I = inst[l];
+        if (I.status == UV_STATUS_RUNNING) {
+            double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            for (int b0 = 0; b0 < nblk; b0 += 8) {  // eight blocks' loads in flight, added in block order
+                double t[8][5];
 #pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const int b = b0 + r * tpi < nblk ? b0 + r * tpi : t;
-                for (int k = 0; k < 3; ++k) v[r][k] = prow[((size_t)b * 3 + k) * B + l];
-                for (int k = 0; k < 2; ++k) v[r][3 + k] = pcol[((size_t)b * 2 + k) * B + l];
+                for (int r = 0; r < 8; ++r) {
+                    const int b = b0 + r < nblk ? b0 + r : nblk - 1;
+                    for (int k = 0; k < 3; ++k) t[r][k] = prow[((size_t)b * 3 + k) * B + l];
+                    for (int k = 0; k < 2; ++k) t[r][3 + k] = pcol[((size_t)b * 2 + k) * B + l];
+                }
+#pragma unroll
+                for (int r = 0; r < 8; ++r)
+                    if (b0 + r < nblk)
+                        for (int k = 0; k < 5; ++k) a[k] += t[r][k];
             }
-#pragma unroll
-            for (int r = 0; r < 8; ++r)
-                if (b0 + r * tpi < nblk)
-                    for (int k = 0; k < 5; ++k) a[k] += v[r][k];
+            const double rpr = sqrt(a[0]) / (1.0 + sqrt(I.bnorm2));
+            const double rdu = sqrt(a[3]) / (1.0 + sqrt(sh->cnorm2));
+            const double cz = a[4], bl = a[1];
+            const double rg = fabs(cz + bl) / (1.0 + fabs(cz) + fabs(bl));
+            const double kkt = fmax(rpr, fmax(rdu, rg));
+            I.r_prim = rpr;
+            I.r_dual = rdu;
+            I.r_gap = rg;
+            I.kkt = kkt;
+            I.pobj = cz;
+            I.dobj = -bl;
+            I.res_ax_b = sqrt(a[2]);
+            I.iter = sh->iter;
+            if (!isfinite(kkt)) I.status = UV_STATUS_NUMERIC;
+            else if (kkt <= eps) I.status = UV_STATUS_CONVERGED;
+            else if (max_iter > 0 && sh->iter >= max_iter) I.status = UV_STATUS_MAX_ITER;
+            running = I.status == UV_STATUS_RUNNING;
         }
     }
-    for (int k = 0; k < 5; ++k) s_part[tid][k] = a[k];
+    s_active[l] = running;
     __syncthreads();
-    int running = 0;
-    if (mine && t == 0) {
-        FInst &I = inst[l];
-        double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int u = 0; u < tpi; ++u)
-            for (int k = 0; k < 5; ++k) q[k] += s_part[tid + u][k];
-        const double rpr = sqrt(q[0]) / (1.0 + sqrt(I.bnorm2));
-        const double rdu = sqrt(q[3]) / (1.0 + sqrt(sh->cnorm2));
-        const double cz = q[4], bl = q[1];
-        const double rg = fabs(cz + bl) / (1.0 + fabs(cz) + fabs(bl));
-        const double kkt = fmax(rpr, fmax(rdu, rg));
-        I.r_prim = rpr;
-        I.r_dual = rdu;
-        I.r_gap = rg;
-        I.kkt = kkt;
-        I.pobj = cz;
-        I.dobj = -bl;
-        I.res_ax_b = sqrt(q[2]);
-        I.iter = sh->iter;
-        if (!isfinite(kkt)) I.status = UV_STATUS_NUMERIC;
-        else if (kkt <= eps) I.status = UV_STATUS_CONVERGED;
-        else if (max_iter > 0 && sh->iter >= max_iter) I.status = UV_STATUS_MAX_ITER;
-        running = I.status == UV_STATUS_RUNNING;
-    }
-    s_active[tid] = running;
-    __syncthreads();
-    if (tid == 0) {
-        int c = 0;
-        for (int i = 0; i < (int)blockDim.x; ++i) c += s_active[i];
-        sh->active = c;
+    if (l == 0) {
+        int t = 0;
+        for (int i = 0; i < (int)blockDim.x; ++i) t += s_active[i];
+        sh->active = t;
     }
 }
 
