@@ -252,7 +252,8 @@ def standard_block(inst, mu, cg_iters, cg_tol, check_every, cap_s, uv_ttk_s=None
     return out
 
 
-def batched_block(steps_sweep=100, ttk_cap=60_000, plain_sample=8, count=4096, log_fn=log):
+def batched_block(steps_sweep=100, ttk_cap=60_000, plain_sample=8, count=4096, log_fn=log, cpu_threads=0,
+                  cpu_iters=1000):
     """The batched workload: all instances in one persistent launch (mixed
     precision), sweep throughput, time to 1e-4 for the batch, and the plain
     single-problem solver on a sample of the same instances."""
@@ -303,7 +304,35 @@ def batched_block(steps_sweep=100, ttk_cap=60_000, plain_sample=8, count=4096, l
                            "us_per_iter": tp / ip * 1e6,
                            "est_all_instances_s": tp / ip * 1e6 * its.sum() * 1e-6,
                            "batched_iters_same_sample": batch_sample_iters}
+    if cpu_threads:
+        out["cpu_oracle"] = batched_cpu(insts, sample_size=16 * cpu_threads, iters=cpu_iters, threads=cpu_threads)
     return out
+
+
+def host_threads() -> int:
+    """Threads the CPU legs use: the oracle's OpenMP thread count."""
+    import oracle
+    return oracle.num_threads()
+
+
+def batched_cpu(insts, sample_size, iters, threads):
+    """The CPU oracle on the batched workload, one instance per host thread
+    (ctypes releases the interpreter lock during the oracle's calls; its own
+    parallel loops stay serial at these sizes): `iters` FP64 iterations of a
+    seeded sample of the instances, as instance-iterations/s."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+
+    rng = np.random.default_rng(2)
+    pick = rng.choice(len(insts), min(sample_size, len(insts)), replace=False)
+    orcs = [oracle.Oracle.from_instance(insts[i]) for i in pick]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(lambda o: o.iterate(iters), orcs))
+    dt = time.perf_counter() - t0
+    return {"value": len(orcs) * iters / dt, "unit": "instance-iter/s", "threads": threads, "kind": "oracle",
+            "sample": f"{len(orcs)} random instances x {iters} FP64 iterations of the literal Algorithm 1 "
+                      f"oracle, one instance per thread ({dt:.1f} s)"}
 
 
 def bench_parametric(args):
@@ -342,6 +371,17 @@ def bench_parametric(args):
             tp += time.perf_counter() - t1
             ip += s.residuals()["iter"]
     ne = len(held)
+    cpu_member = None
+    if not args.no_cpu:
+        import oracle
+        orc = oracle.Oracle.from_instance(fam.instance(held[0]), mu=1.0)
+        orc.iterate(1)
+        t1 = time.perf_counter()
+        orc.iterate(100)
+        rate = 100 / (time.perf_counter() - t1)
+        cpu_member = {"value": rate, "unit": "iter/s", "cores": oracle.num_threads(), "kind": "oracle",
+                      "est_cold_member_s": float(np.median(cmp["cold"]["iters"])) / rate,
+                      "sample": "100 FP64 iterations of the literal Algorithm 1 oracle on the first held-out member"}
     def summary(v):
         d = cmp[v]
         return {"seconds": d["seconds"], "per_member_s": d["seconds"] / ne,
@@ -367,6 +407,7 @@ def bench_parametric(args):
         "basis_projection_of_solution": summary("projection"),
         "plain_gpu_cold": {"members": args.plain, "seconds": tp, "per_member_s": tp / max(args.plain, 1),
                            "iters": ip},
+        "cpu_baseline": cpu_member,
     }
     print(json.dumps(line), flush=True)
 
@@ -426,7 +467,7 @@ def main():
     if args.workload == "lp_parametric":
         return bench_parametric(args)
     if args.workload == "lp_batched":
-        out = batched_block()
+        out = batched_block(cpu_threads=0 if args.no_cpu else host_threads())
         print(json.dumps({"metric": "instance-iterations/s of the batched sweep (4096 LPs, one launch)",
                           "value": out["instance_iters_per_s"], "unit": "instance-iter/s", "n_gpus": 1,
                           "higher_is_better": True, "dtype": "f32 sweep / f64 duals", "data": "synthetic",
@@ -476,7 +517,7 @@ def main():
     batched = None
     if not args.no_batched and args.workload == "lp_large":
         log("batched workload")
-        batched = batched_block()
+        batched = batched_block(cpu_threads=0 if args.no_cpu else host_threads())
         log(f"batched: {json.dumps(batched)}")
 
     cpu = None
