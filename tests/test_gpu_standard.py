@@ -119,3 +119,24 @@ def test_full_size_lp_matches_oracle():
     inst = I.config_instance("lp_large")
     errs, _, _ = _compare(inst, 3, cg_iters=2)
     assert max(errs.values()) <= 1e-9, errs
+
+
+def test_empty_rows_make_a_singular_system():
+    """Empty rows (b_i = 0) give A A' zero rows and columns: their
+    multipliers stay zero, CG works on the rest, and the GPU matches the
+    oracle step for step."""
+    base = I.lp_instance(600, 1300, 4, seed=45)
+    rp = base["row_ptr"].copy()
+    cnt = np.diff(rp)
+    keep = np.ones(base["m"], bool)
+    keep[[3, 77, 500]] = False                      # these rows lose their entries
+    mask = np.repeat(keep, cnt)
+    cnt = np.where(keep, cnt, 0)
+    row_ptr = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int64)
+    col_idx, val = base["col_idx"][mask], base["val"][mask]
+    A = np.zeros((base["m"], base["n"]))
+    A[np.repeat(np.arange(base["m"]), cnt), col_idx] = val
+    inst = dict(base, row_ptr=row_ptr, col_idx=col_idx, val=val, nnz=int(mask.sum()), b=A @ base["x0"])
+    errs, ro, rg = _compare(inst, 80, cg_iters=10)
+    assert max(errs.values()) <= 1e-9, errs
+    assert rg["cg_steps"] == ro["cg_steps"] == 800
