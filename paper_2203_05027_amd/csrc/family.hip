@@ -678,17 +678,27 @@ int family_iterate(uv_family *h, int64_t k, int32_t *n_active)
     if (h->sh_host->active > 0) {
         int64_t left = k;
         if (h->o.max_iter > 0) left = std::min<int64_t>(left, h->o.max_iter - h->host_iter);
-        int64_t it = h->host_iter;
+        int64_t it = h->host_iter, since = 0;
         const int ce = h->o.check_every;
+        const int64_t look = 50 * (int64_t)ce;  // read the active count every 50 checks
         while (left > 0) {
             if (h->exec && it % ce == 0 && left >= ce) {
                 UV_FTRY(hipGraphLaunch(h->exec, h->stream));
                 it += ce;
                 left -= ce;
+                since += ce;
             } else {
                 fam_iteration(h, h->stream, (it + 1) % ce == 0 || (h->o.max_iter > 0 && it + 1 >= h->o.max_iter));
                 it += 1;
                 left -= 1;
+                since += 1;
+            }
+            if (left > 0 && since >= look) {  // stop launching once every member has stopped
+                UV_FTRY(hipGetLastError());
+                int rc = fam_sync(h);
+                if (rc != UV_OK) return rc;
+                if (h->sh_host->active == 0) break;
+                since = 0;
             }
         }
         UV_FTRY(hipGetLastError());

@@ -1196,17 +1196,27 @@ int solver_iterate(uv_solver *s, int64_t k, int32_t *done)
     if (!s->st_host->done) {
         int64_t left = k;
         if (s->o.max_iter > 0) left = std::min<int64_t>(left, s->o.max_iter - s->host_iter);
-        int64_t it = s->host_iter;
+        int64_t it = s->host_iter, since = 0;
         const int ce = s->o.check_every;
+        const int64_t look = 50 * (int64_t)ce;  // read the stop flag every 50 checks
         while (left > 0) {
             if (s->exec && it % ce == 0 && left >= ce) {
                 UV_TRY(hipGraphLaunch(s->exec, s->stream));
                 it += ce;
                 left -= ce;
+                since += ce;
             } else {
                 launch_iteration(s, s->stream, (it + 1) % ce == 0);
                 it += 1;
                 left -= 1;
+                since += 1;
+            }
+            if (left > 0 && since >= look) {  // stop launching once a check has stopped the run
+                UV_TRY(hipGetLastError());
+                int rc = sync_status(s);
+                if (rc != UV_OK) return rc;
+                if (s->st_host->done) break;
+                since = 0;
             }
         }
         UV_TRY(hipGetLastError());

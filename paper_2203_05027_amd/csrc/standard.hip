@@ -630,17 +630,27 @@ int standard_iterate(uv_standard *h, int64_t k, int32_t *done)
     if (!h->st_host->done) {
         int64_t left = k;
         if (h->max_iter > 0) left = std::min<int64_t>(left, h->max_iter - h->host_iter);
-        int64_t it = h->host_iter;
+        int64_t it = h->host_iter, since = 0;
         const int ce = h->check_every;
+        const int64_t look = 50 * (int64_t)ce;  // read the stop flag every 50 checks
         while (left > 0) {
             if (h->exec && it % ce == 0 && left >= ce) {
                 UV_TRY(hipGraphLaunch(h->exec, h->stream));
                 it += ce;
                 left -= ce;
+                since += ce;
             } else {
                 launch_iteration(h, h->stream, (it + 1) % ce == 0);
                 it += 1;
                 left -= 1;
+                since += 1;
+            }
+            if (left > 0 && since >= look) {  // stop launching once a check has stopped the run
+                UV_TRY(hipGetLastError());
+                int rc = sync_status(h);
+                if (rc != UV_OK) return rc;
+                if (h->st_host->done) break;
+                since = 0;
             }
         }
         UV_TRY(hipGetLastError());
