@@ -70,13 +70,17 @@ def log(msg):
 def describe(inst) -> str:
     """Problem class, sizes and cone of a single-instance workload."""
     m, n, nnz = inst["m"], inst["n"], inst["nnz"]
+    gen = ""
+    if inst.get("bounded") is False:
+        gen = (f", the experiments' generator (density {nnz / (m * n):.3%}, b = A proj_K(N(0, I)), "
+               f"c ~ N(0, I): not bounded, sweep rate only)")
     soc = inst.get("soc_sizes")
     if soc is not None and len(soc):
         soc = np.asarray(soc)
         return (f"SOCP m={m} n={n} nnz={nnz}, {len(soc)} second-order cones of sizes "
-                f"{int(soc.min())}..{int(soc.max())} (sum {int(soc.sum())}), orthant part {inst.get('n_orth', 0)}")
+                f"{int(soc.min())}..{int(soc.max())} (sum {int(soc.sum())}), orthant part {inst.get('n_orth', 0)}{gen}")
     rows = ", unit-norm rows" if inst.get("unit_rows") else ""
-    return f"LP m={m} n={n} nnz={nnz}{rows}, orthant cone"
+    return f"LP m={m} n={n} nnz={nnz}{rows}, orthant cone{gen}"
 
 
 def alg_bytes(m, n, nnz, precision):
@@ -479,10 +483,11 @@ def main():
     log(f"workload {args.workload} m={m} n={n} nnz={nnz} generated in {time.time() - t0:.1f} s")
 
     res = {}
+    ttk = not args.no_ttk and inst.get("bounded", True)   # no time to a tolerance on unbounded problems
     for prec in (["fp64"] if args.no_mixed else ["fp64", "mixed"]):
         log(f"measuring {prec}")
         res[prec] = measure(inst, prec, args.steps, args.warmup, args.check_every,
-                            args.ttk_cap, args.mu, ttk=not args.no_ttk)
+                            args.ttk_cap, args.mu, ttk=ttk)
         log(f"{prec}: {json.dumps(res[prec])}")
 
     main_r = res["fp64"]
@@ -495,7 +500,7 @@ def main():
     sweep_gbs = (row_b + col_b) / ((main_r["ms_col"] + main_r["ms_row"]) * 1e-3) / 1e9
 
     literal = None
-    if not args.no_literal and not len(inst.get("soc_sizes", ())):
+    if not args.no_literal and not len(inst.get("soc_sizes", ())) and args.workload == "lp_large":
         log("literal Algorithm 1 ablation")
         literal = literal_block(inst)
         literal["reduced_ms_per_iter"] = main_r["ms_col"] + main_r["ms_row"]
@@ -508,7 +513,7 @@ def main():
         log(f"small: {json.dumps(small)}")
 
     standard = None
-    if not args.no_standard and not args.no_ttk and not len(inst.get("soc_sizes", ())):
+    if not args.no_standard and ttk and not len(inst.get("soc_sizes", ())):
         log("standard ADMM + CG baseline")
         standard = standard_block(inst, args.mu, args.std_cg_iters, args.std_cg_tol, args.check_every,
                                   args.std_cap_s, main_r["ttk_s"])

@@ -275,15 +275,19 @@ class ParametricFamily:
         }
 
 
-# The five named workloads: small LP, large LP (unit rows), large SOCP,
-# batched LPs, parametric family.  ``scale`` shrinks m, n (and the cone count)
-# for tests; the sparsity per column is kept.
+# The named workloads: small LP, large LP (unit rows), large SOCP, batched
+# LPs, parametric family, and the experiments' own generator at 1e7 stored
+# entries (0.5 % density; with m < n and c unrelated to A these are not
+# bounded, so only the sweep rate is measured on them).  ``scale`` shrinks m,
+# n (and the cone count) for tests; the sparsity per column is kept.
 CONFIGS = {
     "lp_small": dict(kind="lp", m=500, n=1000, k=5, seed=0, unit_rows=False),
     "lp_large": dict(kind="lp", m=1_000_000, n=2_000_000, k=10, seed=1, unit_rows=True),
     "socp_large": dict(kind="socp", n_cones=100_000, k=8, seed=2),
     "lp_batched": dict(kind="batch", count=4096, k=6),
     "lp_parametric": dict(kind="param", m=50_000, n=100_000, k=8, p=64, seed=4),
+    "paper_lp": dict(kind="paper", m=20_000, n=100_000, density=0.005, cone="lp", seed=5),
+    "paper_socp": dict(kind="paper", m=20_000, n=100_000, density=0.005, cone="socp", seed=6),
 }
 
 
@@ -295,6 +299,11 @@ def config_instance(name: str, scale: float = 1.0) -> dict:
         inst = lp_instance(m, n, cfg["k"], cfg["seed"], cfg["unit_rows"])
     elif cfg["kind"] == "socp":
         inst = socp_instance(max(int(cfg["n_cones"] * scale), 1), cfg["k"], cfg["seed"])
+    elif cfg["kind"] == "paper":
+        m = max(int(cfg["m"] * scale), 1)
+        n = max(int(cfg["n"] * scale) // 4 * 4, 4)
+        inst = paper_instance(m, n, cfg["density"], cfg["cone"], cfg["seed"])
+        inst["bounded"] = False
     else:
         raise ValueError(f"{name} is not a single-instance workload")
     inst["name"] = name
