@@ -434,6 +434,7 @@ def main():
     ap.add_argument("--no-standard", action="store_true", help="skip the standard ADMM + CG baseline")
     ap.add_argument("--no-small", action="store_true", help="skip the small-LP block")
     ap.add_argument("--no-literal", action="store_true", help="skip the literal Algorithm 1 ablation")
+    ap.add_argument("--no-slab-search", action="store_true", help="skip the slab-count search")
     ap.add_argument("--std-cg-iters", type=int, default=2, help="baseline: CG steps per iteration at most")
     ap.add_argument("--std-cg-tol", type=float, default=0.0, help="baseline: CG stop, ||r|| <= tol (1 + ||b||)")
     ap.add_argument("--std-cap-s", type=float, default=60.0, help="baseline: wall-time cap of its solve")
@@ -491,6 +492,13 @@ def main():
         log(f"{prec}: {json.dumps(res[prec])}")
 
     main_r = res["fp64"]
+    slab_search = None
+    if args.workload == "lp_large" and not args.no_slab_search:
+        from paper_2203_05027_amd import autotune
+        rec = autotune.tune_slabs(inst, "fp64", iters=20, cache_path=None, log=log)
+        slab_search = {"rule": {"slabs_row": main_r["slabs_row"], "slabs_col": main_r["slabs_col"]},
+                       "search": {"slabs_row": rec["slabs_row"], "slabs_col": rec["slabs_col"]},
+                       "trials": rec["trials"]}
     floor = gather_floor(m, n, nnz, main_r["slabs_row"], main_r["slabs_col"])
     log(f"gather floor (ms): {floor}")
     row_b, col_b = alg_bytes(m, n, nnz, "fp64")
@@ -575,6 +583,7 @@ def main():
         "standard_admm_cg": standard,
         "small_lp": small,
         "literal_algorithm1": literal,
+        "slab_search": slab_search,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

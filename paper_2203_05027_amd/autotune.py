@@ -1,4 +1,5 @@
-"""Tile search for the batched solver, with a JSON cache.
+"""Launch-shape searches, with a JSON cache: tiles of the batched solver
+(``tune``) and XCD slab counts of the single-problem solver (``tune_slabs``).
 
 The measurement runs in the library (``batch_time``: one timed launch of a
 size bucket's instances from a saved copy of the state, put back after); the
@@ -82,3 +83,55 @@ def tune(batch, iters: int = 20, cache_path: str | None = DEFAULT_CACHE, threads
             json.dump(cache, f, indent=1)
         os.replace(tmp, cache_path)
     return dict(best_overall, cached=False, trials=trials)
+
+
+SLABS = (1, 2, 4, 8)
+
+
+def slab_signature(inst, precision: str) -> str:
+    """Shape key of a single problem: sizes rounded to powers of two, cone mix."""
+    def r(v):
+        return 0 if v <= 0 else 2 ** round(math.log2(v))
+    soc = inst.get("soc_sizes")
+    cones = "orthant" if soc is None or len(soc) == 0 else f"soc{r(len(soc))}"
+    return f"slabs|{precision}|m={r(inst['m'])}|n={r(inst['n'])}|nnz={r(inst['nnz'])}|{cones}"
+
+
+def tune_slabs(inst, precision: str = "fp64", iters: int = 20, cache_path: str | None = DEFAULT_CACHE,
+               slabs=SLABS, log=None) -> dict:
+    """Times the column and row passes of ``inst`` (solver_time_kernels) for
+    every slab count of the gathered vectors and returns the fastest pair
+    {"slabs_row", "slabs_col", "ms_row", "ms_col"}; the two passes are
+    independent, so each count is chosen on its own pass.  Cached by shape."""
+    from .solver import Solver
+
+    key = slab_signature(inst, precision)
+    cache = _load(cache_path) if cache_path else {}
+    if key in cache:
+        return dict(cache[key], cached=True)
+    best_row = best_col = None
+    trials = []
+    for S in slabs:
+        if S > 1 and (S > inst["m"] or S > inst["n"]):
+            continue
+        with Solver.from_instance(inst, precision=precision, eps=0.0, slabs_row=S, slabs_col=S) as s:
+            s.iterate(2)
+            ms_col, ms_row = s.time_kernels(iters)
+        trials.append({"slabs": S, "ms_row": ms_row, "ms_col": ms_col})
+        if log:
+            log(f"slabs={S}: row pass {ms_row:.4f} ms, column pass {ms_col:.4f} ms")
+        if best_row is None or ms_row < best_row[1]:
+            best_row = (S, ms_row)
+        if best_col is None or ms_col < best_col[1]:
+            best_col = (S, ms_col)
+    rec = {"slabs_row": best_row[0], "slabs_col": best_col[0], "ms_row": best_row[1], "ms_col": best_col[1],
+           "iters": iters}
+    if cache_path:
+        cache = _load(cache_path)
+        cache[key] = rec
+        os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+        tmp = cache_path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1)
+        os.replace(tmp, cache_path)
+    return dict(rec, cached=False, trials=trials)
