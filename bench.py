@@ -339,6 +339,34 @@ def batched_cpu(insts, sample_size, iters, threads):
                       f"oracle, one instance per thread ({dt:.1f} s)"}
 
 
+def bench_family_sweep(args, B=256, iters=300):
+    """The parametric family's sweep alone: one group of B held-out members
+    (one A, B right-hand sides, mixed precision), `iters` iterations with
+    the residual check every check_every, as member-iterations/s."""
+    import torch
+    from paper_2203_05027_amd import instances as I
+    from paper_2203_05027_amd.solver import Family
+
+    fam = I.ParametricFamily(m=50_000, n=100_000, k=8, p=64, seed=4)
+    th = np.stack([fam.theta(2_000_000 + i) for i in range(B)])
+    with Family(fam.m, fam.n, fam.row_ptr, fam.col_idx, fam.val, fam.c, B=B, eps=0.0,
+                check_every=args.check_every) as F:
+        F.set_rhs(fam.b_many(th))
+        F.iterate(20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F.iterate(iters)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    print(json.dumps({"metric": "member-iterations/s of the family sweep (one A, many b)",
+                      "value": B * iters / dt, "unit": "member-iter/s", "n_gpus": 1, "higher_is_better": True,
+                      "dtype": "f32 sweep / f64 duals", "data": "synthetic",
+                      "ms_per_iteration": dt * 1e3 / iters,
+                      "config": {"workload": f"lp_family_sweep: m={fam.m} n={fam.n} nnz={fam.row_ptr[-1]}, "
+                                             f"B={B} right-hand sides, check_every={args.check_every}"}}),
+          flush=True)
+
+
 def bench_parametric(args):
     import torch
     from paper_2203_05027_amd import instances as I
@@ -471,6 +499,8 @@ def main():
         return gather_sweep()
     if args.workload == "lp_parametric":
         return bench_parametric(args)
+    if args.workload == "lp_family_sweep":
+        return bench_family_sweep(args)
     if args.workload == "lp_batched":
         out = batched_block(cpu_threads=0 if args.no_cpu else host_threads())
         print(json.dumps({"metric": "instance-iterations/s of the batched sweep (4096 LPs, one launch)",
