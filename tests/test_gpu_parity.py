@@ -278,7 +278,7 @@ def test_bitwise_reproducible():
             assert np.array_equal(o[k], outs[0][k])
 
 
-@pytest.mark.parametrize("name", ["lp_large", "socp_large"])
+@pytest.mark.parametrize("name", ["lp_large", "socp_large", "paper_lp", "paper_socp"])
 def test_full_size_sampled_parity(name):
     """The full-size workloads in the launch configuration the benchmark
     times (automatic lanes, unroll and XCD slabs, graph replay): 3 iterations
@@ -289,6 +289,17 @@ def test_full_size_sampled_parity(name):
     assert_parity(g, o)
     for k in ("r_prim", "r_dual", "r_gap", "pobj", "dobj"):
         assert abs(gr[k] - orr[k]) <= 1e-9 * max(abs(orr[k]), 1e-12), k
+
+
+def test_full_size_mixed_precision():
+    """The 1e6 x 2e6 LP in the mixed form the benchmark times: 3 iterations
+    against the FP64 oracle, every entry within FP32 rounding of the sweep."""
+    inst = I.config_instance("lp_large")
+    g, o, _, _ = run_pair(inst, 3, check_every=3, precision="mixed")
+    errs = {k: rel(g[k], o[k]) for k in KEYS}
+    say(f"lp_large mixed vs fp64 oracle after 3 iterations: {errs}")
+    for k in KEYS:
+        assert errs[k] <= 1e-5, (k, errs[k])
 
 
 def test_mixed_precision_small_lp():
