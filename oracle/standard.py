@@ -1,5 +1,6 @@
 """Plain FP64 CPU oracle of standard two-block ADMM with a warm-started CG
-solve of the block system eq. lin (Sections II-B and III-B).
+solve of the block system eq. lin (Sections II-B and III-B), for the
+orthant and products of Lorentz cones.
 
 TEST INFRASTRUCTURE ONLY, like the rest of this package: the tests and the
 benchmark's CPU leg use it; the solver library never does.  The arithmetic is
@@ -45,7 +46,7 @@ def _load():
     P = ctypes.c_void_p
     i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     lib.ors_create.restype = P
-    lib.ors_create.argtypes = [i32, i32, i64, P, P, P, P, P, f64, i32, f64]
+    lib.ors_create.argtypes = [i32, i32, i64, P, P, P, P, P, i32, i32, P, f64, i32, f64]
     lib.ors_destroy.argtypes = [P]
     lib.ors_destroy.restype = None
     lib.ors_set_state.argtypes = [P, P, P, P]
@@ -73,9 +74,11 @@ def _f64(a):
 
 
 class StandardADMM:
-    """Standard ADMM + CG on one LP (A in CSR, b, c, x >= 0)."""
+    """Standard ADMM + CG on one problem (A in CSR, b, c; K = n_orth orthant
+    coordinates, then Lorentz cones of soc_sizes; default: all orthant)."""
 
-    def __init__(self, m, n, row_ptr, col_idx, val, b, c, mu=1.0, cg_iters=10, cg_tol=0.0):
+    def __init__(self, m, n, row_ptr, col_idx, val, b, c, mu=1.0, cg_iters=10, cg_tol=0.0,
+                 n_orth=None, soc_sizes=()):
         lib = _load()
         self._lib = lib
         self.m, self.n = int(m), int(n)
@@ -84,8 +87,11 @@ class StandardADMM:
         self._val = _f64(val)
         self._b = _f64(b)
         self._c = _f64(c)
+        self._sizes = np.ascontiguousarray(soc_sizes, dtype=np.int32)
+        n_orth = self.n if n_orth is None else int(n_orth)
         h = lib.ors_create(self.m, self.n, int(self._row_ptr[-1]), _ptr(self._row_ptr),
                            _ptr(self._col_idx), _ptr(self._val), _ptr(self._b), _ptr(self._c),
+                           n_orth, int(self._sizes.size), _ptr(self._sizes) if self._sizes.size else None,
                            float(mu), int(cg_iters), float(cg_tol))
         if not h:
             raise ValueError("standard-ADMM oracle rejected the problem")
@@ -93,10 +99,8 @@ class StandardADMM:
 
     @classmethod
     def from_instance(cls, inst, **kw):
-        if inst.get("soc_sizes") is not None and len(inst["soc_sizes"]):
-            raise ValueError("the standard-ADMM oracle takes the orthant cone only")
         return cls(inst["m"], inst["n"], inst["row_ptr"], inst["col_idx"], inst["val"],
-                   inst["b"], inst["c"], **kw)
+                   inst["b"], inst["c"], n_orth=inst["n_orth"], soc_sizes=inst["soc_sizes"], **kw)
 
     def close(self):
         if getattr(self, "_h", None):

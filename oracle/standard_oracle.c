@@ -10,11 +10,13 @@
  * shares no code, header or helper with the HIP library (nor with the UV
  * oracle next to it).
  *
- * Problem (Section II, eq. prob_primal), nonnegative orthant cone:
- *     minimize c'x  subject to  A x = b,  x >= 0.
+ * Problem (Section II, eq. prob_primal):
+ *     minimize c'x  subject to  A x = b,  x in K,
+ * K = R_+^{n_orth} x K_{s_1} x ... (orthant coordinates first, then Lorentz
+ * cones, each with its t coordinate first).
  * Splitting (Section II-A): f = indicator of the cone, g = c'x on the affine
  * set {A x = b}; ADMM on x1 = x2 (Section II-B) with the paper's order:
- *   x1     <- prox_f(x2 - lam/mu)        = max(x2 - lam/mu, 0)
+ *   x1     <- prox_f(x2 - lam/mu)        = proj_K(x2 - lam/mu)  (eq. proj per cone)
  *   x2     <- prox_{g/mu}(x1 + lam/mu)   : with w0 = x1 + lam/mu, the block
  *             system eq. lin
  *                 [ I  A' ] [ w  ]   [ w0 - c/mu ]
@@ -49,6 +51,9 @@
 typedef struct {
     int32_t m, n;
     int64_t nnz;
+    int32_t n_orth, n_soc;
+    int32_t *soc_size;
+    int64_t *soc_off;     /* first coordinate of each Lorentz cone */
     int64_t *rp;          /* CSR: row i owns [rp[i], rp[i+1]) */
     int32_t *ci;
     double *va;
@@ -58,7 +63,7 @@ typedef struct {
     /* state */
     double *x1, *x2, *lam, *nu, *delta;
     /* work */
-    double *v, *g, *r, *p, *q, *tn;
+    double *v, *g, *r, *p, *q, *tn, *a;
     int64_t iter, cg_steps;
 } ors_t;
 
@@ -73,18 +78,38 @@ void ors_destroy(ors_t *h)
     free(h->rp); free(h->ci); free(h->va); free(h->b); free(h->c);
     free(h->x1); free(h->x2); free(h->lam); free(h->nu); free(h->delta);
     free(h->v); free(h->g); free(h->r); free(h->p); free(h->q); free(h->tn);
+    free(h->soc_size); free(h->soc_off); free(h->a);
     free(h);
 }
 
 ors_t *ors_create(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr,
                   const int32_t *col_idx, const double *val, const double *b,
-                  const double *c, double mu, int32_t cg_iters, double cg_tol)
+                  const double *c, int32_t n_orth, int32_t n_soc, const int32_t *soc_sizes,
+                  double mu, int32_t cg_iters, double cg_tol)
 {
     if (m < 1 || n < 1 || nnz < 0 || !(mu > 0.0) || cg_iters < 0 || cg_tol < 0.0) return NULL;
-    if (row_ptr[0] != 0 || row_ptr[m] != nnz) return NULL;
+    if (row_ptr[0] != 0 || row_ptr[m] != nnz || n_orth < 0 || n_soc < 0) return NULL;
+    int64_t tot = n_orth;
+    for (int32_t q = 0; q < n_soc; ++q) {
+        if (soc_sizes[q] < 1) return NULL;
+        tot += soc_sizes[q];
+    }
+    if (tot != n) return NULL;
     ors_t *h = (ors_t *)calloc(1, sizeof(ors_t));
     if (!h) return NULL;
     h->m = m; h->n = n; h->nnz = nnz; h->mu = mu;
+    h->n_orth = n_orth; h->n_soc = n_soc;
+    h->soc_size = (int32_t *)zalloc((size_t)n_soc, sizeof(int32_t));
+    h->soc_off = (int64_t *)zalloc((size_t)n_soc, sizeof(int64_t));
+    h->a = (double *)zalloc((size_t)n, sizeof(double));
+    if (!h->soc_size || !h->soc_off || !h->a) {
+        ors_destroy(h);
+        return NULL;
+    }
+    for (int32_t q = 0, o = n_orth; q < n_soc; o += soc_sizes[q], ++q) {
+        h->soc_size[q] = soc_sizes[q];
+        h->soc_off[q] = o;
+    }
     h->cg_iters = cg_iters; h->cg_tol = cg_tol;
     h->rp = (int64_t *)zalloc((size_t)m + 1, sizeof(int64_t));
     h->ci = (int32_t *)zalloc((size_t)nnz, sizeof(int32_t));
@@ -143,6 +168,26 @@ static double dot(const double *a, const double *b, int64_t len)
     return s;
 }
 
+/* Projection of w (length k) onto the Lorentz cone {w_1 >= ||w_{2..k}||_2}:
+ * zero when the tail norm is at most -w_1, w itself when it is at most w_1,
+ * else the point ((w_1 + a)/2, (1 + w_1/a)/2 * w_{2..k}) with a the tail
+ * norm (eq. proj).  A cone of size 1 is the half line: max(w_1, 0). */
+static void lorentz(const double *w, double *out, int32_t k)
+{
+    double t2 = 0.0;
+    for (int32_t i = 1; i < k; ++i) t2 += w[i] * w[i];
+    const double a = sqrt(t2), w1 = w[0];
+    if (a <= -w1) {
+        for (int32_t i = 0; i < k; ++i) out[i] = 0.0;
+    } else if (a <= w1) {
+        for (int32_t i = 0; i < k; ++i) out[i] = w[i];
+    } else {
+        const double s = 0.5 * (1.0 + w1 / a);
+        out[0] = 0.5 * (w1 + a);
+        for (int32_t i = 1; i < k; ++i) out[i] = s * w[i];
+    }
+}
+
 /* Any pointer may be NULL (zero).  Sets x2, lam and the CG start nu. */
 void ors_set_state(ors_t *h, const double *x2, const double *lam, const double *nu)
 {
@@ -175,9 +220,10 @@ static void iterate_once(ors_t *h)
     const int32_t m = h->m, n = h->n;
     const double mu = h->mu;
     /* x1 <- proj_K(x2 - lam/mu); the cone multiplier delta; v = w0 - c/mu */
+    for (int32_t j = 0; j < n; ++j) h->a[j] = h->x2[j] - h->lam[j] / mu;
+    for (int32_t j = 0; j < h->n_orth; ++j) lorentz(h->a + j, h->x1 + j, 1);
+    for (int32_t q = 0; q < h->n_soc; ++q) lorentz(h->a + h->soc_off[q], h->x1 + h->soc_off[q], h->soc_size[q]);
     for (int32_t j = 0; j < n; ++j) {
-        const double a = h->x2[j] - h->lam[j] / mu;
-        h->x1[j] = a > 0.0 ? a : 0.0;
         h->delta[j] = h->lam[j] + mu * (h->x1[j] - h->x2[j]);
         h->v[j] = h->x1[j] + h->lam[j] / mu - h->c[j] / mu;
     }

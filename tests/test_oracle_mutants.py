@@ -59,6 +59,9 @@ STD_MUTANTS = {
     "lam update sign": ("h->lam[j] += mu * (h->x1[j] - h->x2[j]);", "h->lam[j] -= mu * (h->x1[j] - h->x2[j]);"),
     "residual multiplier not scaled by mu": ("la[i] = h->mu * h->nu[i];", "la[i] = h->nu[i];"),
     "rhs drops b": ("for (int32_t i = 0; i < m; ++i) h->g[i] -= h->b[i];", ""),
+    "Lorentz head sign": ("out[0] = 0.5 * (w1 + a);", "out[0] = 0.5 * (w1 - a);"),
+    "Lorentz tail scale": ("const double s = 0.5 * (1.0 + w1 / a);", "const double s = 0.5 * (1.0 - w1 / a);"),
+    "Lorentz case order": ("} else if (a <= w1) {", "} else if (a <= w1 + 1e-3) {"),
 }
 
 

@@ -6,7 +6,10 @@ what the mathematics fixes:
 * the fixed point at a known primal-dual optimum, for several mu;
 * exact invariants of every iterate (x1 in K, delta in K*, complementarity)
   whatever the CG accuracy, and the dual-residual identity of an exact solve;
-* brute-force vertex enumeration on tiny LPs and a hand-solved LP.
+* brute-force vertex enumeration on tiny LPs and a hand-solved LP;
+* with Lorentz cones: one iteration against the (separately pinned)
+  projection and the dense block solve, cone invariants, closed-form tiny
+  SOCPs.
 """
 import itertools
 
@@ -20,6 +23,12 @@ from paper_2203_05027_amd import instances as I
 def std():
     from oracle import standard
     return standard
+
+
+@pytest.fixture(scope="module")
+def oracle_mod():
+    import oracle
+    return oracle
 
 
 def _dense(inst):
@@ -156,3 +165,79 @@ def test_generator_lp_reaches_known_optimum(std):
     assert r["kkt"] <= 1e-5
     assert r["pobj"] == pytest.approx(inst["p_star"], rel=1e-4)
     assert r["dobj"] == pytest.approx(inst["p_star"], rel=1e-4)
+
+
+# --------------------------------------------------------------------------
+# Lorentz cones
+# --------------------------------------------------------------------------
+def _csr_from_dense(A):
+    rows, cols = np.nonzero(A)
+    row_ptr = np.zeros(A.shape[0] + 1, np.int64)
+    np.cumsum(np.bincount(rows, minlength=A.shape[0]), out=row_ptr[1:])
+    return row_ptr, cols.astype(np.int32), A[rows, cols]
+
+
+@pytest.mark.parametrize("seed,mu", [(61, 1.0), (62, 0.5)])
+def test_one_iteration_with_cones_against_dense_block_solve(std, oracle_mod, seed, mu):
+    """x1 is the projection onto K (the UV oracle's, pinned on its own), x2
+    the dense solve of eq. lin."""
+    inst = I.conic_instance(6, 3, [3, 4, 1], 2, seed=seed)
+    A = _dense(inst)
+    m, n = A.shape
+    rng = np.random.default_rng(seed)
+    x2, lam = rng.standard_normal(n), rng.standard_normal(n)
+    s = std.StandardADMM.from_instance(inst, mu=mu, cg_iters=60, cg_tol=0.0)
+    s.set_state(x2=x2, lam=lam)
+    s.iterate(1)
+    st = s.state()
+    x1 = oracle_mod.project(x2 - lam / mu, inst["n_orth"], inst["soc_sizes"])
+    np.testing.assert_allclose(st["x1"], x1, atol=1e-13)
+    K = np.block([[np.eye(n), A.T], [A, np.zeros((m, m))]])
+    sol = np.linalg.lstsq(K, np.concatenate([x1 + lam / mu - inst["c"] / mu, inst["b"]]), rcond=None)[0]
+    np.testing.assert_allclose(st["x2"], sol[:n], atol=1e-9)
+    np.testing.assert_allclose(st["lam"], lam + mu * (x1 - sol[:n]), atol=1e-9)
+
+
+def _cone_parts(v, n_orth, sizes):
+    parts, off = [v[:n_orth]], n_orth
+    for k in sizes:
+        parts.append(v[off:off + k])
+        off += k
+    return parts
+
+
+def test_cone_invariants_with_inexact_cg(std):
+    inst = I.conic_instance(60, 20, [3, 7, 12, 5, 1, 30], 3, seed=63)
+    s = std.StandardADMM.from_instance(inst, mu=0.9, cg_iters=2, cg_tol=0.0)
+    for _ in range(4):
+        s.iterate(9)
+        st = s.state()
+        tol = 1e-12 * (1 + np.abs(st["lam"]).max() + np.abs(st["x1"]).max())
+        xp = _cone_parts(st["x1"], inst["n_orth"], inst["soc_sizes"])
+        dp = _cone_parts(st["delta"], inst["n_orth"], inst["soc_sizes"])
+        assert xp[0].min() >= 0.0 and dp[0].min() >= -tol
+        for xb, db in zip(xp[1:], dp[1:]):                  # K and K* (self-dual) per cone
+            assert xb[0] >= np.linalg.norm(xb[1:]) - tol
+            assert db[0] >= np.linalg.norm(db[1:]) - tol
+            assert abs(xb @ db) <= 10 * tol * (1 + np.abs(db).max())
+
+
+@pytest.mark.parametrize("u,expect", [((1.0, 2.0), np.sqrt(5.0)), ((3.0, 4.0), 5.0)])
+def test_tiny_socp_closed_form(std, u, expect):
+    """min t s.t. (t, u1, u2) in K_3 with u fixed: the optimum is ||u||."""
+    A = np.array([[0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+    s = std.StandardADMM(2, 3, *_csr_from_dense(A), np.array(u), np.array([1.0, 0, 0]), mu=1.0,
+                         cg_iters=10, n_orth=0, soc_sizes=[3])
+    r = s.solve(1e-10, max_iter=100_000)
+    assert r["pobj"] == pytest.approx(expect, abs=1e-7)
+
+
+def test_socp_two_cones_mixed_orthant(std):
+    """min x1 + 2t s.t. x1 + t = 3, u = (1, 1), x1 >= 0, t >= ||u||:
+    t = sqrt(2), x1 = 3 - sqrt(2)."""
+    A = np.array([[1.0, 1.0, 0.0, 0.0], [0.0, 0.0, 1.0, 0.0], [0.0, 0.0, 0.0, 1.0]])
+    s = std.StandardADMM(3, 4, *_csr_from_dense(A), np.array([3.0, 1.0, 1.0]),
+                         np.array([1.0, 2.0, 0.0, 0.0]), mu=1.0, cg_iters=10, n_orth=1, soc_sizes=[3])
+    r = s.solve(1e-10, max_iter=200_000)
+    np.testing.assert_allclose(s.state()["x1"], [3 - np.sqrt(2), np.sqrt(2), 1, 1], atol=1e-6)
+    assert r["pobj"] == pytest.approx(3 + np.sqrt(2), abs=1e-6)
