@@ -61,6 +61,8 @@ def _load():
     lib.ors_iterate.restype = None
     lib.ors_residuals.argtypes = [P, P]
     lib.ors_residuals.restype = None
+    lib.ors_project.argtypes = [i32, i32, P, P, P]
+    lib.ors_project.restype = None
     _lib = lib
     return lib
 
@@ -71,6 +73,16 @@ def _ptr(a):
 
 def _f64(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def project(w, n_orth: int, soc_sizes=()) -> np.ndarray:
+    """proj_K(w) with this oracle's own projection (eq. proj per cone)."""
+    lib = _load()
+    w = _f64(w)
+    sizes = np.ascontiguousarray(soc_sizes, dtype=np.int32)
+    out = np.empty_like(w)
+    lib.ors_project(int(n_orth), int(sizes.size), _ptr(sizes) if sizes.size else None, _ptr(w), _ptr(out))
+    return out
 
 
 class StandardADMM:

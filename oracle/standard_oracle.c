@@ -188,6 +188,17 @@ static void lorentz(const double *w, double *out, int32_t k)
     }
 }
 
+/* Stand-alone projection onto K = R_+^{n_orth} x K_{sizes[0]} x ... */
+void ors_project(int32_t n_orth, int32_t n_soc, const int32_t *sizes, const double *w, double *out)
+{
+    for (int32_t j = 0; j < n_orth; ++j) lorentz(w + j, out + j, 1);
+    int64_t o = n_orth;
+    for (int32_t q = 0; q < n_soc; ++q) {
+        lorentz(w + o, out + o, sizes[q]);
+        o += sizes[q];
+    }
+}
+
 /* Any pointer may be NULL (zero).  Sets x2, lam and the CG start nu. */
 void ors_set_state(ors_t *h, const double *x2, const double *lam, const double *nu)
 {

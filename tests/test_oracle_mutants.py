@@ -49,7 +49,7 @@ def test_pins_catch_mutant(name, tmp_path):
 STD_SRC = os.path.join(ROOT, "oracle", "standard_oracle.c")
 
 STD_MUTANTS = {
-    "x1 step sign of lam": ("const double a = h->x2[j] - h->lam[j] / mu;", "const double a = h->x2[j] + h->lam[j] / mu;"),
+    "x1 step sign of lam": ("h->a[j] = h->x2[j] - h->lam[j] / mu;", "h->a[j] = h->x2[j] + h->lam[j] / mu;"),
     "v drops c/mu": ("h->v[j] = h->x1[j] + h->lam[j] / mu - h->c[j] / mu;", "h->v[j] = h->x1[j] + h->lam[j] / mu;"),
     "delta from the new x2": ("h->delta[j] = h->lam[j] + mu * (h->x1[j] - h->x2[j]);", "h->delta[j] = h->lam[j];"),
     "CG beta inverted": ("const double beta = rr_new / rr;", "const double beta = rr / rr_new;"),

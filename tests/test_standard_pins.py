@@ -241,3 +241,31 @@ def test_socp_two_cones_mixed_orthant(std):
     r = s.solve(1e-10, max_iter=200_000)
     np.testing.assert_allclose(s.state()["x1"], [3 - np.sqrt(2), np.sqrt(2), 1, 1], atol=1e-6)
     assert r["pobj"] == pytest.approx(3 + np.sqrt(2), abs=1e-6)
+
+
+def test_projection_characterisation(std):
+    """Moreau for a self-dual cone: w = P(w) - P(-w) with P(w), P(-w) in K
+    and orthogonal -- which determines the projection -- on random points,
+    points near the cone's boundary and on it, and size-1 cones (ReLU)."""
+    rng = np.random.default_rng(64)
+    sizes = [1, 2, 3, 5, 8, 13]
+    pts = [rng.standard_normal(sum(sizes) + 4) for _ in range(20)]
+    for eps in (0.0, 1e-9, 1e-6, 1e-4, -1e-6, -1e-4):           # t = ||u|| (1 + eps)
+        w = rng.standard_normal(sum(sizes) + 4)
+        off = 4
+        for k in sizes:
+            if k > 1:
+                w[off] = np.linalg.norm(w[off + 1:off + k]) * (1 + eps) * rng.choice([-1, 1])
+            off += k
+        pts.append(w)
+    for w in pts:
+        p, q = std.project(w, 4, sizes), std.project(-w, 4, sizes)
+        np.testing.assert_allclose(p - q, w, atol=1e-12)
+        np.testing.assert_allclose(p[:4], np.maximum(w[:4], 0.0), atol=0)
+        off = 4
+        for k in sizes:
+            pb, qb = p[off:off + k], q[off:off + k]
+            for v in (pb, qb):
+                assert v[0] >= np.linalg.norm(v[1:]) - 1e-12 * (1 + np.abs(w).max())
+            assert abs(pb @ qb) <= 1e-12 * (1 + np.abs(w).max()) ** 2
+            off += k
