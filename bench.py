@@ -551,7 +551,7 @@ def main():
         log(f"small: {json.dumps(small)}")
 
     standard = None
-    if not args.no_standard and ttk and not len(inst.get("soc_sizes", ())):
+    if not args.no_standard and ttk:
         log("standard ADMM + CG baseline")
         standard = standard_block(inst, args.mu, args.std_cg_iters, args.std_cg_tol, args.check_every,
                                   args.std_cap_s, main_r["ttk_s"])

@@ -345,8 +345,8 @@ void literal_destroy(uv_literal *h);
  * f the cone indicator, g the objective on {A x = b}) with the block system
  * eq. lin solved indirectly every iteration (Section III-B): conjugate
  * gradients on (A A') nu = A (w0 - c/mu) - b, warm-started from the previous
- * nu.  FP64, nonnegative orthant only.  Per iteration:
- *   x1 = max(x2 - lam/mu, 0);  delta = lam + mu (x1 - x2)
+ * nu.  FP64, K as for solver_create.  Per iteration:
+ *   x1 = proj_K(x2 - lam/mu);  delta = lam + mu (x1 - x2)
  *   CG: at most cg_iters steps, stopping once ||r||_2 <= cg_tol (1 + ||b||_2)
  *       or when p'A A'p is not positive
  *   x2 = x1 + lam/mu - c/mu - A'nu;  lam += mu (x1 - x2)
@@ -356,7 +356,9 @@ void literal_destroy(uv_literal *h);
  * others are zero.
  *
  * standard_create: A, b, c as for solver_create (host, copied; invalid CSR
- *   -> UV_EBADCSR); opts: mu, check_every, eps_kkt, max_iter, hip_stream,
+ *   -> UV_EBADCSR); K as for solver_create, or NULL for the orthant (cone
+ *   sizes not summing to n or below 1 -> UV_ECONE; a thread projects a cone,
+ *   so very large cones are slow but allowed); opts: mu, check_every, eps_kkt, max_iter, hip_stream,
  *   use_graph, slabs_row / slabs_col (0, 1, 2 or 4; 0 = the solver's rule);
  *   precision must be UV_FP64 (else UV_EINVAL); cg_iters >= 0,
  *   cg_tol >= 0 (else UV_EINVAL).  Zero start.
@@ -369,8 +371,8 @@ void literal_destroy(uv_literal *h);
  * ------------------------------------------------------------------------ */
 typedef struct uv_standard uv_standard;
 int standard_create(const uv_csr *A, const double *b, const double *c,
-                    const uv_opts *opts, int32_t cg_iters, double cg_tol,
-                    uv_standard **out);
+                    const uv_cones *K, const uv_opts *opts, int32_t cg_iters,
+                    double cg_tol, uv_standard **out);
 int standard_set_state(uv_standard *h, const double *x2, const double *lam,
                        const double *nu);
 int standard_iterate(uv_standard *h, int64_t k, int32_t *done);

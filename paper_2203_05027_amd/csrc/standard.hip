@@ -3,12 +3,12 @@
 // set against (Section II-B, ADMM on the splitting x1 = x2 with f the cone
 // indicator and g the objective on {A x = b}; Section III-B, indirect
 // methods: conjugate gradients warm-started from the previous iteration).
-// FP64, nonnegative orthant.  Every sparse product runs through the slab
+// FP64; K = orthant coordinates, then Lorentz cones.  Every sparse product runs through the slab
 // kernel of the UV solver (spmv.hpp) with the same slab choice, so a
 // comparison of the two measures the methods, not two SpMV codes.
 //
 // One iteration, in the paper's order:
-//   x1 = max(x2 - lam/mu, 0);  delta = lam + mu (x1 - x2);  v = x1 + lam/mu - c/mu
+//   x1 = proj_K(x2 - lam/mu);  delta = lam + mu (x1 - x2);  v = x1 + lam/mu - c/mu
 //   eq. lin with w0 = x1 + lam/mu: eliminating w = v - A'nu leaves
 //   (A A') nu = A v - b, solved by conjugate gradients from the previous nu:
 //   at most cg_iters steps, stopping once ||r||_2 <= cg_tol (1 + ||b||_2) or
@@ -76,15 +76,16 @@ k_std_norms(int m, const double *__restrict__ b, int n, const double *__restrict
     }
 }
 
-// x1 step, the cone multiplier, v and d = v - w (w = A'nu).
+// x1 step on the orthant coordinates [0, n_orth), the cone multiplier, v and
+// d = v - w (w = A'nu).
 __global__ void __launch_bounds__(kWG)
-k_std_x1(int n, const double *__restrict__ x2, const double *__restrict__ lam, const double *__restrict__ c,
+k_std_x1(int n_orth, const double *__restrict__ x2, const double *__restrict__ lam, const double *__restrict__ c,
          const double *__restrict__ w, double *__restrict__ x1, double *__restrict__ delta, double *__restrict__ v,
          double *__restrict__ d, double mu, double inv_mu, const StdStatus *st)
 {
     if (st->done) return;
     const int j = blockIdx.x * kWG + threadIdx.x;
-    if (j >= n) return;
+    if (j >= n_orth) return;
     const double l = lam[j], x2j = x2[j];
     const double a = x2j - l * inv_mu;
     const double x1j = a > 0.0 ? a : 0.0;
@@ -93,6 +94,41 @@ k_std_x1(int n, const double *__restrict__ x2, const double *__restrict__ lam, c
     const double vj = x1j + l * inv_mu - c[j] * inv_mu;
     v[j] = vj;
     d[j] = vj - w[j];
+}
+
+// The same on the Lorentz cones, one thread per cone [off[q], off[q+1]):
+// eq. proj on a = x2 - lam/mu (zero, identity, or the boundary point).
+__global__ void __launch_bounds__(kWG)
+k_std_x1_soc(int n_soc, const int *__restrict__ off, const double *__restrict__ x2,
+             const double *__restrict__ lam, const double *__restrict__ c, const double *__restrict__ w,
+             double *__restrict__ x1, double *__restrict__ delta, double *__restrict__ v, double *__restrict__ d,
+             double mu, double inv_mu, const StdStatus *st)
+{
+    if (st->done) return;
+    const int q = blockIdx.x * kWG + threadIdx.x;
+    if (q >= n_soc) return;
+    const int j0 = off[q], j1 = off[q + 1];
+    const double w1 = x2[j0] - lam[j0] * inv_mu;
+    double t2 = 0.0;
+    for (int j = j0 + 1; j < j1; ++j) {
+        const double a = x2[j] - lam[j] * inv_mu;
+        t2 += a * a;
+    }
+    const double na = sqrt(t2);
+    // x1_j = head for j0, scale * a_j for the tail
+    double head, scale;
+    if (na <= -w1) { head = 0.0; scale = 0.0; }
+    else if (na <= w1) { head = w1; scale = 1.0; }
+    else { head = 0.5 * (w1 + na); scale = 0.5 * (1.0 + w1 / na); }
+    for (int j = j0; j < j1; ++j) {
+        const double l = lam[j], x2j = x2[j];
+        const double x1j = j == j0 ? head : scale * (x2j - l * inv_mu);
+        x1[j] = x1j;
+        delta[j] = l + mu * (x1j - x2j);
+        const double vj = x1j + l * inv_mu - c[j] * inv_mu;
+        v[j] = vj;
+        d[j] = vj - w[j];
+    }
 }
 
 // r = p = sum_s P[s] - b and the partial sums of r'r.
@@ -306,6 +342,8 @@ k_std_finalize(int nr, const double *__restrict__ prow, int nc, const double *__
 
 struct uv_standard {
     int m = 0, n = 0, nnz = 0, S_row = 1, S_col = 1, cg_iters = 10;
+    int n_orth = 0, n_soc = 0;
+    int *soc_off = nullptr;  // n_soc + 1 cone boundaries
     double mu = 1.0, eps = 0.0;
     int check_every = 10;
     int64_t max_iter = 0, host_iter = 0;
@@ -364,7 +402,12 @@ void iteration(uv_standard *h, hipStream_t st, bool check)
     const unsigned gm = blocks_for(m, kWG), gn = blocks_for(n, kWG), gmn = blocks_for(std::max(m, n), kWG);
     const double mu = h->mu, im = 1.0 / h->mu;
     const int *done = &h->st->done, *idle = &h->st->idle;
-    k_std_x1<<<gn, kWG, 0, st>>>(n, h->x2, h->lam, h->c, h->w, h->x1, h->delta, h->v, h->d, mu, im, h->st);
+    if (h->n_orth > 0)
+        k_std_x1<<<blocks_for(h->n_orth, kWG), kWG, 0, st>>>(h->n_orth, h->x2, h->lam, h->c, h->w, h->x1, h->delta,
+                                                              h->v, h->d, mu, im, h->st);
+    if (h->n_soc > 0)
+        k_std_x1_soc<<<blocks_for(h->n_soc, kWG), kWG, 0, st>>>(h->n_soc, h->soc_off, h->x2, h->lam, h->c, h->w,
+                                                                h->x1, h->delta, h->v, h->d, mu, im, h->st);
     prod_row<SR>(h, st, h->d, done);
     k_std_r0<SR><<<gm, kWG, 0, st>>>(m, h->P_row, h->b, h->r, h->p, h->part, h->st);
     k_std_cg_start<<<1, kWG, 0, st>>>((int)gm, h->part, h->st);
@@ -452,8 +495,8 @@ void standard_destroy(uv_standard *h)
     delete h;
 }
 
-int standard_create(const uv_csr *A, const double *b, const double *c, const uv_opts *opts, int32_t cg_iters,
-                    double cg_tol, uv_standard **out)
+int standard_create(const uv_csr *A, const double *b, const double *c, const uv_cones *K, const uv_opts *opts,
+                    int32_t cg_iters, double cg_tol, uv_standard **out)
 {
     if (!out) return UV_EINVAL;
     *out = nullptr;
@@ -477,6 +520,18 @@ int standard_create(const uv_csr *A, const double *b, const double *c, const uv_
             if (k > b0 && A->col_idx[k] <= A->col_idx[k - 1]) return UV_EBADCSR;
         }
     }
+    int32_t n_orth = A->n, n_soc = 0;
+    if (K) {
+        if (K->n_orthant < 0 || K->n_soc < 0 || (K->n_soc > 0 && !K->soc_sizes)) return UV_ECONE;
+        int64_t tot = K->n_orthant;
+        for (int32_t q = 0; q < K->n_soc; ++q) {
+            if (K->soc_sizes[q] < 1) return UV_ECONE;
+            tot += K->soc_sizes[q];
+        }
+        if (tot != A->n) return UV_ECONE;
+        n_orth = K->n_orthant;
+        n_soc = K->n_soc;
+    }
     uv_standard *h = new (std::nothrow) uv_standard();
     if (!h) return UV_ENOMEM;
     auto fail = [&](int code) {
@@ -484,6 +539,8 @@ int standard_create(const uv_csr *A, const double *b, const double *c, const uv_
         return code;
     };
     const int m = A->m, n = A->n, nnz = (int)A->nnz;
+    h->n_orth = n_orth;
+    h->n_soc = n_soc;
     h->m = m;
     h->n = n;
     h->nnz = nnz;
@@ -539,6 +596,15 @@ int standard_create(const uv_csr *A, const double *b, const double *c, const uv_
     if (hipMemcpy(h->b, b, 8 * (size_t)m, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(h->c, c, 8 * (size_t)n, hipMemcpyHostToDevice) != hipSuccess)
         return fail(UV_EHIP);
+    if (n_soc > 0) {
+        std::vector<int> offs(n_soc + 1);
+        offs[0] = n_orth;
+        for (int q = 0; q < n_soc; ++q) offs[q + 1] = offs[q] + K->soc_sizes[q];
+        h->soc_off = salloc<int>(h, n_soc + 1);
+        if (!h->soc_off) return fail(UV_ENOMEM);
+        if (hipMemcpy(h->soc_off, offs.data(), 4 * (size_t)(n_soc + 1), hipMemcpyHostToDevice) != hipSuccess)
+            return fail(UV_EHIP);
+    }
     if (!build_csc(m, n, nnz, h->rp, h->ci, h->va, h->cp, h->ri, h->vc, cnt, bsum, st)) return fail(UV_EHIP);
     h->srp = h->rp; h->sci = h->ci; h->sva = h->va;
     h->scp = h->cp; h->sri = h->ri; h->svc = h->vc;

@@ -577,8 +577,8 @@ def _bind_standard():
     L = lib()
     if not hasattr(L, "_standard_bound"):
         P, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
-        L.standard_create.argtypes = [ctypes.POINTER(UvCsr), P, P, ctypes.POINTER(UvOpts), i32, f64,
-                                      ctypes.POINTER(P)]
+        L.standard_create.argtypes = [ctypes.POINTER(UvCsr), P, P, ctypes.POINTER(UvCones), ctypes.POINTER(UvOpts),
+                                      i32, f64, ctypes.POINTER(P)]
         L.standard_create.restype = ctypes.c_int
         L.standard_set_state.argtypes = [P, P, P, P]
         L.standard_set_state.restype = ctypes.c_int
@@ -598,11 +598,11 @@ def _bind_standard():
 
 class Standard:
     """Baseline: standard two-block ADMM with a warm-started CG solve of the
-    block system every iteration (FP64, orthant cone), on the same sparse
-    product kernels as the UV solver."""
+    block system every iteration (FP64; orthant and Lorentz cones), on the
+    same sparse product kernels as the UV solver."""
 
-    def __init__(self, m, n, row_ptr, col_idx, val, b, c, *, mu=1.0, cg_iters=10, cg_tol=0.0,
-                 check_every=10, eps=1e-4, max_iter=0, slabs_row=0, slabs_col=0, use_graph=True,
+    def __init__(self, m, n, row_ptr, col_idx, val, b, c, *, n_orth=None, soc_sizes=(), mu=1.0, cg_iters=10,
+                 cg_tol=0.0, check_every=10, eps=1e-4, max_iter=0, slabs_row=0, slabs_col=0, use_graph=True,
                  stream=None):
         L = _bind_standard()
         self.m, self.n = int(m), int(n)
@@ -620,18 +620,19 @@ class Standard:
         o.slabs_col = int(slabs_col)
         o.use_graph = 1 if use_graph else 0
         o.hip_stream = stream
+        sizes = np.ascontiguousarray(soc_sizes, dtype=np.int32)
+        cones = UvCones(self.n if n_orth is None else int(n_orth), int(sizes.size),
+                        _ptr(sizes) if sizes.size else None)
         h = ctypes.c_void_p()
         _check(L.standard_create(ctypes.byref(csr), _ptr(_f64(b, self.m)), _ptr(_f64(c, self.n)),
-                                 ctypes.byref(o), int(cg_iters), float(cg_tol), ctypes.byref(h)),
-               "standard_create")
+                                 ctypes.byref(cones), ctypes.byref(o), int(cg_iters), float(cg_tol),
+                                 ctypes.byref(h)), "standard_create")
         self._h = h
 
     @classmethod
     def from_instance(cls, inst, **kw):
-        if inst.get("soc_sizes") is not None and len(inst["soc_sizes"]):
-            raise ValueError("the standard-ADMM baseline takes the orthant cone only")
         return cls(inst["m"], inst["n"], inst["row_ptr"], inst["col_idx"], inst["val"], inst["b"],
-                   inst["c"], **kw)
+                   inst["c"], n_orth=inst["n_orth"], soc_sizes=inst["soc_sizes"], **kw)
 
     def close(self):
         if getattr(self, "_h", None):

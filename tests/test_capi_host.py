@@ -184,9 +184,9 @@ def test_standard_rejects_mixed_precision():
     o.precision = S.UV_MIXED
     h = ctypes.c_void_p()
     L = S._bind_standard()
-    assert L.standard_create(ctypes.byref(csr), S._ptr(b), S._ptr(c), ctypes.byref(o), 2, 0.0,
+    assert L.standard_create(ctypes.byref(csr), S._ptr(b), S._ptr(c), None, ctypes.byref(o), 2, 0.0,
                              ctypes.byref(h)) == S.UV_EINVAL and not h.value
-    assert L.standard_create(None, None, None, None, 2, 0.0, ctypes.byref(h)) == S.UV_EINVAL
+    assert L.standard_create(None, None, None, None, None, 2, 0.0, ctypes.byref(h)) == S.UV_EINVAL
     assert L.standard_iterate(None, 1, None) == S.UV_EINVAL
     assert L.standard_residuals(None, None, None) == S.UV_EINVAL
     assert L.standard_solution(None, None, None, None, None, None) == S.UV_EINVAL
@@ -223,5 +223,13 @@ def test_rejects_nnz_beyond_32bit_indices():
     assert L.solver_create(ctypes.byref(csr), S._ptr(b), S._ptr(c), ctypes.byref(cones), None,
                            ctypes.byref(h)) == S.UV_ETOOBIG and not h.value
     L = S._bind_standard()
-    assert L.standard_create(ctypes.byref(csr), S._ptr(b), S._ptr(c), None, 2, 0.0,
+    assert L.standard_create(ctypes.byref(csr), S._ptr(b), S._ptr(c), None, None, 2, 0.0,
                              ctypes.byref(h)) == S.UV_ETOOBIG and not h.value
+
+
+@pytest.mark.parametrize("n_orth,sizes", [(2, ()), (0, (2,)), (1, (1, 0)), (-1, (4,))])
+def test_standard_rejects_bad_cones(n_orth, sizes):
+    a = GOOD
+    with pytest.raises(S.UvError) as ei:
+        S.Standard(a["m"], a["n"], a["rp"], a["ci"], a["va"], a["b"], a["c"], n_orth=n_orth, soc_sizes=sizes)
+    assert ei.value.code == S.UV_ECONE

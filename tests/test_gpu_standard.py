@@ -140,3 +140,21 @@ def test_empty_rows_make_a_singular_system():
     errs, ro, rg = _compare(inst, 80, cg_iters=10)
     assert max(errs.values()) <= 1e-9, errs
     assert rg["cg_steps"] == ro["cg_steps"] == 800
+
+
+@pytest.mark.parametrize("sizes", [[3, 7, 50, 1, 260] + [5] * 40, [4] * 30])
+def test_cones_match_oracle(sizes):
+    """Orthant part and Lorentz cones of many sizes (one of 260 entries)."""
+    inst = I.conic_instance(900, 211, sizes, 4, seed=46)
+    errs, ro, rg = _compare(inst, 60, mu=0.8, cg_iters=4, check_every=6)
+    assert max(errs.values()) <= 1e-9, errs
+    for k in ("r_prim", "r_dual", "r_gap", "pobj", "dobj"):
+        assert rg[k] == pytest.approx(ro[k], rel=1e-9, abs=1e-13), k
+
+
+def test_full_size_socp_matches_oracle():
+    """The 1e5-cone SOCP in the benchmark's launch shape: 3 iterations, every
+    entry against the oracle."""
+    inst = I.config_instance("socp_large")
+    errs, _, _ = _compare(inst, 3, cg_iters=2)
+    assert max(errs.values()) <= 1e-9, errs
