@@ -142,10 +142,14 @@ def test_empty_rows_make_a_singular_system():
     assert rg["cg_steps"] == ro["cg_steps"] == 800
 
 
-@pytest.mark.parametrize("sizes", [[3, 7, 50, 1, 260] + [5] * 40, [4] * 30])
-def test_cones_match_oracle(sizes):
-    """Orthant part and Lorentz cones of many sizes (one of 260 entries)."""
-    inst = I.conic_instance(900, 211, sizes, 4, seed=46)
+@pytest.mark.parametrize("m,sizes", [(300, [3, 7, 50, 1, 260] + [5] * 40), (150, [4] * 30)])
+def test_cones_match_oracle(m, sizes):
+    """Orthant part and Lorentz cones of many sizes (one of 260 entries).
+    A has full row rank (m < n): with m > n, A A' is singular and a CG of a
+    fixed number of steps amplifies rounding -- the oracle's own iterates
+    move by O(1) when b is perturbed by 1e-15 -- so no two implementations
+    can agree there."""
+    inst = I.conic_instance(m, 211, sizes, 4, seed=46)
     errs, ro, rg = _compare(inst, 60, mu=0.8, cg_iters=4, check_every=6)
     assert max(errs.values()) <= 1e-9, errs
     for k in ("r_prim", "r_dual", "r_gap", "pobj", "dobj"):
