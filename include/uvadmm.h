@@ -357,9 +357,10 @@ void literal_destroy(uv_literal *h);
  *
  * standard_create: A, b, c as for solver_create (host, copied; invalid CSR
  *   -> UV_EBADCSR); K as for solver_create, or NULL for the orthant (cone
- *   sizes not summing to n or below 1 -> UV_ECONE; a thread projects a cone,
- *   so very large cones are slow but allowed); opts: mu, check_every, eps_kkt, max_iter, hip_stream,
- *   use_graph, slabs_row / slabs_col (0, 1, 2 or 4; 0 = the solver's rule);
+ *   sizes not summing to n or below 1 -> UV_ECONE; one thread projects a
+ *   cone, so very large cones are slow but allowed); opts: mu, check_every,
+ *   eps_kkt, max_iter, hip_stream, use_graph, slabs_row / slabs_col (0, 1,
+ *   2 or 4; 0 = the solver's rule);
  *   precision must be UV_FP64 (else UV_EINVAL); cg_iters >= 0,
  *   cg_tol >= 0 (else UV_EINVAL).  Zero start.
  * standard_set_state: x2, lam (n) and the CG start nu (m), host, any NULL =
