@@ -101,46 +101,6 @@ __device__ __forceinline__ T seg_sum(int beg, int end, int lane, int L, const in
     return acc;
 }
 
-// Two segments [b0, e0) and [b1, e1) summed side by side, their loads in
-// flight together; each segment's entries are added in the order seg_sum
-// adds them, so the sums are the same.
-template <int U, typename T, typename TV, typename TS>
-__device__ __forceinline__ void seg_sum2(int b0, int e0, int b1, int e1, int lane, int L,
-                                         const int *__restrict__ idx, const TV *__restrict__ val, const TS *vs,
-                                         int off, T &s0, T &s1)
-{
-    T a0 = 0, a1 = 0;
-    const int len = max(e0 - b0, e1 - b1);
-    for (int t = lane; t < len; t += L * U) {
-        int j0[U], j1[U];
-        TV v0[U], v1[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int k = t + u * L;
-            j0[u] = off;
-            v0[u] = (TV)0;
-            j1[u] = off;
-            v1[u] = (TV)0;
-            if (b0 + k < e0) {
-                j0[u] = idx[b0 + k];
-                v0[u] = val[b0 + k];
-            }
-            if (b1 + k < e1) {
-                j1[u] = idx[b1 + k];
-                v1[u] = val[b1 + k];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int k = t + u * L;
-            if (b0 + k < e0) a0 += (T)v0[u] * (T)vs[j0[u] - off];
-            if (b1 + k < e1) a1 += (T)v1[u] * (T)vs[j1[u] - off];
-        }
-    }
-    s0 = a0;
-    s1 = a1;
-}
-
 // ||b_i||^2, ||c_i||^2 per instance (one workgroup each).
 __global__ void __launch_bounds__(256)
 k_batch_norms(BInst *inst, const double *__restrict__ b64, const double *__restrict__ c64)
@@ -202,73 +162,56 @@ k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__
         const int gr = tid / Lr, lr = tid % Lr, Gr = nthr / Lr;
         int stop = 0;
         for (int k = 0; k < budget && !stop; ++k) {
-            // column pass: p = N x + A'u, x-step, projection onto R_+, delta;
-            // a lane group takes two columns at a time (their loads overlap)
-            for (int jb = 0; jb < n; jb += 2 * Gc) {
-                T atu[2] = {0, 0}, zj[2] = {0, 0}, cj[2] = {0, 0};
-                double d[2] = {0.0, 0.0};
-                int beg[2] = {0, 0}, end[2] = {0, 0};
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int j = jb + h * Gc + gc;
-                    if (j < n) {
-                        beg[h] = cp[c0 + j];
-                        end[h] = cp[c0 + j + 1];
-                        if (lc == 0) {  // the update's own loads, in flight with the sum's
-                            d[h] = delta[c0 + j];
-                            zj[h] = z[c0 + j];
-                            cj[h] = c[c0 + j];
-                        }
+            // column pass: p = N x + A'u, x-step, projection onto R_+, delta
+            for (int jb = 0; jb < n; jb += Gc) {
+                const int j = jb + gc;
+                T atu = 0, zj = 0, cj = 0;
+                double d = 0.0;
+                int beg = 0, end = 0;
+                if (j < n) {
+                    beg = cp[c0 + j];
+                    end = cp[c0 + j + 1];
+                    if (lc == 0) {  // the update's own loads, in flight with the sum's
+                        d = delta[c0 + j];
+                        zj = z[c0 + j];
+                        cj = c[c0 + j];
                     }
+                    atu = seg_sum<4, T>(beg, end, lc, Lc, ri, vc, us, r0);
                 }
-                seg_sum2<4, T>(beg[0], end[0], beg[1], end[1], lc, Lc, ri, vc, us, r0, atu[0], atu[1]);
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int j = jb + h * Gc + gc;
-                    const T a = group_sum_rt(atu[h], Lc);
-                    if (j < n && lc == 0) {
-                        const T dm = (T)(d[h] * inv_mu);
-                        const int cnt = end[h] - beg[h];
-                        const T p = (T)cnt * xs[j] + a;
-                        const T xn = (p + zj[h] + dm - cj[h] * (T)inv_mu) / (T)(1 + cnt);
-                        const T v = xn - dm;
-                        const T zn = v > (T)0 ? v : (T)0;
-                        xs[j] = xn;
-                        z[c0 + j] = zn;
-                        delta[c0 + j] = d[h] + mu * ((double)zn - (double)xn);
-                    }
+                atu = group_sum_rt(atu, Lc);
+                if (j < n && lc == 0) {
+                    const T dm = (T)(d * inv_mu);
+                    const int cnt = end - beg;
+                    const T p = (T)cnt * xs[j] + atu;
+                    const T xn = (p + zj + dm - cj * (T)inv_mu) / (T)(1 + cnt);
+                    const T v = xn - dm;
+                    const T zn = v > (T)0 ? v : (T)0;
+                    xs[j] = xn;
+                    z[c0 + j] = zn;
+                    delta[c0 + j] = d + mu * ((double)zn - (double)xn);
                 }
             }
             __syncthreads();
-            // row pass: q = A x, lambda update, u; two rows at a time per lane group
-            for (int ib = 0; ib < m; ib += 2 * Gr) {
-                T q[2] = {0, 0}, fi[2] = {0, 0}, bi[2] = {0, 0};
-                double l0[2] = {0.0, 0.0};
-                int beg[2] = {0, 0}, end[2] = {0, 0};
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int i = ib + h * Gr + gr;
-                    if (i < m) {
-                        beg[h] = rp[r0 + i];
-                        end[h] = rp[r0 + i + 1];
-                        if (lr == 0) {
-                            fi[h] = fu[r0 + i];
-                            bi[h] = b[r0 + i];
-                            l0[h] = lam[r0 + i];
-                        }
+            // row pass: q = A x, lambda update, u
+            for (int ib = 0; ib < m; ib += Gr) {
+                const int i = ib + gr;
+                T q = 0, fi = 0, bi = 0;
+                double l0 = 0.0;
+                if (i < m) {
+                    const int beg = rp[r0 + i], end = rp[r0 + i + 1];
+                    if (lr == 0) {
+                        fi = fu[r0 + i];
+                        bi = b[r0 + i];
+                        l0 = lam[r0 + i];
                     }
+                    q = seg_sum<4, T>(beg, end, lr, Lr, ci, va, xs, c0);
                 }
-                seg_sum2<4, T>(beg[0], end[0], beg[1], end[1], lr, Lr, ci, va, xs, c0, q[0], q[1]);
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int i = ib + h * Gr + gr;
-                    const T qq = group_sum_rt(q[h], Lr);
-                    if (i < m && lr == 0) {
-                        const T e = fi[h] * (bi[h] - qq);
-                        const double li = l0[h] - mu * (double)e;
-                        lam[r0 + i] = li;
-                        us[i] = (T)((double)e - li * inv_mu);
-                    }
+                q = group_sum_rt(q, Lr);
+                if (i < m && lr == 0) {
+                    const T e = fi * (bi - q);
+                    const double li = l0 - mu * (double)e;
+                    lam[r0 + i] = li;
+                    us[i] = (T)((double)e - li * inv_mu);
                 }
             }
             __syncthreads();
