@@ -28,7 +28,7 @@
 namespace {
 
 constexpr int kMaxThreads = 1024;
-constexpr int kLdsMax = 160 * 1024;  // LDS of one gfx950 CU
+constexpr int kLdsMax = 160 * 1024 - 1024;  // LDS of one gfx950 CU less the kernel's static LDS
 
 struct BInst {
     int m, n;

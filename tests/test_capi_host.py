@@ -141,7 +141,10 @@ def test_batch_rejects_bad_input():
     assert _batch_err([good, bad]) == S.UV_EBADCSR
     assert _batch_err([good], mu=0.0) == S.UV_EINVAL
     assert _batch_err([good], check_every=0) == S.UV_EINVAL
-    # x and u of an instance must fit in one workgroup's LDS (160 KiB)
+    # x and u of an instance must fit in one workgroup's LDS (160 KiB less
+    # the kernel's 1 KiB of static LDS: 20,401 FP64 values are 163,208 bytes)
+    assert _batch_err([dict(good, m=1, n=20_400, row_ptr=[0, 1], col_idx=[0], val=[1.0], b=[1.0],
+                            c=np.ones(20_400))], precision="fp64") == S.UV_ETOOBIG
     n = 41_000
     wide = dict(m=1, n=n, row_ptr=[0, 1], col_idx=[0], val=[1.0], b=[1.0], c=np.ones(n))
     assert _batch_err([good, wide], precision="mixed") == S.UV_ETOOBIG
