@@ -72,13 +72,17 @@ __device__ __forceinline__ void block_sum_rt(double (&v)[K])
     }
 }
 
+// Instance-local row and column numbers fit 16 bits: x and u of an
+// instance must fit in LDS, so m + n < 40,704 in either precision.
+typedef unsigned short lidx_t;
+
 // sum over the entries k = beg + lane, beg + lane + L, ... < end of
-// val[k] * vs[idx[k] - off]: U entries per lane have their index and value
-// loads in flight together (the entries are added in the same order as one
-// at a time, so the result does not depend on U).
+// val[k] * vs[idx[k]] (idx instance-local): U entries per lane have their
+// index and value loads in flight together (the entries are added in the
+// same order as one at a time, so the result does not depend on U).
 template <int U, typename T, typename TV, typename TS>
-__device__ __forceinline__ T seg_sum(int beg, int end, int lane, int L, const int *__restrict__ idx,
-                                     const TV *__restrict__ val, const TS *vs, int off)
+__device__ __forceinline__ T seg_sum(int beg, int end, int lane, int L, const lidx_t *__restrict__ idx,
+                                     const TV *__restrict__ val, const TS *vs)
 {
     T acc = 0;
     for (int k0 = beg + lane; k0 < end; k0 += L * U) {
@@ -87,7 +91,7 @@ __device__ __forceinline__ T seg_sum(int beg, int end, int lane, int L, const in
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int k = k0 + u * L;
-            j[u] = off;
+            j[u] = 0;
             v[u] = (TV)0;
             if (k < end) {
                 j[u] = idx[k];
@@ -96,9 +100,52 @@ __device__ __forceinline__ T seg_sum(int beg, int end, int lane, int L, const in
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (k0 + u * L < end) acc += (T)v[u] * (T)vs[j[u] - off];
+            if (k0 + u * L < end) acc += (T)v[u] * (T)vs[j[u]];
     }
     return acc;
+}
+
+// The same over two vectors at once (the residual check's A z and A x): one
+// stream of the entries for both sums.
+template <int U, typename TS1, typename TS2>
+__device__ __forceinline__ void seg_sum2(int beg, int end, int lane, int L, const lidx_t *__restrict__ idx,
+                                         const double *__restrict__ val, const TS1 *vs1, const TS2 *vs2,
+                                         double &s1, double &s2)
+{
+    double a1 = 0.0, a2 = 0.0;
+    for (int k0 = beg + lane; k0 < end; k0 += L * U) {
+        int j[U];
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u * L;
+            j[u] = 0;
+            v[u] = 0.0;
+            if (k < end) {
+                j[u] = idx[k];
+                v[u] = val[k];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u * L < end) {
+                a1 += v[u] * (double)vs1[j[u]];
+                a2 += v[u] * (double)vs2[j[u]];
+            }
+    }
+    s1 = a1;
+    s2 = a2;
+}
+
+// Instance-local copies of the global row (CSC) and column (CSR) numbers,
+// one workgroup per instance: its entries are contiguous in both forms.
+__global__ void __launch_bounds__(256)
+k_local_idx(const BInst *__restrict__ inst, const int *__restrict__ rp, const int *__restrict__ ci,
+            const int *__restrict__ cp, const int *__restrict__ ri, lidx_t *__restrict__ cl, lidx_t *__restrict__ rl)
+{
+    const BInst &I = inst[blockIdx.x];
+    for (int k = rp[I.row_off] + threadIdx.x; k < rp[I.row_off + I.m]; k += 256) cl[k] = (lidx_t)(ci[k] - I.col_off);
+    for (int k = cp[I.col_off] + threadIdx.x; k < cp[I.col_off + I.n]; k += 256) rl[k] = (lidx_t)(ri[k] - I.row_off);
 }
 
 // ||b_i||^2, ||c_i||^2 per instance (one workgroup each).
@@ -130,9 +177,9 @@ k_batch_start_u(int r0, int m, const double *__restrict__ lam, T *__restrict__ u
 template <typename T>
 __global__ void __launch_bounds__(kMaxThreads)
 k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__restrict__ queue,
-        const int *__restrict__ budget_p, const int *__restrict__ rp, const int *__restrict__ ci,
+        const int *__restrict__ budget_p, const int *__restrict__ rp, const lidx_t *__restrict__ cl,
         const T *__restrict__ va, const double *__restrict__ va64, const int *__restrict__ cp,
-        const int *__restrict__ ri, const T *__restrict__ vc, const double *__restrict__ vc64,
+        const lidx_t *__restrict__ rl, const T *__restrict__ vc, const double *__restrict__ vc64,
         const T *__restrict__ b, const double *__restrict__ b64, const T *__restrict__ fu,
         const T *__restrict__ c, const double *__restrict__ c64, T *__restrict__ x, T *__restrict__ z,
         T *__restrict__ u, double *__restrict__ lam, double *__restrict__ delta, double mu, double inv_mu,
@@ -176,7 +223,7 @@ k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__
                         zj = z[c0 + j];
                         cj = c[c0 + j];
                     }
-                    atu = seg_sum<4, T>(beg, end, lc, Lc, ri, vc, us, r0);
+                    atu = seg_sum<4, T>(beg, end, lc, Lc, rl, vc, us);
                 }
                 atu = group_sum_rt(atu, Lc);
                 if (j < n && lc == 0) {
@@ -204,7 +251,7 @@ k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__
                         bi = b[r0 + i];
                         l0 = lam[r0 + i];
                     }
-                    q = seg_sum<4, T>(beg, end, lr, Lr, ci, va, xs, c0);
+                    q = seg_sum<4, T>(beg, end, lr, Lr, cl, va, xs);
                 }
                 q = group_sum_rt(q, Lr);
                 if (i < m && lr == 0) {
@@ -224,8 +271,7 @@ k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__
                     double qz = 0.0, qx = 0.0;
                     if (i < m) {
                         const int beg = rp[r0 + i], end = rp[r0 + i + 1];
-                        qz = seg_sum<4, double>(beg, end, lr, Lr, ci, va64, z, 0);
-                        qx = seg_sum<4, double>(beg, end, lr, Lr, ci, va64, xs, c0);
+                        seg_sum2<4>(beg, end, lr, Lr, cl, va64, z + c0, xs, qz, qx);
                     }
                     qz = group_sum_rt(qz, Lr);
                     qx = group_sum_rt(qx, Lr);
@@ -239,7 +285,7 @@ k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__
                 for (int jb = 0; jb < n; jb += Gc) {
                     const int j = jb + gc;
                     double atl = 0.0;
-                    if (j < n) atl = seg_sum<4, double>(cp[c0 + j], cp[c0 + j + 1], lc, Lc, ri, vc64, lam, 0);
+                    if (j < n) atl = seg_sum<4, double>(cp[c0 + j], cp[c0 + j + 1], lc, Lc, rl, vc64, lam + r0);
                     atl = group_sum_rt(atl, Lc);
                     if (j < n && lc == 0) {
                         const double r = atl + c64[c0 + j] - delta[c0 + j];
@@ -293,6 +339,7 @@ struct uv_batch {
     bool own_stream = false;
     std::vector<void *> allocs;
     int *rp = nullptr, *ci = nullptr, *cp = nullptr, *ri = nullptr;
+    lidx_t *cl = nullptr, *rl = nullptr;  // instance-local column (CSR) and row (CSC) numbers
     double *va64 = nullptr, *vc64 = nullptr, *b64 = nullptr, *c64 = nullptr;
     void *va = nullptr, *vc = nullptr, *b = nullptr, *c = nullptr, *fu = nullptr;
     void *x = nullptr, *z = nullptr, *u = nullptr;
@@ -332,7 +379,7 @@ int batch_launch(uv_batch *h, hipStream_t st, const int *order, int nq)
     const uv_opts &o = h->o;
     const double mu = o.mu, im = 1.0 / o.mu;
 #define UV_BATCH_ARGS(T)                                                                                     \
-    h->inst, order, nq, h->queue, h->budget, h->rp, h->ci, (const T *)h->va, h->va64, h->cp, h->ri,          \
+    h->inst, order, nq, h->queue, h->budget, h->rp, h->cl, (const T *)h->va, h->va64, h->cp, h->rl,          \
         (const T *)h->vc, h->vc64, (const T *)h->b, h->b64, (const T *)h->fu, (const T *)h->c, h->c64,      \
         (T *)h->x, (T *)h->z, (T *)h->u, h->lam, h->delta, mu, im, o.eps_kkt, o.check_every, (long long)o.max_iter
     const int grid = std::max(1, std::min(h->grid, nq));
@@ -478,6 +525,8 @@ int batch_create(int32_t count, const uv_csr *A, const double *const *b, const d
     h->cp = balloc<int>(h, N + 1);
     h->ri = balloc<int>(h, NNZ);
     h->vc64 = balloc<double>(h, NNZ);
+    h->cl = balloc<lidx_t>(h, NNZ);
+    h->rl = balloc<lidx_t>(h, NNZ);
     h->b64 = balloc<double>(h, M);
     h->c64 = balloc<double>(h, N);
     h->lam = balloc<double>(h, M);
@@ -504,7 +553,7 @@ int batch_create(int32_t count, const uv_csr *A, const double *const *b, const d
     h->budget = balloc<int>(h, 1);
     int *cnt = balloc<int>(h, N);
     int *bsum = balloc<int>(h, blocks_for(N, 4 * kWG));
-    for (void *p : {(void *)h->rp, (void *)h->ci, (void *)h->va64, (void *)h->cp, (void *)h->ri, (void *)h->vc64,
+    for (void *p : {(void *)h->rp, (void *)h->ci, (void *)h->va64, (void *)h->cp, (void *)h->ri, (void *)h->vc64, (void *)h->cl, (void *)h->rl,
                     (void *)h->b64, (void *)h->c64, (void *)h->lam, (void *)h->delta, (void *)h->scratch, h->x,
                     h->z, h->u, h->fu, h->va, h->vc, h->b, h->c, (void *)h->inst, (void *)h->order,
                     (void *)h->queue, (void *)h->budget, (void *)cnt, (void *)bsum})
@@ -582,6 +631,7 @@ int batch_create(int32_t count, const uv_csr *A, const double *const *b, const d
     if (hipMemcpyAsync(h->inst, h->inst_host, sizeof(BInst) * count, hipMemcpyHostToDevice, st) != hipSuccess)
         return fail(UV_EHIP);
     k_batch_norms<<<count, 256, 0, st>>>(h->inst, h->b64, h->c64);
+    k_local_idx<<<count, 256, 0, st>>>(h->inst, h->rp, h->ci, h->cp, h->ri, h->cl, h->rl);
     if (hipGetLastError() != hipSuccess) return fail(UV_EHIP);
     if (hipMemcpyAsync(h->inst_host, h->inst, sizeof(BInst) * count, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
