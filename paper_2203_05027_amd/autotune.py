@@ -19,7 +19,9 @@ DEFAULT_CACHE = os.environ.get(
     "UVADMM_TILE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "uvadmm", "tiles.json"))
 
 THREADS = (256, 512, 1024)
-LANE_PAIRS = ((1, 1), (2, 1), (4, 1), (2, 2), (4, 2), (8, 2), (8, 4))
+# (lanes per row, lanes per column); lanes per column 0 = the sliced column
+# copy (a wavefront per 64 columns, coalesced entry loads)
+LANE_PAIRS = ((1, 1), (2, 1), (4, 1), (2, 2), (4, 2), (8, 2), (8, 4), (1, 0), (2, 0), (4, 0), (8, 0))
 
 
 def signature(batch) -> str:

@@ -35,7 +35,7 @@ struct BInst {
     int row_off, col_off;  // first global row / column of the instance
     int Lr, Lc;            // lanes per row / per column
     int status;
-    int pad;
+    int ch_off;            // first 64-column slice of the instance (sliced column copy)
     long long iter, check_iter;
     double r_prim, r_dual, r_gap, kkt, pobj, dobj, res_ax_b;
     double bnorm2, cnorm2;
@@ -137,6 +137,58 @@ __device__ __forceinline__ void seg_sum2(int beg, int end, int lane, int L, cons
     s2 = a2;
 }
 
+// Sliced column copy (lanes per column 0): the columns of an instance are
+// cut into slices of 64; slice h stores entry t of its column l at
+// s0 + 64 t + l, so lane l's t-th load is one coalesced 64-wide access.  The
+// slice is as wide as its longest column; lane l reads only its cnt
+// entries, in column order, so the sum is that of one lane per column.
+template <int U, typename T, typename TV, typename TS>
+__device__ __forceinline__ T sell_sum(int s0, int w, int cnt, int lane, const lidx_t *__restrict__ idx,
+                                      const TV *__restrict__ val, const TS *vs)
+{
+    T acc = 0;
+    for (int t0 = 0; t0 < w; t0 += U) {
+        int j[U];
+        TV v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = s0 + (t0 + u) * 64 + lane;
+            j[u] = 0;
+            v[u] = (TV)0;
+            if (t0 + u < cnt) {
+                j[u] = idx[k];
+                v[u] = val[k];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (t0 + u < cnt) acc += (T)v[u] * (T)vs[j[u]];
+    }
+    return acc;
+}
+
+// Fills the sliced column copy from the compressed columns, one workgroup
+// per instance (slots past a column's end hold zeros).
+__global__ void __launch_bounds__(256)
+k_sell_fill(const BInst *__restrict__ inst, const int *__restrict__ cp, const int *__restrict__ ri,
+            const double *__restrict__ vc, const int *__restrict__ sptr, lidx_t *__restrict__ sidx,
+            double *__restrict__ sval)
+{
+    const BInst &I = inst[blockIdx.x];
+    const int nch = (I.n + 63) >> 6;
+    for (int p = threadIdx.x; p < nch * 64; p += 256) {
+        const int h = p >> 6, l = p & 63, j = p;  // local column j = 64 h + l
+        const int s0 = sptr[I.ch_off + h], w = (sptr[I.ch_off + h + 1] - s0) >> 6;
+        const int beg = j < I.n ? cp[I.col_off + j] : 0;
+        const int len = j < I.n ? cp[I.col_off + j + 1] - beg : 0;
+        for (int t = 0; t < w; ++t) {
+            const int k = s0 + t * 64 + l;
+            sidx[k] = t < len ? (lidx_t)(ri[beg + t] - I.row_off) : (lidx_t)0;
+            sval[k] = t < len ? vc[beg + t] : 0.0;
+        }
+    }
+}
+
 // Instance-local copies of the global row (CSC) and column (CSR) numbers,
 // one workgroup per instance: its entries are contiguous in both forms.
 __global__ void __launch_bounds__(256)
@@ -183,7 +235,8 @@ k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__
         const T *__restrict__ b, const double *__restrict__ b64, const T *__restrict__ fu,
         const T *__restrict__ c, const double *__restrict__ c64, T *__restrict__ x, T *__restrict__ z,
         T *__restrict__ u, double *__restrict__ lam, double *__restrict__ delta, double mu, double inv_mu,
-        double eps, int check_every, long long max_iter)
+        double eps, int check_every, long long max_iter, const int *__restrict__ sptr,
+        const lidx_t *__restrict__ sidx, const T *__restrict__ sval, const double *__restrict__ sval64)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T *xs = reinterpret_cast<T *>(lds_raw);
@@ -205,11 +258,41 @@ k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__
         for (int j = tid; j < n; j += nthr) xs[j] = x[c0 + j];
         for (int i = tid; i < m; i += nthr) us[i] = u[r0 + i];
         __syncthreads();
-        const int gc = tid / Lc, lc = tid % Lc, Gc = nthr / Lc;
+        // lane groups per column (Lc > 0) or the sliced copy (Lc == 0: a wavefront per 64 columns)
+        const int Lc1 = Lc > 0 ? Lc : 1;
+        const int gc = tid / Lc1, lc = tid % Lc1, Gc = nthr / Lc1;
+        const int wv = tid >> 6, lane64 = tid & 63, nwv = nthr >> 6, nch = (n + 63) >> 6, ch0 = I->ch_off;
         const int gr = tid / Lr, lr = tid % Lr, Gr = nthr / Lr;
         int stop = 0;
         for (int k = 0; k < budget && !stop; ++k) {
             // column pass: p = N x + A'u, x-step, projection onto R_+, delta
+            auto col_update = [&](int j, int cnt, T atu, double d, T zj, T cj) {
+                const T dm = (T)(d * inv_mu);
+                const T p = (T)cnt * xs[j] + atu;
+                const T xn = (p + zj + dm - cj * (T)inv_mu) / (T)(1 + cnt);
+                const T v = xn - dm;
+                const T zn = v > (T)0 ? v : (T)0;
+                xs[j] = xn;
+                z[c0 + j] = zn;
+                delta[c0 + j] = d + mu * ((double)zn - (double)xn);
+            };
+            if (Lc == 0) {
+                for (int h = wv; h < nch; h += nwv) {
+                    const int j = (h << 6) + lane64;
+                    T zj = 0, cj = 0;
+                    double d = 0.0;
+                    int cnt = 0;
+                    if (j < n) {  // the update's own loads, in flight with the sum's
+                        d = delta[c0 + j];
+                        zj = z[c0 + j];
+                        cj = c[c0 + j];
+                        cnt = cp[c0 + j + 1] - cp[c0 + j];
+                    }
+                    const int s0 = sptr[ch0 + h], w = (sptr[ch0 + h + 1] - s0) >> 6;
+                    const T atu = sell_sum<4, T>(s0, w, cnt, lane64, sidx, sval, us);
+                    if (j < n) col_update(j, cnt, atu, d, zj, cj);
+                }
+            } else
             for (int jb = 0; jb < n; jb += Gc) {
                 const int j = jb + gc;
                 T atu = 0, zj = 0, cj = 0;
@@ -226,17 +309,7 @@ k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__
                     atu = seg_sum<4, T>(beg, end, lc, Lc, rl, vc, us);
                 }
                 atu = group_sum_rt(atu, Lc);
-                if (j < n && lc == 0) {
-                    const T dm = (T)(d * inv_mu);
-                    const int cnt = end - beg;
-                    const T p = (T)cnt * xs[j] + atu;
-                    const T xn = (p + zj + dm - cj * (T)inv_mu) / (T)(1 + cnt);
-                    const T v = xn - dm;
-                    const T zn = v > (T)0 ? v : (T)0;
-                    xs[j] = xn;
-                    z[c0 + j] = zn;
-                    delta[c0 + j] = d + mu * ((double)zn - (double)xn);
-                }
+                if (j < n && lc == 0) col_update(j, end - beg, atu, d, zj, cj);
             }
             __syncthreads();
             // row pass: q = A x, lambda update, u
@@ -282,16 +355,26 @@ k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__
                         a[2] += (qx - bi) * (qx - bi);
                     }
                 }
+                auto col_res = [&](int j, double atl) {
+                    const double r = atl + c64[c0 + j] - delta[c0 + j];
+                    a[3] += r * r;
+                    a[4] += c64[c0 + j] * (double)z[c0 + j];
+                };
+                if (Lc == 0) {
+                    for (int h = wv; h < nch; h += nwv) {
+                        const int j = (h << 6) + lane64;
+                        const int cnt = j < n ? cp[c0 + j + 1] - cp[c0 + j] : 0;
+                        const int s0 = sptr[ch0 + h], w = (sptr[ch0 + h + 1] - s0) >> 6;
+                        const double atl = sell_sum<4, double>(s0, w, cnt, lane64, sidx, sval64, lam + r0);
+                        if (j < n) col_res(j, atl);
+                    }
+                } else
                 for (int jb = 0; jb < n; jb += Gc) {
                     const int j = jb + gc;
                     double atl = 0.0;
                     if (j < n) atl = seg_sum<4, double>(cp[c0 + j], cp[c0 + j + 1], lc, Lc, rl, vc64, lam + r0);
                     atl = group_sum_rt(atl, Lc);
-                    if (j < n && lc == 0) {
-                        const double r = atl + c64[c0 + j] - delta[c0 + j];
-                        a[3] += r * r;
-                        a[4] += c64[c0 + j] * (double)z[c0 + j];
-                    }
+                    if (j < n && lc == 0) col_res(j, atl);
                 }
                 block_sum_rt<5>(a);
                 if (tid == 0) {
@@ -340,6 +423,11 @@ struct uv_batch {
     std::vector<void *> allocs;
     int *rp = nullptr, *ci = nullptr, *cp = nullptr, *ri = nullptr;
     lidx_t *cl = nullptr, *rl = nullptr;  // instance-local column (CSR) and row (CSC) numbers
+    // sliced column copy: slice offsets (64 slots per unit of width), local rows, values
+    int *sptr = nullptr;
+    lidx_t *sidx = nullptr;
+    double *sval64 = nullptr;
+    void *sval = nullptr;
     double *va64 = nullptr, *vc64 = nullptr, *b64 = nullptr, *c64 = nullptr;
     void *va = nullptr, *vc = nullptr, *b = nullptr, *c = nullptr, *fu = nullptr;
     void *x = nullptr, *z = nullptr, *u = nullptr;
@@ -381,7 +469,8 @@ int batch_launch(uv_batch *h, hipStream_t st, const int *order, int nq)
 #define UV_BATCH_ARGS(T)                                                                                     \
     h->inst, order, nq, h->queue, h->budget, h->rp, h->cl, (const T *)h->va, h->va64, h->cp, h->rl,          \
         (const T *)h->vc, h->vc64, (const T *)h->b, h->b64, (const T *)h->fu, (const T *)h->c, h->c64,      \
-        (T *)h->x, (T *)h->z, (T *)h->u, h->lam, h->delta, mu, im, o.eps_kkt, o.check_every, (long long)o.max_iter
+        (T *)h->x, (T *)h->z, (T *)h->u, h->lam, h->delta, mu, im, o.eps_kkt, o.check_every, (long long)o.max_iter, \
+        h->sptr, h->sidx, (const T *)h->sval, h->sval64
     const int grid = std::max(1, std::min(h->grid, nq));
     if (o.precision == UV_MIXED)
         k_batch<float><<<grid, h->threads, h->lds_bytes, st>>>(UV_BATCH_ARGS(float));
@@ -389,6 +478,45 @@ int batch_launch(uv_batch *h, hipStream_t st, const int *order, int nq)
         k_batch<double><<<grid, h->threads, h->lds_bytes, st>>>(UV_BATCH_ARGS(double));
 #undef UV_BATCH_ARGS
     return hipGetLastError() == hipSuccess ? UV_OK : UV_EHIP;
+}
+
+// The sliced column copy (lanes per column 0): slices of 64 columns, each as
+// wide as its longest column, filled on the device from the compressed
+// columns.  Needs the instances' col_off / n on the host and cp on the
+// device; sets every instance's ch_off.
+int build_slices(uv_batch *h)
+{
+    const bool mixed = h->o.precision == UV_MIXED;
+    std::vector<int> cph((size_t)h->N + 1);
+    UV_BTRY(hipMemcpy(cph.data(), h->cp, sizeof(int) * cph.size(), hipMemcpyDeviceToHost));
+    std::vector<int> sptr(1, 0);
+    int64_t slots = 0;
+    for (int i = 0; i < h->count; ++i) {
+        BInst &I = h->inst_host[i];
+        I.ch_off = (int)sptr.size() - 1;
+        for (int j0 = 0; j0 < I.n; j0 += 64) {
+            int w = 0;
+            for (int j = j0; j < std::min(j0 + 64, I.n); ++j)
+                w = std::max(w, cph[(size_t)I.col_off + j + 1] - cph[(size_t)I.col_off + j]);
+            slots += 64 * (int64_t)w;
+            if (slots >= ((int64_t)1 << 31)) return UV_ETOOBIG;
+            sptr.push_back((int)slots);
+        }
+    }
+    h->sptr = balloc<int>(h, sptr.size());
+    h->sidx = balloc<lidx_t>(h, slots);
+    h->sval64 = balloc<double>(h, slots);
+    h->sval = mixed ? (void *)balloc<float>(h, slots) : (void *)h->sval64;
+    if (!h->sptr || !h->sidx || !h->sval64 || !h->sval) return UV_ENOMEM;
+    UV_BTRY(hipMemcpy(h->sptr, sptr.data(), sizeof(int) * sptr.size(), hipMemcpyHostToDevice));
+    UV_BTRY(hipMemcpy(h->inst, h->inst_host, sizeof(BInst) * h->count, hipMemcpyHostToDevice));
+    hipStream_t st = h->stream;
+    k_sell_fill<<<h->count, 256, 0, st>>>(h->inst, h->cp, h->ri, h->vc64, h->sptr, h->sidx, h->sval64);
+    if (mixed && slots > 0)
+        k_narrow<float><<<blocks_for(slots, kWG), kWG, 0, st>>>(slots, h->sval64, (float *)h->sval);
+    UV_BTRY(hipGetLastError());
+    UV_BTRY(hipStreamSynchronize(st));
+    return UV_OK;
 }
 
 int apply_tiles(uv_batch *h)
@@ -636,6 +764,7 @@ int batch_create(int32_t count, const uv_csr *A, const double *const *b, const d
     if (hipMemcpyAsync(h->inst_host, h->inst, sizeof(BInst) * count, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return fail(UV_EHIP);
+    if ((rc = build_slices(h)) != UV_OK) return fail(rc);
     if ((rc = apply_tiles(h)) != UV_OK) return fail(rc);
     if ((rc = occupancy_grid(h)) != UV_OK) return fail(rc);
     if ((rc = rebuild_graph(h)) != UV_OK) return fail(rc);
@@ -647,8 +776,10 @@ int batch_set_tiles(uv_batch *h, int32_t threads, const int32_t *lanes)
 {
     if (!h || !lanes) return UV_EINVAL;
     if (threads != 64 && threads != 128 && threads != 256 && threads != 512 && threads != 1024) return UV_EINVAL;
-    for (int k = 0; k < 8; ++k)
-        if (lanes[k] < 1 || lanes[k] > 64 || (lanes[k] & (lanes[k] - 1)) || lanes[k] > threads) return UV_EINVAL;
+    for (int k = 0; k < 8; ++k) {
+        const int lo = k % 2 ? 0 : 1;  // lanes per row >= 1; lanes per column >= 0 (0: sliced copy)
+        if (lanes[k] < lo || lanes[k] > 64 || (lanes[k] & (lanes[k] - 1)) || lanes[k] > threads) return UV_EINVAL;
+    }
     UV_BTRY(hipStreamSynchronize(h->stream));
     UV_BTRY(hipMemcpy(h->inst_host, h->inst, sizeof(BInst) * h->count, hipMemcpyDeviceToHost));
     h->threads = threads;

@@ -42,7 +42,9 @@ def small_mix(seed=0):
 
 
 @pytest.mark.parametrize("threads,lanes", [(256, [2, 1] * 4), (64, [1, 1] * 4),
-                                           (1024, [4, 2, 8, 4, 1, 2, 16, 8]), (512, [64, 32] * 4)])
+                                           (1024, [4, 2, 8, 4, 1, 2, 16, 8]), (512, [64, 32] * 4),
+                                           (1024, [8, 0, 4, 0, 4, 0, 2, 0]), (64, [1, 0] * 4),
+                                           (256, [2, 0, 1, 1, 4, 0, 8, 2])])
 def test_fp64_batch_matches_oracle(threads, lanes):
     insts = small_mix()
     say(f"fp64 batch threads={threads} lanes={lanes}")
@@ -56,6 +58,26 @@ def test_fp64_batch_matches_oracle(threads, lanes):
             errs = {k: rel(g[k], o[k]) for k in KEYS}
             assert max(errs.values()) <= 1e-9, (i, errs)
             assert b.residuals(i)["iter"] == 200
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_sliced_columns_equal_one_lane_per_column(precision):
+    """The sliced column copy (lanes per column 0) adds each column's
+    products in the order one lane per column does: the iterates agree bit
+    for bit, residual checks included."""
+    insts = small_mix(seed=3)
+    out = []
+    for lanes in ([2, 1] * 4, [2, 0] * 4):
+        with Batch(insts, precision=precision, eps=0.0, check_every=7) as b:
+            b.set_tiles(256, lanes)
+            b.iterate(137)
+            out.append([(b.solution(i), b.residuals(i)) for i in range(len(insts))])
+    for i in range(len(insts)):
+        (s1, r1), (s2, r2) = out[0][i], out[1][i]
+        for k in KEYS:
+            assert np.array_equal(s1[k], s2[k]), (i, k)
+        assert r1["kkt"] == r2["kkt"] and r1["iter"] == r2["iter"] and r1["status"] == r2["status"]
+        assert r1["iter"] == 137 or r1["status"] == "converged"  # a tiny instance can reach kkt 0
 
 
 def test_fp64_batch_converges_like_oracle():
@@ -129,12 +151,24 @@ def test_autotune_cache(tmp_path):
         assert rec2["cached"] and b2.get_tiles() == (rec["threads"], rec["lanes"])
 
 
-def test_full_batched_workload_sampled():
+_FULL = {}
+
+
+def full_batch():
+    if "insts" not in _FULL:
+        _FULL["insts"] = [I.batch_lp_instance(i) for i in range(4096)]
+    return _FULL["insts"]
+
+
+@pytest.mark.parametrize("threads,lanes", [(256, [2, 1] * 4), (1024, [8, 0, 4, 0, 2, 0, 2, 0])])
+def test_full_batched_workload_sampled(threads, lanes):
     """All 4096 instances of the batched workload in one launch (FP64), 50
-    iterations; sampled instances checked one by one against the oracle."""
-    insts = [I.batch_lp_instance(i) for i in range(4096)]
-    say(f"4096 instances, total nnz {sum(i['nnz'] for i in insts)}")
+    iterations, lane-group and sliced column passes; sampled instances
+    checked one by one against the oracle."""
+    insts = full_batch()
+    say(f"4096 instances, total nnz {sum(i['nnz'] for i in insts)}, tiles {threads} {lanes}")
     with Batch(insts, precision="fp64", eps=0.0) as b:
+        b.set_tiles(threads, lanes)
         say(f"info {b.info()}")
         b.iterate(50)
         rng = np.random.default_rng(0)
