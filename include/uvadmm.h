@@ -253,7 +253,11 @@ int batch_set_start(uv_batch *h, int32_t i, const double *x, const double *z,
 
 /* Launch tiles: threads per workgroup (64..1024, a power of two) and
  * lanes[8] = (lanes per row, lanes per column) for the four size buckets
- * m < 128, m < 512, m < 2048, m >= 2048 (powers of two, <= threads). */
+ * m < 128, m < 512, m < 2048, m >= 2048 (powers of two, <= threads).
+ * Lanes per column 0 selects the sliced column copy: a wavefront per 64
+ * columns whose t-th entries are stored side by side, so every entry load
+ * is one coalesced access; the sums are those of one lane per column, bit
+ * for bit.  UV_EINVAL for any other value. */
 int batch_set_tiles(uv_batch *h, int32_t threads, const int32_t *lanes);
 int batch_get_tiles(const uv_batch *h, int32_t *threads, int32_t *lanes);
 
