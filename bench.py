@@ -83,15 +83,17 @@ def describe(inst) -> str:
     return f"LP m={m} n={n} nnz={nnz}{rows}, orthant cone{gen}"
 
 
-def alg_bytes(m, n, nnz, precision):
+def alg_bytes(m, n, nnz, precision, index_bytes=4):
     """Algorithmic bytes per launch of the row and column passes: every array
-    counted once, gathered vectors at their compulsory size, int32 indices."""
+    counted once, gathered vectors at their compulsory size, indices of
+    `index_bytes` (int32 in the single-problem solver, 16-bit instance-local
+    in the batched one)."""
     if precision == "fp64":
-        row = 12 * nnz + 4 * (m + 1) + 8 * n + 8 * m + 8 * m + 16 * m + 8 * m
-        col = 12 * nnz + 4 * (n + 1) + 8 * m + 8 * n + 24 * n + 24 * n
+        row = (index_bytes + 8) * nnz + 4 * (m + 1) + 8 * n + 8 * m + 8 * m + 16 * m + 8 * m
+        col = (index_bytes + 8) * nnz + 4 * (n + 1) + 8 * m + 8 * n + 24 * n + 24 * n
     else:  # FP32 A, x, z, u, b, c, F_U; FP64 lambda, delta
-        row = 8 * nnz + 4 * (m + 1) + 4 * n + 4 * m + 4 * m + 16 * m + 4 * m
-        col = 8 * nnz + 4 * (n + 1) + 4 * m + 4 * n + 4 * n + 8 * n + 4 * n + 4 * n + 4 * n + 8 * n
+        row = (index_bytes + 4) * nnz + 4 * (m + 1) + 4 * n + 4 * m + 4 * m + 16 * m + 4 * m
+        col = (index_bytes + 4) * nnz + 4 * (n + 1) + 4 * m + 4 * n + 4 * n + 8 * n + 4 * n + 4 * n + 4 * n + 8 * n
     return row, col
 
 
@@ -276,7 +278,7 @@ def batched_block(steps_sweep=100, ttk_cap=60_000, plain_sample=8, count=4096, l
         rec = autotune.tune(b, iters=20, log=log_fn)
         out["tiles"] = {"threads": rec["threads"], "lanes": rec["lanes"], "cached": rec["cached"]}
         ms = b.time(-1, steps_sweep)
-        rb, cb = alg_bytes(M, N, NNZ, "mixed")
+        rb, cb = alg_bytes(M, N, NNZ, "mixed", index_bytes=2)
         out["sweep_ms"] = ms / steps_sweep
         out["instance_iters_per_s"] = count * steps_sweep / (ms * 1e-3)
         out["sweep_GBs"] = (rb + cb) * steps_sweep / (ms * 1e-3) / 1e9
