@@ -254,8 +254,8 @@ k_col_orth(int n_orth, const int *__restrict__ cp, const int *__restrict__ ri, c
 // Column pass over second-order cones.  Workgroup t owns whole cones
 // [tcone[t], tcone[t+1]) = columns [tcol[t], tcol[t+1]) (at most TC
 // columns): phase 1 computes x and v = x - delta/mu per column into LDS,
-// phase 2 takes each cone's tail norm and its projection case (eq. proj),
-// phase 3 writes x, z and delta.
+// phase 2 takes each cone's tail norm (a wavefront per cone) and its
+// projection case (eq. proj), phase 3 writes x, z and delta.
 template <typename T, int L, int E, int TC, int S>
 __global__ void __launch_bounds__(kWG)
 k_col_soc(const int *__restrict__ tcol, const int *__restrict__ tcone, const int *__restrict__ soc_off,
@@ -292,20 +292,26 @@ k_col_soc(const int *__restrict__ tcol, const int *__restrict__ tcone, const int
         }
     }
     __syncthreads();
-    for (int qi = threadIdx.x; qi < ncones; qi += kWG) {
+    // a wavefront per cone: the lanes take the tail's squares 64 apart, then
+    // a fixed butterfly adds the lanes' sums
+    const int wl = threadIdx.x & 63;
+    for (int qi = threadIdx.x >> 6; qi < ncones; qi += kWG / 64) {
         const int s0 = soc_off[q0 + qi] - c0, s1 = soc_off[q0 + qi + 1] - c0;
         double a2 = 0.0;
-        for (int j = s0 + 1; j < s1; ++j) a2 += (double)sv[j] * (double)sv[j];
-        for (int j = s0; j < s1; ++j) sown[j] = (short)qi;
-        const double w1 = (double)sv[s0];
-        const double alpha = sqrt(a2);
-        double a1, beta;
-        if (alpha <= -w1) { a1 = 0.0; beta = 0.0; }
-        else if (alpha <= w1) { a1 = w1; beta = 1.0; }
-        else { a1 = 0.5 * (w1 + alpha); beta = 0.5 * (1.0 + w1 / alpha); }
-        sa1[qi] = a1;
-        sbeta[qi] = beta;
-        shead[qi] = (short)s0;
+        for (int j = s0 + 1 + wl; j < s1; j += 64) a2 += (double)sv[j] * (double)sv[j];
+        for (int j = s0 + wl; j < s1; j += 64) sown[j] = (short)qi;
+        a2 = uv::group_sum<64>(a2);
+        if (wl == 0) {
+            const double w1 = (double)sv[s0];
+            const double alpha = sqrt(a2);
+            double a1, beta;
+            if (alpha <= -w1) { a1 = 0.0; beta = 0.0; }
+            else if (alpha <= w1) { a1 = w1; beta = 1.0; }
+            else { a1 = 0.5 * (w1 + alpha); beta = 0.5 * (1.0 + w1 / alpha); }
+            sa1[qi] = a1;
+            sbeta[qi] = beta;
+            shead[qi] = (short)s0;
+        }
     }
     __syncthreads();
     for (int jj = threadIdx.x; jj < ncols; jj += kWG) {
