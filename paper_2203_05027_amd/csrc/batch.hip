@@ -937,6 +937,7 @@ int batch_time(uv_batch *h, int32_t bucket, int32_t iters, double *ms)
     cp_(p + 2 * bytes_xz, h->u, bytes_u);
     cp_(p + 2 * bytes_xz + bytes_u, h->lam, 8 * (size_t)h->M);
     cp_(p + 2 * bytes_xz + bytes_u + 8 * (size_t)h->M, h->delta, 8 * (size_t)h->N);
+    const bool saved = rc == UV_OK;  // restore below only from a complete copy
     int *dsel = nullptr;
     if (rc == UV_OK && hipMalloc(&dsel, sizeof(int) * sel.size()) != hipSuccess) rc = UV_ENOMEM;
     if (rc == UV_OK && hipMemcpyAsync(dsel, sel.data(), sizeof(int) * sel.size(), hipMemcpyHostToDevice, st) != hipSuccess)
@@ -967,12 +968,17 @@ int batch_time(uv_batch *h, int32_t bucket, int32_t iters, double *ms)
         *ms = t;
     }
     h->o = keep;
-    // restore
-    cp_(h->x, p, bytes_xz);
-    cp_(h->z, p + bytes_xz, bytes_xz);
-    cp_(h->u, p + 2 * bytes_xz, bytes_u);
-    cp_(h->lam, p + 2 * bytes_xz + bytes_u, 8 * (size_t)h->M);
-    cp_(h->delta, p + 2 * bytes_xz + bytes_u + 8 * (size_t)h->M, 8 * (size_t)h->N);
+    // restore, whatever happened in between (an error keeps its code)
+    auto back = [&](void *dst, const void *src, size_t n) {
+        if (hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, st) != hipSuccess) rc = UV_EHIP;
+    };
+    if (saved) {
+        back(h->x, p, bytes_xz);
+        back(h->z, p + bytes_xz, bytes_xz);
+        back(h->u, p + 2 * bytes_xz, bytes_u);
+        back(h->lam, p + 2 * bytes_xz + bytes_u, 8 * (size_t)h->M);
+        back(h->delta, p + 2 * bytes_xz + bytes_u + 8 * (size_t)h->M, 8 * (size_t)h->N);
+    }
     if (hipMemcpyAsync(h->inst, inst_save.data(), sizeof(BInst) * h->count, hipMemcpyHostToDevice, st) != hipSuccess)
         rc = UV_EHIP;
     if (hipStreamSynchronize(st) != hipSuccess) rc = UV_EHIP;
