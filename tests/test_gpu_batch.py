@@ -60,6 +60,35 @@ def test_fp64_batch_matches_oracle(threads, lanes):
             assert b.residuals(i)["iter"] == 200
 
 
+def holed(m, n, k, seed, zero_rows, zero_cols):
+    """An LP instance with its first rows and columns emptied (b recomputed)."""
+    base = I.lp_instance(m, n, k, seed=seed)
+    A = np.zeros((m, n))
+    rows = np.repeat(np.arange(m), np.diff(base["row_ptr"]))
+    A[rows, base["col_idx"]] = base["val"]
+    A[:zero_rows, :] = 0.0
+    A[:, :zero_cols] = 0.0
+    rr, cc = np.nonzero(A)
+    row_ptr = np.zeros(m + 1, np.int64)
+    np.cumsum(np.bincount(rr, minlength=m), out=row_ptr[1:])
+    return dict(base, row_ptr=row_ptr, col_idx=cc.astype(np.int32), val=A[rr, cc], nnz=int(rr.size),
+                b=A @ base["x0"])
+
+
+@pytest.mark.parametrize("threads,lanes", [(256, [2, 1] * 4), (256, [1, 0] * 4), (64, [4, 2] * 4)])
+def test_empty_rows_and_columns(threads, lanes):
+    """Empty rows and columns (a whole empty 64-column slice among them) in
+    every pass form, against the oracle."""
+    insts = [holed(90, 200, 3, 61, 7, 70), holed(600, 1300, 4, 62, 40, 5), I.lp_instance(20, 30, 2, seed=63)]
+    with Batch(insts, precision="fp64", eps=0.0) as b:
+        b.set_tiles(threads, lanes)
+        b.iterate(150)
+        for i, inst in enumerate(insts):
+            o = oracle_run(inst, 150)
+            errs = {k: rel(b.solution(i)[k], o[k]) for k in KEYS}
+            assert max(errs.values()) <= 1e-9, (i, errs)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_sliced_columns_equal_one_lane_per_column(precision):
     """The sliced column copy (lanes per column 0) adds each column's
