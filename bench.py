@@ -259,10 +259,11 @@ def standard_block(inst, mu, cg_iters, cg_tol, check_every, cap_s, uv_ttk_s=None
 
 
 def batched_block(steps_sweep=100, ttk_cap=60_000, plain_sample=8, count=4096, log_fn=log, cpu_threads=0,
-                  cpu_iters=1000):
+                  cpu_iters=1000, ttk=True):
     """The batched workload: all instances in one persistent launch (mixed
     precision), sweep throughput, time to 1e-4 for the batch, and the plain
-    single-problem solver on a sample of the same instances."""
+    single-problem solver on a sample of the same instances (ttk=False: the
+    sweep alone, its timed launch the last of the block)."""
     from paper_2203_05027_amd import autotune
     from paper_2203_05027_amd import instances as I
     from paper_2203_05027_amd.solver import Batch, Solver
@@ -282,6 +283,8 @@ def batched_block(steps_sweep=100, ttk_cap=60_000, plain_sample=8, count=4096, l
         out["sweep_ms"] = ms / steps_sweep
         out["instance_iters_per_s"] = count * steps_sweep / (ms * 1e-3)
         out["sweep_GBs"] = (rb + cb) * steps_sweep / (ms * 1e-3) / 1e9
+        if not ttk:
+            return out
         t0 = time.perf_counter()
         left = count
         while left:
@@ -459,7 +462,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--no-ttk", action="store_true", help="skip the time-to-1e-4 runs")
+    ap.add_argument("--no-ttk", action="store_true",
+                    help="skip the time-to-1e-4 runs (with --workload lp_batched: the sweep alone)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-workload block")
     ap.add_argument("--no-standard", action="store_true", help="skip the standard ADMM + CG baseline")
     ap.add_argument("--no-small", action="store_true", help="skip the small-LP block")
@@ -504,7 +508,7 @@ def main():
     if args.workload == "lp_family_sweep":
         return bench_family_sweep(args)
     if args.workload == "lp_batched":
-        out = batched_block(cpu_threads=0 if args.no_cpu else host_threads())
+        out = batched_block(cpu_threads=0 if args.no_cpu else host_threads(), ttk=not args.no_ttk)
         print(json.dumps({"metric": "instance-iterations/s of the batched sweep (4096 LPs, one launch)",
                           "value": out["instance_iters_per_s"], "unit": "instance-iter/s", "n_gpus": 1,
                           "higher_is_better": True, "dtype": "f32 sweep / f64 duals", "data": "synthetic",
