@@ -226,7 +226,7 @@ k_batch_start_u(int r0, int m, const double *__restrict__ lam, T *__restrict__ u
     if (i < m) u[r0 + i] = (T)(-lam[r0 + i] * inv_mu);
 }
 
-template <typename T>
+template <typename T, bool ZC>
 __global__ void __launch_bounds__(kMaxThreads)
 k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__restrict__ queue,
         const int *__restrict__ budget_p, const int *__restrict__ rp, const lidx_t *__restrict__ cl,
@@ -255,8 +255,17 @@ k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__
         const int Lr = I->Lr, Lc = I->Lc;
         long long it = I->iter;
         T *us = xs + n;
+        // ZC: z and c of the instance in LDS as well (after u), so the column
+        // pass streams only delta and the entries
+        T *zi = ZC ? us + m : z + c0;
+        const T *ci_ = ZC ? us + m + n : c + c0;
         for (int j = tid; j < n; j += nthr) xs[j] = x[c0 + j];
         for (int i = tid; i < m; i += nthr) us[i] = u[r0 + i];
+        if (ZC)
+            for (int j = tid; j < n; j += nthr) {
+                zi[j] = z[c0 + j];
+                us[m + n + j] = c[c0 + j];
+            }
         __syncthreads();
         // lane groups per column (Lc > 0) or the sliced copy (Lc == 0: a wavefront per 64 columns)
         const int Lc1 = Lc > 0 ? Lc : 1;
@@ -273,7 +282,7 @@ k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__
                 const T v = xn - dm;
                 const T zn = v > (T)0 ? v : (T)0;
                 xs[j] = xn;
-                z[c0 + j] = zn;
+                zi[j] = zn;
                 delta[c0 + j] = d + mu * ((double)zn - (double)xn);
             };
             if (Lc == 0) {
@@ -284,8 +293,8 @@ k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__
                     int cnt = 0;
                     if (j < n) {  // the update's own loads, in flight with the sum's
                         d = delta[c0 + j];
-                        zj = z[c0 + j];
-                        cj = c[c0 + j];
+                        zj = zi[j];
+                        cj = ci_[j];
                         cnt = cp[c0 + j + 1] - cp[c0 + j];
                     }
                     const int s0 = sptr[ch0 + h], w = (sptr[ch0 + h + 1] - s0) >> 6;
@@ -303,8 +312,8 @@ k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__
                     end = cp[c0 + j + 1];
                     if (lc == 0) {  // the update's own loads, in flight with the sum's
                         d = delta[c0 + j];
-                        zj = z[c0 + j];
-                        cj = c[c0 + j];
+                        zj = zi[j];
+                        cj = ci_[j];
                     }
                     atu = seg_sum<4, T>(beg, end, lc, Lc, rl, vc, us);
                 }
@@ -344,7 +353,7 @@ k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__
                     double qz = 0.0, qx = 0.0;
                     if (i < m) {
                         const int beg = rp[r0 + i], end = rp[r0 + i + 1];
-                        seg_sum2<4>(beg, end, lr, Lr, cl, va64, z + c0, xs, qz, qx);
+                        seg_sum2<4>(beg, end, lr, Lr, cl, va64, zi, xs, qz, qx);
                     }
                     qz = group_sum_rt(qz, Lr);
                     qx = group_sum_rt(qx, Lr);
@@ -358,7 +367,7 @@ k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__
                 auto col_res = [&](int j, double atl) {
                     const double r = atl + c64[c0 + j] - delta[c0 + j];
                     a[3] += r * r;
-                    a[4] += c64[c0 + j] * (double)z[c0 + j];
+                    a[4] += c64[c0 + j] * (double)zi[j];
                 };
                 if (Lc == 0) {
                     for (int h = wv; h < nch; h += nwv) {
@@ -403,6 +412,8 @@ k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__
             }
         }
         for (int j = tid; j < n; j += nthr) x[c0 + j] = xs[j];
+        if (ZC)
+            for (int j = tid; j < n; j += nthr) z[c0 + j] = zi[j];
         for (int i = tid; i < m; i += nthr) u[r0 + i] = us[i];
         if (tid == 0) I->iter = it;
         __syncthreads();  // LDS is reused by the next instance
@@ -438,7 +449,10 @@ struct uv_batch {
     int *budget_host = nullptr;  // pinned
     std::vector<int> order_host;
     int threads = 256;
-    int lds_bytes = 0;
+    int xu_bytes = 0;   // x and u of the largest instance (16-byte aligned)
+    int zc_bytes = 0;   // x, u, z and c of the largest instance
+    bool zc = false;    // z and c staged in LDS too
+    int lds_bytes = 0;  // dynamic LDS per workgroup of the launch
     int grid = 0;
     int tiles[2 * 4] = {2, 1, 2, 1, 2, 1, 2, 1};  // (Lr, Lc) per size bucket
     hipGraph_t graph = nullptr;
@@ -473,9 +487,11 @@ int batch_launch(uv_batch *h, hipStream_t st, const int *order, int nq)
         h->sptr, h->sidx, (const T *)h->sval, h->sval64
     const int grid = std::max(1, std::min(h->grid, nq));
     if (o.precision == UV_MIXED)
-        k_batch<float><<<grid, h->threads, h->lds_bytes, st>>>(UV_BATCH_ARGS(float));
+        h->zc ? k_batch<float, true><<<grid, h->threads, h->lds_bytes, st>>>(UV_BATCH_ARGS(float))
+              : k_batch<float, false><<<grid, h->threads, h->lds_bytes, st>>>(UV_BATCH_ARGS(float));
     else
-        k_batch<double><<<grid, h->threads, h->lds_bytes, st>>>(UV_BATCH_ARGS(double));
+        h->zc ? k_batch<double, true><<<grid, h->threads, h->lds_bytes, st>>>(UV_BATCH_ARGS(double))
+              : k_batch<double, false><<<grid, h->threads, h->lds_bytes, st>>>(UV_BATCH_ARGS(double));
 #undef UV_BATCH_ARGS
     return hipGetLastError() == hipSuccess ? UV_OK : UV_EHIP;
 }
@@ -532,27 +548,33 @@ int apply_tiles(uv_batch *h)
     return UV_OK;
 }
 
-int occupancy_grid(uv_batch *h)
+template <typename T, bool ZC>
+int occupancy_of(uv_batch *h, int *per_cu)
 {
     // LDS above the default 64 KiB per workgroup has to be asked for
-    if (h->lds_bytes > 64 * 1024) {
-        hipError_t e = h->o.precision == UV_MIXED
-                           ? hipFuncSetAttribute((const void *)k_batch<float>,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, h->lds_bytes)
-                           : hipFuncSetAttribute((const void *)k_batch<double>,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, h->lds_bytes);
-        if (e != hipSuccess) return UV_ETOOBIG;
-    }
+    if (h->lds_bytes > 64 * 1024 &&
+        hipFuncSetAttribute((const void *)k_batch<T, ZC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            h->lds_bytes) != hipSuccess)
+        return UV_ETOOBIG;
+    UV_BTRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_batch<T, ZC>, h->threads, h->lds_bytes));
+    return UV_OK;
+}
+
+// LDS per workgroup (x and u of the largest instance, and z and c too when
+// every instance's fit: ZC) and the persistent grid the occupancy allows.
+int occupancy_grid(uv_batch *h)
+{
+    h->zc = h->zc_bytes <= kLdsMax;
+    h->lds_bytes = h->zc ? h->zc_bytes : h->xu_bytes;
     int dev = 0, cus = 0;
     UV_BTRY(hipGetDevice(&dev));
     UV_BTRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    int per_cu = 0;
-    hipError_t e = h->o.precision == UV_MIXED
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<float>, h->threads,
-                                                                      h->lds_bytes)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<double>, h->threads,
-                                                                      h->lds_bytes);
-    if (e != hipSuccess) return UV_EHIP;
+    int per_cu = 0, rc;
+    if (h->o.precision == UV_MIXED)
+        rc = h->zc ? occupancy_of<float, true>(h, &per_cu) : occupancy_of<float, false>(h, &per_cu);
+    else
+        rc = h->zc ? occupancy_of<double, true>(h, &per_cu) : occupancy_of<double, false>(h, &per_cu);
+    if (rc != UV_OK) return rc;
     h->grid = std::max(1, per_cu) * cus;
     return UV_OK;
 }
@@ -603,7 +625,7 @@ int batch_create(int32_t count, const uv_csr *A, const double *const *b, const d
         return UV_EINVAL;
     const size_t ts = o.precision == UV_MIXED ? 4 : 8;
     int64_t M = 0, N = 0, NNZ = 0;
-    size_t lds = 0;
+    size_t lds = 0, lds_zc = 0;
     for (int i = 0; i < count; ++i) {
         const uv_csr &a = A[i];
         if (!b[i] || !c[i] || !a.row_ptr || a.m < 1 || a.n < 1 || a.nnz < 0) return UV_EINVAL;
@@ -621,6 +643,7 @@ int batch_create(int32_t count, const uv_csr *A, const double *const *b, const d
         N += a.n;
         NNZ += a.nnz;
         lds = std::max(lds, (size_t)(a.m + a.n) * ts);
+        lds_zc = std::max(lds_zc, (size_t)(a.m + 3 * (size_t)a.n) * ts);
     }
     if (NNZ >= ((int64_t)1 << 31) || M >= ((int64_t)1 << 31) || N >= ((int64_t)1 << 31)) return UV_ETOOBIG;
     if (lds > (size_t)kLdsMax) return UV_ETOOBIG;  // x and u of every instance must fit in LDS
@@ -632,7 +655,9 @@ int batch_create(int32_t count, const uv_csr *A, const double *const *b, const d
     h->N = (int)N;
     h->nnz = (int)NNZ;
     h->o = o;
-    h->lds_bytes = (int)((lds + 15) / 16 * 16);
+    h->xu_bytes = (int)((lds + 15) / 16 * 16);
+    h->zc_bytes = (int)std::min<size_t>((lds_zc + 15) / 16 * 16, (size_t)1 << 30);
+    h->lds_bytes = h->xu_bytes;
     int rc = UV_OK;
     auto fail = [&](int code) {
         batch_destroy(h);
