@@ -204,10 +204,37 @@ k_fam_res_col(int n, int B, const int *__restrict__ cp, const int *__restrict__ 
             part[((size_t)blk * 2 + k) * B + l] = ((s[k][0][lane] + s[k][1][lane]) + s[k][2][lane]) + s[k][3][lane];
 }
 
-// One thread per instance: add the partials in block order, decide.
+constexpr int kFold = 16;  // partial blocks added per thread in the first stage of the check's sum
+static_assert(kResBlocks % kFold == 0, "the partial blocks fold into whole groups");
+
+// First stage of the check's sum: red[(g * 5 + k) * B + l] = the sum, in
+// block order, of component k of instance l over the partial blocks
+// g * kFold .. (g + 1) * kFold - 1 (components 0-2 from the row pass, 3-4
+// from the column pass).  k_fam_finalize then adds the groups in order, so
+// the result is fixed and independent of the launch.
+__global__ void __launch_bounds__(256)
+k_fam_fold(int B, int nblk, const double *__restrict__ prow, const double *__restrict__ pcol, double *__restrict__ red)
+{
+    const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const int ng = nblk / kFold;
+    if (t >= (size_t)ng * 5 * B) return;
+    const int l = (int)(t % B), k = (int)((t / B) % 5), g = (int)(t / ((size_t)B * 5));
+    double v[kFold];
+#pragma unroll
+    for (int r = 0; r < kFold; ++r) {
+        const size_t b = (size_t)g * kFold + r;
+        v[r] = k < 3 ? prow[(b * 3 + k) * B + l] : pcol[(b * 2 + (k - 3)) * B + l];
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int r = 0; r < kFold; ++r) s += v[r];
+    red[t] = s;
+}
+
+// One thread per instance: add the group sums of k_fam_fold in order, decide.
 __global__ void __launch_bounds__(1024)
-k_fam_finalize(int B, int nblk, const double *__restrict__ prow, const double *__restrict__ pcol, double eps,
-               long long max_iter, FInst *inst, FShared *sh)
+k_fam_finalize(int B, int nblk, const double *__restrict__ red, double eps, long long max_iter, FInst *inst,
+               FShared *sh)
 {
     __shared__ int s_active[1024];
     const int l = threadIdx.x;
@@ -221,8 +248,7 @@ k_fam_finalize(int B, int nblk, const double *__restrict__ prow, const double *_
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
                     const int b = b0 + r < nblk ? b0 + r : nblk - 1;
-                    for (int k = 0; k < 3; ++k) t[r][k] = prow[((size_t)b * 3 + k) * B + l];
-                    for (int k = 0; k < 2; ++k) t[r][3 + k] = pcol[((size_t)b * 2 + k) * B + l];
+                    for (int k = 0; k < 5; ++k) t[r][k] = red[((size_t)b * 5 + k) * B + l];
                 }
 #pragma unroll
                 for (int r = 0; r < 8; ++r)
@@ -326,13 +352,44 @@ k_fam_reset(int B, int nb, FInst *inst, FShared *sh, const double *__restrict__ 
     }
 }
 
-// ||b_l||^2 per instance.
-__global__ void __launch_bounds__(1024) k_fam_bnorm(int m, int B, const double *__restrict__ BV64, FInst *inst)
+// ||b_l||^2 per instance in two fixed-order stages: part[c * B + l] sums
+// the rows c, c + kBChunks, c + 2 kBChunks, ... (eight loads in flight),
+// then one thread per instance adds the kBChunks partials in order.
+constexpr int kBChunks = 256;
+static_assert(kBChunks % 8 == 0 && kBChunks <= 3 * kResBlocks, "partials fit the check's row scratch");
+
+__global__ void __launch_bounds__(256)
+k_fam_bnorm_part(int m, int B, const double *__restrict__ BV64, double *__restrict__ part)
+{
+    const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (size_t)kBChunks * B) return;
+    const int l = (int)(t % B), c = (int)(t / B);
+    double s = 0.0;
+    for (int i0 = c; i0 < m; i0 += 8 * kBChunks) {
+        double v[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int i = i0 + r * kBChunks;
+            v[r] = i < m ? BV64[(size_t)i * B + l] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) s += v[r] * v[r];
+    }
+    part[t] = s;
+}
+
+__global__ void __launch_bounds__(1024) k_fam_bnorm(int B, const double *__restrict__ part, FInst *inst)
 {
     const int l = threadIdx.x;
     if (l >= B) return;
     double s = 0.0;
-    for (int i = 0; i < m; ++i) s += BV64[(size_t)i * B + l] * BV64[(size_t)i * B + l];
+    for (int c0 = 0; c0 < kBChunks; c0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r] = part[(size_t)(c0 + r) * B + l];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) s += v[r];
+    }
     inst[l].bnorm2 = s;
 }
 
@@ -349,7 +406,7 @@ struct uv_family {
     void *va = nullptr, *vc = nullptr, *c = nullptr, *fu = nullptr;
     void *X = nullptr, *Z = nullptr, *U = nullptr, *BV = nullptr;
     double *LAM = nullptr, *D = nullptr, *BV64 = nullptr;
-    double *prow = nullptr, *pcol = nullptr;
+    double *prow = nullptr, *pcol = nullptr, *pred = nullptr;
     double *stage = nullptr;  // B * max(m, n) doubles of staging
     FInst *inst = nullptr, *inst_host = nullptr;
     FShared *sh = nullptr, *sh_host = nullptr;
@@ -390,8 +447,11 @@ void fam_iteration_t(uv_family *h, hipStream_t st, bool check)
                                                      (const T *)h->Z, h->BV64, h->LAM, h->prow);
         k_fam_res_col<T><<<kResBlocks * (h->B / 64), 256, 0, st>>>(h->n, h->B, h->cp, h->ri, h->vc64, h->LAM, h->c64, h->D,
                                                      (const T *)h->Z, h->pcol);
-        k_fam_finalize<<<1, 1024, 0, st>>>(h->B, kResBlocks, h->prow, h->pcol, h->o.eps_kkt,
-                                           (long long)h->o.max_iter, h->inst, h->sh);
+        const int ng = kResBlocks / kFold;
+        k_fam_fold<<<blocks_for((int64_t)ng * 5 * h->B, 256), 256, 0, st>>>(h->B, kResBlocks, h->prow, h->pcol,
+                                                                           h->pred);
+        k_fam_finalize<<<1, 1024, 0, st>>>(h->B, ng, h->pred, h->o.eps_kkt, (long long)h->o.max_iter, h->inst,
+                                           h->sh);
     }
 }
 
@@ -532,6 +592,7 @@ int family_create(const uv_csr *A, const double *c, int32_t B, const uv_opts *op
     h->BV64 = falloc<double>(h, Bm);
     h->prow = falloc<double>(h, (size_t)kResBlocks * 3 * B);
     h->pcol = falloc<double>(h, (size_t)kResBlocks * 2 * B);
+    h->pred = falloc<double>(h, (size_t)(kResBlocks / kFold) * 5 * B);
     h->stage = falloc<double>(h, (size_t)B * std::max(m, n));
     h->inst = falloc<FInst>(h, B);
     h->sh = falloc<FShared>(h, 1);
@@ -539,7 +600,7 @@ int family_create(const uv_csr *A, const double *c, int32_t B, const uv_opts *op
     int *bsum = falloc<int>(h, blocks_for(n, 4 * kWG));
     for (void *p : {(void *)h->rp, (void *)h->ci, (void *)h->va64, (void *)h->cp, (void *)h->ri, (void *)h->vc64,
                     (void *)h->c64, h->fu, h->va, h->vc, h->c, h->X, h->Z, h->U, h->BV, (void *)h->LAM,
-                    (void *)h->D, (void *)h->BV64, (void *)h->prow, (void *)h->pcol, (void *)h->stage,
+                    (void *)h->D, (void *)h->BV64, (void *)h->prow, (void *)h->pcol, (void *)h->pred, (void *)h->stage,
                     (void *)h->inst, (void *)h->sh, (void *)cnt, (void *)bsum})
         if (!p) return fail(UV_ENOMEM);
     if (hipHostMalloc((void **)&h->inst_host, sizeof(FInst) * B, hipHostMallocDefault) != hipSuccess) {
@@ -597,7 +658,9 @@ int family_set_rhs(uv_family *h, int32_t nb, const double *b)
     int rc;
     if ((rc = upload_cols<double>(h, b, h->m, h->BV, false)) != UV_OK) return rc;
     if ((rc = upload_cols<double>(h, b, h->m, h->BV64, true)) != UV_OK) return rc;
-    k_fam_bnorm<<<1, 1024, 0, h->stream>>>(h->m, h->B, h->BV64, h->inst);
+    // the check's row partials serve as scratch (kResBlocks * 3 * B >= kBChunks * B doubles)
+    k_fam_bnorm_part<<<blocks_for((int64_t)kBChunks * h->B, 256), 256, 0, h->stream>>>(h->m, h->B, h->BV64, h->prow);
+    k_fam_bnorm<<<1, 1024, 0, h->stream>>>(h->B, h->prow, h->inst);
     UV_FTRY(hipGetLastError());
     return family_set_start(h, nullptr, nullptr, nullptr, nullptr);
 }
