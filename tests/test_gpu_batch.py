@@ -189,6 +189,27 @@ def full_batch():
     return _FULL["insts"]
 
 
+def test_full_batched_workload_mixed_as_benchmarked():
+    """The benchmark's configuration: all 4096 instances, mixed precision
+    (z and c staged in LDS beside x and u), the tiles the search picks there
+    (one bucket on the sliced column copy), 50 iterations; sampled instances
+    against the FP64 oracle within the mixed-precision bar (1e-4 relative)."""
+    insts = full_batch()
+    with Batch(insts, precision="mixed", eps=0.0) as b:
+        b.set_tiles(1024, [8, 2, 4, 0, 2, 1, 2, 0])
+        info = b.info()
+        say(f"mixed info {info}")
+        assert info["lds_bytes"] >= 4 * max(i["m"] + 3 * i["n"] for i in insts)  # z and c staged
+        b.iterate(50)
+        rng = np.random.default_rng(1)
+        big = int(np.argmax([i["m"] for i in insts]))
+        for i in sorted(set(rng.integers(0, 4096, 6).tolist() + [big])):
+            o = oracle_run(insts[i], 50)
+            errs = {k: rel(b.solution(i)[k], o[k]) for k in KEYS}
+            say(f"instance {i} m={insts[i]['m']} (mixed): {errs}")
+            assert max(errs.values()) <= 1e-4, (i, errs)
+
+
 @pytest.mark.parametrize("threads,lanes", [(256, [2, 1] * 4), (1024, [8, 0, 4, 0, 2, 0, 2, 0])])
 def test_full_batched_workload_sampled(threads, lanes):
     """All 4096 instances of the batched workload in one launch (FP64), 50
