@@ -123,6 +123,22 @@ def _f64(a, size=None):
     return a
 
 
+def _csr(m, row_ptr, col_idx, val):
+    """Contiguous int64 / int32 / float64 copies of a CSR matrix with m rows,
+    checked for lengths the library cannot see (it reads m + 1 row offsets
+    and row_ptr[m] indices and values); the values themselves (order,
+    ranges) are the library's to check.  Returns (rp, ci, va, nnz)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    va = np.ascontiguousarray(val, dtype=np.float64)
+    if rp.ndim != 1 or rp.size != int(m) + 1:
+        raise ValueError(f"row_ptr needs m + 1 = {int(m) + 1} entries, got {rp.size}")
+    nnz = int(rp[-1])
+    if nnz < 0 or ci.size < nnz or va.size < nnz:
+        raise ValueError(f"row_ptr[m] = {nnz} entries, but col_idx has {ci.size} and val {va.size}")
+    return rp, ci, va, nnz
+
+
 def default_opts() -> UvOpts:
     o = UvOpts()
     lib().uv_default_opts(ctypes.byref(o))
@@ -143,11 +159,9 @@ class Solver:
                  criterion="kkt", eps_abs=0.0, slab_kernel="auto", use_graph=True, stream=None):
         L = lib()
         self.m, self.n = int(m), int(n)
-        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
-        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
-        va = np.ascontiguousarray(val, dtype=np.float64)
+        rp, ci, va, nnz = _csr(self.m, row_ptr, col_idx, val)
         sizes = np.ascontiguousarray(soc_sizes, dtype=np.int32)
-        csr = UvCsr(self.m, self.n, int(rp[-1]) if rp.size else 0, _ptr(rp), _ptr(ci), _ptr(va))
+        csr = UvCsr(self.m, self.n, nnz, _ptr(rp), _ptr(ci), _ptr(va))
         cones = UvCones(int(n_orth), int(sizes.size), _ptr(sizes) if sizes.size else None)
         o = default_opts()
         o.mu = float(mu)
@@ -285,13 +299,11 @@ class Batch:
         bp = (ctypes.c_void_p * self.count)()
         cpp = (ctypes.c_void_p * self.count)()
         for k, inst in enumerate(instances):
-            rp = np.ascontiguousarray(inst["row_ptr"], dtype=np.int64)
-            ci = np.ascontiguousarray(inst["col_idx"], dtype=np.int32)
-            va = np.ascontiguousarray(inst["val"], dtype=np.float64)
+            rp, ci, va, nnz = _csr(self.ms[k], inst["row_ptr"], inst["col_idx"], inst["val"])
             bb = _f64(inst["b"], self.ms[k])
             cc = _f64(inst["c"], self.ns[k])
             keep += [rp, ci, va, bb, cc]
-            csrs[k] = UvCsr(self.ms[k], self.ns[k], int(rp[-1]), _ptr(rp), _ptr(ci), _ptr(va))
+            csrs[k] = UvCsr(self.ms[k], self.ns[k], nnz, _ptr(rp), _ptr(ci), _ptr(va))
             bp[k] = bb.ctypes.data
             cpp[k] = cc.ctypes.data
         o = default_opts()
@@ -411,11 +423,9 @@ class Family:
             _bind_family(L)
             L._family_bound = True
         self.m, self.n, self.B = int(m), int(n), int(B)
-        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
-        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
-        va = np.ascontiguousarray(val, dtype=np.float64)
+        rp, ci, va, nnz = _csr(self.m, row_ptr, col_idx, val)
         cc = _f64(c, self.n)
-        csr = UvCsr(self.m, self.n, int(rp[-1]), _ptr(rp), _ptr(ci), _ptr(va))
+        csr = UvCsr(self.m, self.n, nnz, _ptr(rp), _ptr(ci), _ptr(va))
         o = default_opts()
         o.mu = float(mu)
         o.precision = {"fp64": UV_FP64, "mixed": UV_MIXED}[precision]
@@ -521,10 +531,7 @@ class Literal:
             L.literal_destroy.restype = None
             L._literal_bound = True
         self.m, self.n = int(m), int(n)
-        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
-        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
-        va = np.ascontiguousarray(val, dtype=np.float64)
-        self.nnz = int(rp[-1])
+        rp, ci, va, self.nnz = _csr(self.m, row_ptr, col_idx, val)
         csr = UvCsr(self.m, self.n, self.nnz, _ptr(rp), _ptr(ci), _ptr(va))
         o = default_opts()
         o.mu = float(mu)
@@ -606,10 +613,7 @@ class Standard:
                  stream=None):
         L = _bind_standard()
         self.m, self.n = int(m), int(n)
-        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
-        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
-        va = np.ascontiguousarray(val, dtype=np.float64)
-        self.nnz = int(rp[-1])
+        rp, ci, va, self.nnz = _csr(self.m, row_ptr, col_idx, val)
         csr = UvCsr(self.m, self.n, self.nnz, _ptr(rp), _ptr(ci), _ptr(va))
         o = default_opts()
         o.mu = float(mu)

@@ -7,6 +7,7 @@ import re
 
 import numpy as np
 import pytest
+from hypothesis import given, settings, strategies as st
 
 from paper_2203_05027_amd import solver as S
 
@@ -236,3 +237,53 @@ def test_standard_rejects_bad_cones(n_orth, sizes):
     with pytest.raises(S.UvError) as ei:
         S.Standard(a["m"], a["n"], a["rp"], a["ci"], a["va"], a["b"], a["c"], n_orth=n_orth, soc_sizes=sizes)
     assert ei.value.code == S.UV_ECONE
+
+
+def _csr_is_valid(m, n, rp, ci):
+    if rp[0] != 0:
+        return False
+    for i in range(m):
+        if rp[i + 1] < rp[i] or rp[i + 1] > rp[m]:
+            return False
+        row = ci[rp[i]:rp[i + 1]]
+        if any(j < 0 or j >= n for j in row) or any(b <= a for a, b in zip(row, row[1:])):
+            return False
+    return True
+
+
+@settings(max_examples=400, deadline=None)
+@given(st.data())
+def test_csr_validation_agrees_with_a_plain_check(data):
+    """Random small CSR inputs, malformed about half the time (offsets out of
+    order, indices out of range, repeated or unsorted within a row): the
+    library answers UV_EBADCSR exactly when a plain reading of the format
+    says the input is malformed (a well-formed one then fails only for the
+    missing GPU, or succeeds on one)."""
+    m = data.draw(st.integers(1, 5), "m")
+    n = data.draw(st.integers(1, 6), "n")
+    nnz = data.draw(st.integers(0, 12), "nnz")
+    inner = sorted(data.draw(st.lists(st.integers(0, nnz), min_size=m - 1, max_size=m - 1), "rp"))
+    rp = [0] + inner + [nnz]
+    if m > 1 and data.draw(st.booleans(), "swap offsets"):
+        i = data.draw(st.integers(1, m - 1), "at")
+        rp[i] = data.draw(st.integers(-1, nnz + 1), "offset")
+    if data.draw(st.booleans(), "sorted rows"):
+        ci = []
+        for i in range(m):
+            k = max(0, min(nnz, rp[i + 1]) - max(0, rp[i]))
+            ci += sorted(data.draw(st.lists(st.integers(0, n - 1), min_size=k, max_size=k, unique=True), "row")) \
+                if k <= n else list(range(k))
+        ci = (ci + [0] * nnz)[:nnz]
+    else:
+        ci = data.draw(st.lists(st.integers(-1, n), min_size=nnz, max_size=nnz), "ci")
+    va = [1.0] * nnz
+    valid = _csr_is_valid(m, n, rp, ci)
+    try:
+        S.Solver(m, n, rp, ci, va, np.ones(m), np.ones(n), n).close()
+        code = S.UV_OK
+    except S.UvError as e:
+        code = e.code
+    if valid:
+        assert code not in (S.UV_EBADCSR, S.UV_EINVAL), (rp, ci, code)
+    else:
+        assert code == S.UV_EBADCSR, (rp, ci, code)
