@@ -287,3 +287,29 @@ def test_csr_validation_agrees_with_a_plain_check(data):
         assert code not in (S.UV_EBADCSR, S.UV_EINVAL), (rp, ci, code)
     else:
         assert code == S.UV_EBADCSR, (rp, ci, code)
+
+
+@settings(max_examples=300, deadline=None)
+@given(st.data())
+def test_cone_validation_agrees_with_a_plain_check(data):
+    """Random cone specifications on a well-formed A: UV_ECONE exactly when
+    the orthant count is negative, a Lorentz cone has fewer than 1 or more
+    than UV_MAX_CONE coordinates, or the sizes do not add up to n."""
+    n = data.draw(st.integers(1, 12), "n")
+    n_orth = data.draw(st.integers(-1, n + 1), "n_orth")
+    sizes = data.draw(st.lists(st.integers(-1, 8), max_size=4), "sizes")
+    if data.draw(st.booleans(), "huge cone"):
+        sizes.append(1025)
+    m = 2
+    rp = [0, 1, 2]
+    ci = [0, min(1, n - 1)] if n > 1 else [0, 0]
+    valid = n_orth >= 0 and all(1 <= q <= 1024 for q in sizes) and n_orth + sum(sizes) == n
+    try:
+        S.Solver(m, n, rp, ci, [1.0, 2.0], np.ones(m), np.ones(n), n_orth, sizes).close()
+        code = S.UV_OK
+    except S.UvError as e:
+        code = e.code
+    if valid:
+        assert code not in (S.UV_ECONE, S.UV_EBADCSR, S.UV_EINVAL), (n_orth, sizes, code)
+    else:
+        assert code == S.UV_ECONE, (n_orth, sizes, code)
