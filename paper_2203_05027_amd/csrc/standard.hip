@@ -96,8 +96,10 @@ k_std_x1(int n_orth, const double *__restrict__ x2, const double *__restrict__ l
     d[j] = vj - w[j];
 }
 
-// The same on the Lorentz cones, one thread per cone [off[q], off[q+1]):
-// eq. proj on a = x2 - lam/mu (zero, identity, or the boundary point).
+// The same on the Lorentz cones, a wavefront per cone [off[q], off[q+1]):
+// the lanes take the cone's coordinates 64 apart (coalesced), a fixed
+// butterfly adds the tail's squares, then eq. proj on a = x2 - lam/mu (zero,
+// identity, or the boundary point).
 __global__ void __launch_bounds__(kWG)
 k_std_x1_soc(int n_soc, const int *__restrict__ off, const double *__restrict__ x2,
              const double *__restrict__ lam, const double *__restrict__ c, const double *__restrict__ w,
@@ -105,22 +107,22 @@ k_std_x1_soc(int n_soc, const int *__restrict__ off, const double *__restrict__ 
              double mu, double inv_mu, const StdStatus *st)
 {
     if (st->done) return;
-    const int q = blockIdx.x * kWG + threadIdx.x;
-    if (q >= n_soc) return;
+    const int q = blockIdx.x * (kWG / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (q >= n_soc) return;  // the whole wavefront leaves
     const int j0 = off[q], j1 = off[q + 1];
-    const double w1 = x2[j0] - lam[j0] * inv_mu;
     double t2 = 0.0;
-    for (int j = j0 + 1; j < j1; ++j) {
+    for (int j = j0 + 1 + lane; j < j1; j += 64) {
         const double a = x2[j] - lam[j] * inv_mu;
         t2 += a * a;
     }
-    const double na = sqrt(t2);
+    const double na = sqrt(uv::group_sum<64>(t2));
+    const double w1 = x2[j0] - lam[j0] * inv_mu;
     // x1_j = head for j0, scale * a_j for the tail
     double head, scale;
     if (na <= -w1) { head = 0.0; scale = 0.0; }
     else if (na <= w1) { head = w1; scale = 1.0; }
     else { head = 0.5 * (w1 + na); scale = 0.5 * (1.0 + w1 / na); }
-    for (int j = j0; j < j1; ++j) {
+    for (int j = j0 + lane; j < j1; j += 64) {
         const double l = lam[j], x2j = x2[j];
         const double x1j = j == j0 ? head : scale * (x2j - l * inv_mu);
         x1[j] = x1j;
@@ -406,7 +408,7 @@ void iteration(uv_standard *h, hipStream_t st, bool check)
         k_std_x1<<<blocks_for(h->n_orth, kWG), kWG, 0, st>>>(h->n_orth, h->x2, h->lam, h->c, h->w, h->x1, h->delta,
                                                               h->v, h->d, mu, im, h->st);
     if (h->n_soc > 0)
-        k_std_x1_soc<<<blocks_for(h->n_soc, kWG), kWG, 0, st>>>(h->n_soc, h->soc_off, h->x2, h->lam, h->c, h->w,
+        k_std_x1_soc<<<blocks_for(h->n_soc, kWG / 64), kWG, 0, st>>>(h->n_soc, h->soc_off, h->x2, h->lam, h->c, h->w,
                                                                 h->x1, h->delta, h->v, h->d, mu, im, h->st);
     prod_row<SR>(h, st, h->d, done);
     k_std_r0<SR><<<gm, kWG, 0, st>>>(m, h->P_row, h->b, h->r, h->p, h->part, h->st);
