@@ -114,3 +114,65 @@ def test_random_batches_match_oracle(data):
             o.iterate(iters)
             errs = errors(b.solution(i), o.state())
             assert max(errs.values()) <= 1e-9, (i, errs)
+
+
+STD_KEYS = ("x1", "x2", "lam", "nu", "delta")
+
+
+@settings(max_examples=100, deadline=None, derandomize=True,
+          suppress_health_check=[HealthCheck.too_slow, HealthCheck.data_too_large])
+@given(data=st.data())
+def test_random_standard_problems_match_oracle(data):
+    """The standard-ADMM + CG baseline on drawn problems with m well below n
+    (A A' nonsingular: a singular one makes the CG solve ill-posed, see the
+    baseline's own tests), cone mixes, CG depth and mu, against its oracle."""
+    from oracle import standard as std_oracle
+    from paper_2203_05027_amd.solver import Standard
+    m = data.draw(st.integers(1, 150), "m")
+    n_orth = data.draw(st.integers(0, 200), "n_orth")
+    sizes = data.draw(st.lists(st.integers(1, 120), max_size=4), "sizes")
+    short = 2 * m + 1 - (n_orth + sum(sizes))
+    if short > 0:
+        n_orth += short
+    k = data.draw(st.integers(2, min(4, m)) if m >= 2 else st.just(1), "k")
+    inst = I.conic_instance(m, n_orth, sizes, k, seed=data.draw(st.integers(0, 10_000), "seed"))
+    mu = data.draw(st.sampled_from([0.5, 1.0, 3.0]), "mu")
+    cg = data.draw(st.sampled_from([1, 2, 5]), "cg")
+    iters = data.draw(st.integers(1, 20), "iters")
+    orc = std_oracle.StandardADMM.from_instance(inst, mu=mu, cg_iters=cg, cg_tol=0.0)
+    orc.iterate(iters)
+    o = orc.state()
+    with Standard.from_instance(inst, mu=mu, cg_iters=cg, cg_tol=0.0, eps=0.0, check_every=5) as s:
+        s.iterate(iters)
+        g = s.solution()
+    scale = max(max(float(np.abs(o[key]).max()) for key in STD_KEYS), 1e-30)
+    errs = {key: float(np.abs(g[key] - o[key]).max()) / scale for key in STD_KEYS}
+    assert max(errs.values()) <= 1e-9, (inst["m"], inst["n"], errs)
+
+
+@settings(max_examples=40, deadline=None, derandomize=True,
+          suppress_health_check=[HealthCheck.too_slow, HealthCheck.data_too_large])
+@given(data=st.data())
+def test_random_families_match_oracle(data):
+    """Parametric families (one A and c, many b) of drawn shapes, group sizes
+    and member counts, every member against its own oracle run."""
+    from paper_2203_05027_amd.solver import Family
+    m = data.draw(st.integers(1, 200), "m")
+    n = data.draw(st.integers(m + 1, 2 * m + 50), "n")
+    k = data.draw(st.integers(1, min(4, m)), "k")
+    fam = I.ParametricFamily(m=m, n=n, k=k, p=4, seed=data.draw(st.integers(0, 10_000), "seed"))
+    B = data.draw(st.sampled_from([64, 128]), "B")
+    nb = data.draw(st.integers(1, B), "nb")
+    iters = data.draw(st.integers(1, 30), "iters")
+    insts = [fam.instance(fam.theta(5000 + i, p=4)) for i in range(nb)]
+    with Family(fam.m, fam.n, fam.row_ptr, fam.col_idx, fam.val, fam.c, B=B, precision="fp64",
+                eps=0.0, check_every=4) as F:
+        F.set_rhs(np.stack([i["b"] for i in insts]))
+        F.iterate(iters)
+        sol = F.solution()
+    for l in sorted({0, nb // 2, nb - 1}):
+        o = oracle.Oracle.from_instance(insts[l])
+        o.iterate(iters)
+        st_ = o.state()
+        errs = errors({key: sol[key][l] for key in KEYS}, st_)
+        assert max(errs.values()) <= 1e-9, (l, errs)
