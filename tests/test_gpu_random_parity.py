@@ -176,3 +176,30 @@ def test_random_families_match_oracle(data):
         st_ = o.state()
         errs = errors({key: sol[key][l] for key in KEYS}, st_)
         assert max(errs.values()) <= 1e-9, (l, errs)
+
+
+@settings(max_examples=100, deadline=None, derandomize=True,
+          suppress_health_check=[HealthCheck.too_slow, HealthCheck.data_too_large])
+@given(data=st.data())
+def test_random_literal_problems_match_oracle(data):
+    """Algorithm 1 as printed (y and gamma per nonzero) on drawn LPs, emptied
+    rows included, against the oracle, y and gamma compared too."""
+    from paper_2203_05027_amd.solver import Literal
+    m = data.draw(st.integers(1, 400), "m")
+    n = data.draw(st.integers(1, 2 * m + 20), "n")
+    k = data.draw(st.integers(1, min(5, m)), "k")
+    inst = I.lp_instance(m, n, k, seed=data.draw(st.integers(0, 10_000), "seed"))
+    if m > 2 and data.draw(st.booleans(), "holes"):
+        inst = empty_rows(inst, data.draw(st.lists(st.integers(0, m - 1), max_size=3), "rows"))
+    mu = data.draw(st.sampled_from([0.4, 1.0, 2.0]), "mu")
+    iters = data.draw(st.integers(1, 30), "iters")
+    orc = oracle.Oracle.from_instance(inst, mu=mu)
+    orc.iterate(iters)
+    o = orc.state()
+    with Literal.from_instance(inst, mu=mu) as L:
+        L.iterate(iters)
+        g = L.solution()
+    keys = ("x", "z", "delta", "lambda", "y", "gamma")
+    scale = max(max((float(np.abs(o[key]).max()) if o[key].size else 0.0) for key in keys), 1e-30)
+    errs = {key: (float(np.abs(g[key] - o[key]).max()) / scale if o[key].size else 0.0) for key in keys}
+    assert max(errs.values()) <= 1e-9, errs
