@@ -219,7 +219,10 @@ int solver_launch_shape(const uv_solver *s, int32_t *shape);
  * launch (replayed as a captured HIP graph) gives each workgroup one
  * instance at a time, longest first; x and u of the instance live in LDS,
  * so (m_i + n_i) * 4 bytes (UV_MIXED) or * 8 bytes (UV_FP64) must fit in
- * 159 KiB (a CU's 160 KiB less the kernel's own reduction slots).  The iteration, residuals and stopping rule are those of the
+ * 159 KiB (a CU's 160 KiB less the kernel's own reduction slots); when
+ * (m_i + 3 n_i) values fit for every instance, z and c are kept there too.
+ * Row and column numbers are held instance-local in 16 bits, which that
+ * bound always allows.  The iteration, residuals and stopping rule are those of the
  * single-problem solver; each instance keeps its own iteration count and
  * status, and an instance that has stopped is skipped by later launches.
  * ------------------------------------------------------------------------ */
