@@ -155,7 +155,7 @@ void uv_default_opts(uv_opts *o);
 
 /* Validates and copies the problem to the device, builds the column-major
  * copy of A and the diagonal factors F_U = (I + U U')^{-1} and
- * F_V = (I + V V')^{-1} (Algorithm 1, steps 1-3; U U' = diag of the squared
+ * F_V = (I + V V')^{-1} (the set-up of Algorithm 1; U U' = diag of the squared
  * row norms of A and V V' = diag of the column counts), and sets the zero
  * start.  b has m entries, c has n.  opts may be NULL (defaults).  On
  * success *out owns device memory until solver_destroy. */

@@ -31,8 +31,8 @@
  *   lambda <- lambda + mu (U y - b)                                   (dual update)
  *   gamma  <- gamma + mu (y - V'x)                                    (dual update)
  *   delta  <- delta + mu (z - x)                                      (dual update)
- * with F_U = (I + U U')^{-1}, F_V = (I + V V')^{-1}, both diagonal (Algorithm 1,
- * steps 2-3).
+ * with F_U = (I + U U')^{-1}, F_V = (I + V V')^{-1}, both diagonal (the set-up of
+ * Algorithm 1, eqs. UU and VV).
  *
  * Residuals (stopping test of Section V-B, SCS form) are evaluated at z and
  * lambda with fresh sparse products; two readings of the printed test are
@@ -187,7 +187,7 @@ orc_t *orc_create(int32_t m, int32_t n, int64_t nnz, const int64_t *row_ptr,
         off += soc_sizes[q];
     }
 
-    /* Algorithm 1, steps 2-3.  U U' is diagonal with entry i equal to the sum
+    /* The set-up of Algorithm 1 (eqs. UU, VV).  U U' is diagonal with entry i equal to the sum
      * of squares of row i's nonzeros (each column of U has a single nonzero
      * a_k in row i_k); V V' is diagonal with entry j equal to the number of
      * nonzeros in column j (each column of V is a single 1 in row j_k). */
@@ -315,7 +315,7 @@ void orc_resume(orc_t *h, const double *x, const double *z, const double *delta,
     y_step(h);
 }
 
-/* Step 6 (Block 2, y-step) at the current x, lambda, gamma:
+/* Block 2, y-step (matrix inversion lemma) at the current x, lambda, gamma:
  *   t = U'(b - lambda/mu) + V'x - gamma/mu,   t_k = a_k (b - lambda/mu)_{i_k} + x_{j_k} - gamma_k/mu
  *   y = (I - U' F_U U) t = t - U'(F_U (U t)). */
 static void y_step(orc_t *h)
@@ -345,7 +345,7 @@ static void iterate_once(orc_t *h)
     const int64_t o = h->o;
     const double mu = h->mu;
 
-    /* Step 5 (Block 1, eq. vvt): x = F_V (V(y + gamma/mu) + z + delta/mu - c/mu),
+    /* Block 1 (eq. vvt): x = F_V (V(y + gamma/mu) + z + delta/mu - c/mu),
      * (V w)_j = sum over the nonzeros k of column j of w_k. */
     #pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
     for (int32_t j = 0; j < n; ++j) {
@@ -359,22 +359,22 @@ static void iterate_once(orc_t *h)
 
     y_step(h);
 
-    /* Step 7 (Block 2, z-step): z = proj_K(x - delta/mu). */
+    /* Block 2, z-step (eq. proj): z = proj_K(x - delta/mu). */
     #pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
     for (int32_t j = 0; j < n; ++j) h->wrk_n[j] = h->x[j] - h->delta[j] / mu;
     proj_K(h->n_orth, h->n_soc, h->soc_size, h->soc_off, h->wrk_n, h->z);
 
-    /* Step 8: lambda = lambda + mu (U y - b). */
+    /* Multiplier update of the U-constraint: lambda = lambda + mu (U y - b). */
     #pragma omp parallel for schedule(static) if (m >= ORC_PAR_MIN)
     for (int32_t i = 0; i < m; ++i) {
         double uy = 0.0;
         for (int64_t k = h->row_ptr[i]; k < h->row_ptr[i + 1]; ++k) uy += h->ak[k] * h->y[k];
         h->lambda[i] += mu * (uy - h->b[i]);
     }
-    /* Step 9: gamma = gamma + mu (y - V'x). */
+    /* Multiplier update of the V-constraint: gamma = gamma + mu (y - V'x). */
     #pragma omp parallel for schedule(static) if (o >= ORC_PAR_MIN)
     for (int64_t k = 0; k < o; ++k) h->gamma[k] += mu * (h->y[k] - h->x[h->ck[k]]);
-    /* Step 10: delta = delta + mu (z - x). */
+    /* Multiplier update of z = x: delta = delta + mu (z - x). */
     #pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
     for (int32_t j = 0; j < n; ++j) h->delta[j] += mu * (h->z[j] - h->x[j]);
 

@@ -1,5 +1,5 @@
 // setup.hpp -- setup kernels shared by the single-problem and batched solvers
-// (Algorithm 1, steps 1-3: the UV decomposition is implicit in the CSR and
+// (the set-up of Algorithm 1: the UV decomposition is implicit in the CSR and
 // CSC copies of A; F_U and F_V are diagonal).
 #pragma once
 

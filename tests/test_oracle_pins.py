@@ -77,7 +77,7 @@ def test_example1_uv_matches_printed(oracle_mod):
 
 
 def test_example1_factors_from_printed_uv(oracle_mod):
-    """Algorithm 1 steps 2-3 on Example 1: F_U, F_V are the inverses of
+    """The set-up of Algorithm 1 on Example 1: F_U, F_V are the inverses of
     I + UU' and I + VV' formed from the printed U and V."""
     g = json.load(open(os.path.join(GOLDEN, "example1.json")))
     A, U_p, V_p = (np.array(g[k], float) for k in ("A", "U", "V"))
