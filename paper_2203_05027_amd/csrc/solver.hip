@@ -325,6 +325,64 @@ k_col_soc(const int *__restrict__ tcol, const int *__restrict__ tcone, const int
     }
 }
 
+// Column pass over second-order cones of at most 64 coordinates: a
+// wavefront per tile of whole cones (at most 64 columns, one lane per
+// column), with no LDS and no workgroup barrier.  Each lane forms x and
+// v = x - delta/mu for its column; a segmented scan over the lanes (cone by
+// cone, a fixed pattern) leaves each cone's tail sum of squares at its last
+// lane, and every lane takes its cone's case of eq. proj from the cone's
+// head value and tail norm.  info[j - off0] = (position of column j in its
+// cone) | (cone size << 16).
+template <typename T, int E, int S>
+__global__ void __launch_bounds__(kWG)
+k_col_soc_wave(int ntiles, const int *__restrict__ tcol, const int *__restrict__ info, int off0,
+               const int *__restrict__ cp, const int *__restrict__ ri, const T *__restrict__ vc,
+               const T *__restrict__ u, T *__restrict__ x, T *__restrict__ z, double *__restrict__ delta,
+               const T *__restrict__ c, double mu, double inv_mu, const T *__restrict__ P, int n, const DevStatus *st)
+{
+    if (st->done) return;
+    const int t = blockIdx.x * (kWG / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (t >= ntiles) return;  // the whole wavefront leaves
+    const int c0 = tcol[t], w = tcol[t + 1] - c0;
+    const int col = c0 + lane;
+    const bool act = lane < w;
+    T xn = 0, v = 0;
+    double d = 0.0;
+    int pos = 0, size = 1;
+    if (act) {
+        const T xo = x[col], zo = z[col], cj = c[col];
+        d = delta[col];
+        const int beg = cp[col], end = cp[col + 1];
+        const T atu = col_atu<1, E, S>(col, beg, end, 0, ri, vc, u, P, n);
+        const T dm = (T)(d * inv_mu);
+        xn = x_step<T>(end - beg, xo, zo, atu, dm, cj, inv_mu);
+        v = xn - dm;
+        const int in = info[col - off0];
+        pos = in & 0xffff;
+        size = in >> 16;
+    }
+    const int head = lane - pos, last = head + size - 1;
+    double sq = pos > 0 ? (double)v * (double)v : 0.0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {  // inclusive scan within each cone
+        const double o = __shfl_up(sq, off);
+        const int oh = __shfl_up(head, off);
+        if (lane >= off && oh == head) sq += o;
+    }
+    const double alpha = sqrt(__shfl(sq, last));
+    const double w1 = (double)__shfl(v, head);
+    double a1, beta;
+    if (alpha <= -w1) { a1 = 0.0; beta = 0.0; }
+    else if (alpha <= w1) { a1 = w1; beta = 1.0; }
+    else { a1 = 0.5 * (w1 + alpha); beta = 0.5 * (1.0 + w1 / alpha); }
+    if (act) {
+        const T zn = pos == 0 ? (T)a1 : (T)(beta * (double)v);
+        x[col] = xn;
+        z[col] = zn;
+        delta[col] = d + mu * ((double)zn - (double)xn);
+    }
+}
+
 // XCD-local slab passes.  The gathered vector (x in the row pass, u in the
 // column pass) is cut into S contiguous slabs and the matrix into the
 // matching slab-major copies; workgroup w works on slab w % S, so with the
@@ -554,6 +612,8 @@ struct uv_solver {
     int nblk_row = 0, nblk_rescol = 0;
     int *tcol = nullptr, *tcone = nullptr, *soc_off = nullptr;
     int ntiles = 0, tile_cap = kSocTile;
+    int *wtcol = nullptr, *winfo = nullptr;   // wavefront tiles (all cones <= 64)
+    int nwtiles = 0;
     DevStatus *st = nullptr;
     DevStatus *st_host = nullptr;             // pinned
     int L_row = 8, L_col = 4;   // lanes per row / column
@@ -678,7 +738,11 @@ void col_update_launch(uv_solver *s, hipStream_t st)
                                                     (T *)s->x, (T *)s->z, s->delta, (const T *)s->c, mu, im,
                                                     (const T *)s->P_col, s->n, s->st);
     }
-    if (s->ntiles > 0) {
+    if (s->nwtiles > 0) {
+        k_col_soc_wave<T, EE, S><<<blocks_for(s->nwtiles, kWG / 64), kWG, 0, st>>>(
+            s->nwtiles, s->wtcol, s->winfo, s->n_orth, s->cp, s->ri, (const T *)s->vc, (const T *)s->u, (T *)s->x,
+            (T *)s->z, s->delta, (const T *)s->c, mu, im, (const T *)s->P_col, s->n, s->st);
+    } else if (s->ntiles > 0) {
 #define UV_SOC_ARGS                                                                                        \
     s->tcol, s->tcone, s->soc_off, s->cp, s->ri, (const T *)s->vc, (const T *)s->u, (T *)s->x, (T *)s->z, \
         s->delta, (const T *)s->c, mu, im, (const T *)s->P_col, s->n, s->st
@@ -974,6 +1038,20 @@ int setup(uv_solver *s, const uv_csr *A, const double *b, const double *c, const
         UV_TRY(hipMemcpy(s->tcol, tcol.data(), tcol.size() * 4, hipMemcpyHostToDevice));
         UV_TRY(hipMemcpy(s->tcone, tcone.data(), tcone.size() * 4, hipMemcpyHostToDevice));
         UV_TRY(hipMemcpy(s->soc_off, off.data(), off.size() * 4, hipMemcpyHostToDevice));
+        if (maxc <= 64) {  // wavefront tiles of whole cones, at most 64 columns each
+            std::vector<int> wt(1, off[0]), info((size_t)(off[K->n_soc] - off[0]));
+            for (int q = 0; q < K->n_soc; ++q) {
+                if (off[q + 1] - wt.back() > 64) wt.push_back(off[q]);
+                for (int j = off[q]; j < off[q + 1]; ++j) info[j - off[0]] = (j - off[q]) | (K->soc_sizes[q] << 16);
+            }
+            wt.push_back(off[K->n_soc]);
+            s->nwtiles = (int)wt.size() - 1;
+            s->wtcol = dalloc<int>(s, wt.size());
+            s->winfo = dalloc<int>(s, info.size());
+            if (!s->wtcol || !s->winfo) return UV_ENOMEM;
+            UV_TRY(hipMemcpy(s->wtcol, wt.data(), wt.size() * 4, hipMemcpyHostToDevice));
+            UV_TRY(hipMemcpy(s->winfo, info.data(), info.size() * 4, hipMemcpyHostToDevice));
+        }
     }
 
     // Upload (row_ptr narrowed to 32-bit; nnz < 2^31 was checked).
