@@ -49,7 +49,9 @@ extern "C" {
                            second-order cone larger than UV_MAX_CONE */
 #define UV_ENOMEM   -4  /* device or pinned-host allocation failed */
 #define UV_EHIP     -5  /* a HIP runtime call failed */
-#define UV_ENUMERIC -6  /* NaN or Inf met in a residual check */
+#define UV_ENUMERIC -6  /* NaN or Inf met in a residual check (non-finite
+                           b or c are accepted at create and end the run
+                           at its first check with this code) */
 #define UV_ETOOBIG  -7  /* nnz >= 2^31 (device indices are 32-bit) */
 
 /* Largest second-order cone handled (one workgroup projects a cone). */
@@ -149,6 +151,14 @@ typedef struct {
 
 typedef struct uv_solver uv_solver;
 
+/* Test hook for the out-of-memory paths: after `after` more successful
+ * device or pinned-host allocations made by the library, the next one fails
+ * as if memory were exhausted (the entry point then returns UV_ENOMEM and
+ * frees what it had taken); the hook then disarms itself.  A negative value
+ * disarms it.  Process-wide; not for use while other threads call the
+ * library. */
+void uv_test_fail_alloc(int64_t after);
+
 /* Fills *o with the defaults: mu = 1, UV_FP64, check_every = 10,
  * eps_kkt = 1e-4, max_iter = 0, NULL stream, automatic lanes, graphs on. */
 void uv_default_opts(uv_opts *o);
@@ -186,7 +196,9 @@ int solver_resume(uv_solver *s, const double *x, const double *z,
 int solver_iterate(uv_solver *s, int64_t k, int32_t *done);
 
 /* Residuals of the current iterate (evaluated now if the state changed
- * since the last check). */
+ * since the last check).  An evaluation made here, between checks, only
+ * reports: the status and the stopping decision change at the iteration's
+ * own checks alone, so polling does not change the trajectory. */
 int solver_residuals(uv_solver *s, uv_residuals *r);
 
 /* Copies the current iterate to caller-owned host buffers: x, z, delta
@@ -241,7 +253,8 @@ int batch_iterate(uv_batch *h, int64_t k, int32_t *n_active);
 
 /* Residuals / status of instance i at its last check (see uv_residuals;
  * the infinity-norm fields are not evaluated by the batched solver and read
- * 0). */
+ * 0).  Returns UV_ENUMERIC (with *r filled) when that instance stopped on a
+ * NaN or Inf. */
 int batch_residuals(uv_batch *h, int32_t i, uv_residuals *r);
 
 /* Iterate of instance i into caller-owned host buffers (any may be NULL):
@@ -315,7 +328,8 @@ int family_set_start_predicted(uv_family *h, const float *xl_dev, int64_t ld,
 int family_iterate(uv_family *h, int64_t k, int32_t *n_active);
 
 /* Residuals of the nb current instances into r[0..nb-1] (infinity-norm
- * fields not evaluated: 0). */
+ * fields not evaluated: 0).  Returns UV_ENUMERIC (with r filled) when any of
+ * them stopped on a NaN or Inf. */
 int family_residuals(uv_family *h, uv_residuals *r);
 
 /* Iterates of the nb instances into host buffers (instance-major; any may

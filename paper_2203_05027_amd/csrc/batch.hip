@@ -465,7 +465,7 @@ template <typename T>
 T *balloc(uv_batch *h, size_t count)
 {
     void *p = nullptr;
-    if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return nullptr;
+    if (uv::dev_malloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return nullptr;
     h->allocs.push_back(p);
     return (T *)p;
 }
@@ -711,11 +711,11 @@ int batch_create(int32_t count, const uv_csr *A, const double *const *b, const d
                     h->z, h->u, h->fu, h->va, h->vc, h->b, h->c, (void *)h->inst, (void *)h->order,
                     (void *)h->queue, (void *)h->budget, (void *)cnt, (void *)bsum})
         if (!p) return fail(UV_ENOMEM);
-    if (hipHostMalloc((void **)&h->inst_host, sizeof(BInst) * count, hipHostMallocDefault) != hipSuccess) {
+    if (uv::host_malloc(&h->inst_host, sizeof(BInst) * count, hipHostMallocDefault) != hipSuccess) {
         h->inst_host = nullptr;
         return fail(UV_ENOMEM);
     }
-    if (hipHostMalloc((void **)&h->budget_host, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    if (uv::host_malloc(&h->budget_host, sizeof(int), hipHostMallocDefault) != hipSuccess) {
         h->budget_host = nullptr;
         return fail(UV_ENOMEM);
     }
@@ -747,13 +747,13 @@ int batch_create(int32_t count, const uv_csr *A, const double *const *b, const d
             ko += a.nnz;
         }
         rp32[M] = (int)NNZ;
-        UV_BTRY(hipMemcpy(h->rp, rp32.data(), sizeof(int) * (M + 1), hipMemcpyHostToDevice));
+        if (hipMemcpy(h->rp, rp32.data(), sizeof(int) * (M + 1), hipMemcpyHostToDevice) != hipSuccess) return fail(UV_EHIP);
         if (NNZ > 0) {
-            UV_BTRY(hipMemcpy(h->ci, ci32.data(), sizeof(int) * NNZ, hipMemcpyHostToDevice));
-            UV_BTRY(hipMemcpy(h->va64, va.data(), sizeof(double) * NNZ, hipMemcpyHostToDevice));
+            if (hipMemcpy(h->ci, ci32.data(), sizeof(int) * NNZ, hipMemcpyHostToDevice) != hipSuccess) return fail(UV_EHIP);
+            if (hipMemcpy(h->va64, va.data(), sizeof(double) * NNZ, hipMemcpyHostToDevice) != hipSuccess) return fail(UV_EHIP);
         }
-        UV_BTRY(hipMemcpy(h->b64, bb.data(), sizeof(double) * M, hipMemcpyHostToDevice));
-        UV_BTRY(hipMemcpy(h->c64, cc.data(), sizeof(double) * N, hipMemcpyHostToDevice));
+        if (hipMemcpy(h->b64, bb.data(), sizeof(double) * M, hipMemcpyHostToDevice) != hipSuccess) return fail(UV_EHIP);
+        if (hipMemcpy(h->c64, cc.data(), sizeof(double) * N, hipMemcpyHostToDevice) != hipSuccess) return fail(UV_EHIP);
     }
     // Longest instances first.
     h->order_host.resize(count);
@@ -761,7 +761,7 @@ int batch_create(int32_t count, const uv_csr *A, const double *const *b, const d
     std::stable_sort(h->order_host.begin(), h->order_host.end(), [&](int p, int q) {
         return A[p].nnz + A[p].m + A[p].n > A[q].nnz + A[q].m + A[q].n;
     });
-    UV_BTRY(hipMemcpy(h->order, h->order_host.data(), sizeof(int) * count, hipMemcpyHostToDevice));
+    if (hipMemcpy(h->order, h->order_host.data(), sizeof(int) * count, hipMemcpyHostToDevice) != hipSuccess) return fail(UV_EHIP);
 
     if (!build_csc((int)M, (int)N, (int)NNZ, h->rp, h->ci, h->va64, h->cp, h->ri, h->vc64, cnt, bsum, st))
         return fail(UV_EHIP);
@@ -862,7 +862,7 @@ int batch_residuals(uv_batch *h, int32_t i, uv_residuals *r)
     r->prim_inf = r->dual_inf = r->scale_p = r->scale_d = 0.0;
     r->iter = I.iter;
     r->status = I.status;
-    return UV_OK;
+    return I.status == UV_STATUS_NUMERIC ? UV_ENUMERIC : UV_OK;
 }
 
 int batch_solution(uv_batch *h, int32_t i, double *x, double *z, double *lambda, double *delta)
@@ -951,7 +951,7 @@ int batch_time(uv_batch *h, int32_t bucket, int32_t iters, double *ms)
     char *save = nullptr;
     const size_t bytes_xz = ts * h->N, bytes_u = ts * h->M;
     const size_t total = 2 * bytes_xz + bytes_u + 8 * (size_t)h->M + 8 * (size_t)h->N;
-    if (hipMalloc(&save, total) != hipSuccess) return UV_ENOMEM;
+    if (uv::dev_malloc(&save, total) != hipSuccess) return UV_ENOMEM;
     char *p = save;
     int rc = UV_OK;
     auto cp_ = [&](void *dst, const void *src, size_t n) {
@@ -964,7 +964,7 @@ int batch_time(uv_batch *h, int32_t bucket, int32_t iters, double *ms)
     cp_(p + 2 * bytes_xz + bytes_u + 8 * (size_t)h->M, h->delta, 8 * (size_t)h->N);
     const bool saved = rc == UV_OK;  // restore below only from a complete copy
     int *dsel = nullptr;
-    if (rc == UV_OK && hipMalloc(&dsel, sizeof(int) * sel.size()) != hipSuccess) rc = UV_ENOMEM;
+    if (rc == UV_OK && uv::dev_malloc(&dsel, sizeof(int) * sel.size()) != hipSuccess) rc = UV_ENOMEM;
     if (rc == UV_OK && hipMemcpyAsync(dsel, sel.data(), sizeof(int) * sel.size(), hipMemcpyHostToDevice, st) != hipSuccess)
         rc = UV_EHIP;
     // run the timed launch with every selected instance marked running

@@ -4,7 +4,44 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 namespace uv {
+
+// Allocation-failure test hook (uv_test_fail_alloc): while armed (>= 0) it
+// counts down on every device or pinned-host allocation made through the two
+// helpers below, and the allocation that finds it at zero fails as if the
+// memory were exhausted; the hook then disarms itself.
+inline std::atomic<long long> g_alloc_fail_after{-1};
+
+inline bool alloc_hook_fires()
+{
+    long long k = g_alloc_fail_after.load();
+    while (k >= 0) {
+        if (g_alloc_fail_after.compare_exchange_weak(k, k - 1)) return k == 0;
+    }
+    return false;
+}
+
+template <typename T>
+inline hipError_t dev_malloc(T **p, size_t bytes)
+{
+    if (alloc_hook_fires()) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc((void **)p, bytes);
+}
+
+template <typename T>
+inline hipError_t host_malloc(T **p, size_t bytes, unsigned flags)
+{
+    if (alloc_hook_fires()) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipHostMalloc((void **)p, bytes, flags);
+}
 
 constexpr int kWG = 256;      // threads per workgroup for every sweep kernel
 constexpr int kWave = 64;     // CDNA wavefront width

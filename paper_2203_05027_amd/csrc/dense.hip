@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/uvadmm.h"
+#include "common.hpp"
 
 namespace {
 
@@ -275,10 +276,10 @@ int pca_fit(float *Y, int64_t N, int64_t D, int64_t ld, int32_t k, int32_t overs
         for (float *p : {Om, Z, W, G, R, Bm, Tm})
             if (p) (void)hipFree(p);
     };
-    if (hipMalloc(&Om, sizeof(float) * D * l) != hipSuccess || hipMalloc(&Z, sizeof(float) * N * l) != hipSuccess ||
-        hipMalloc(&W, sizeof(float) * D * l) != hipSuccess || hipMalloc(&G, sizeof(float) * l * l) != hipSuccess ||
-        hipMalloc(&R, sizeof(float) * l * l) != hipSuccess || hipMalloc(&Bm, sizeof(float) * l * D) != hipSuccess ||
-        hipMalloc(&Tm, sizeof(float) * std::max(N, D) * l) != hipSuccess) {
+    if (uv::dev_malloc(&Om, sizeof(float) * D * l) != hipSuccess || uv::dev_malloc(&Z, sizeof(float) * N * l) != hipSuccess ||
+        uv::dev_malloc(&W, sizeof(float) * D * l) != hipSuccess || uv::dev_malloc(&G, sizeof(float) * l * l) != hipSuccess ||
+        uv::dev_malloc(&R, sizeof(float) * l * l) != hipSuccess || uv::dev_malloc(&Bm, sizeof(float) * l * D) != hipSuccess ||
+        uv::dev_malloc(&Tm, sizeof(float) * std::max(N, D) * l) != hipSuccess) {
         cleanup();
         return UV_ENOMEM;
     }

@@ -421,7 +421,7 @@ template <typename T>
 T *falloc(uv_family *h, size_t count)
 {
     void *p = nullptr;
-    if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return nullptr;
+    if (uv::dev_malloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return nullptr;
     h->allocs.push_back(p);
     return (T *)p;
 }
@@ -603,11 +603,11 @@ int family_create(const uv_csr *A, const double *c, int32_t B, const uv_opts *op
                     (void *)h->D, (void *)h->BV64, (void *)h->prow, (void *)h->pcol, (void *)h->pred, (void *)h->stage,
                     (void *)h->inst, (void *)h->sh, (void *)cnt, (void *)bsum})
         if (!p) return fail(UV_ENOMEM);
-    if (hipHostMalloc((void **)&h->inst_host, sizeof(FInst) * B, hipHostMallocDefault) != hipSuccess) {
+    if (uv::host_malloc(&h->inst_host, sizeof(FInst) * B, hipHostMallocDefault) != hipSuccess) {
         h->inst_host = nullptr;
         return fail(UV_ENOMEM);
     }
-    if (hipHostMalloc((void **)&h->sh_host, sizeof(FShared), hipHostMallocDefault) != hipSuccess) {
+    if (uv::host_malloc(&h->sh_host, sizeof(FShared), hipHostMallocDefault) != hipSuccess) {
         h->sh_host = nullptr;
         return fail(UV_ENOMEM);
     }
@@ -775,6 +775,7 @@ int family_iterate(uv_family *h, int64_t k, int32_t *n_active)
 int family_residuals(uv_family *h, uv_residuals *r)
 {
     if (!h || !r) return UV_EINVAL;
+    int rc = UV_OK;
     for (int l = 0; l < h->nb; ++l) {
         const FInst &I = h->inst_host[l];
         r[l].r_prim = I.r_prim;
@@ -787,8 +788,9 @@ int family_residuals(uv_family *h, uv_residuals *r)
         r[l].prim_inf = r[l].dual_inf = r[l].scale_p = r[l].scale_d = 0.0;
         r[l].iter = I.status == UV_STATUS_RUNNING ? h->host_iter : I.iter;
         r[l].status = I.status;
+        if (I.status == UV_STATUS_NUMERIC) rc = UV_ENUMERIC;
     }
-    return UV_OK;
+    return rc;
 }
 
 int family_solution(uv_family *h, double *x, double *z, double *lambda, double *delta)

@@ -127,7 +127,7 @@ template <typename T>
 T *lalloc(uv_literal *h, size_t count)
 {
     void *p = nullptr;
-    if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return nullptr;
+    if (uv::dev_malloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return nullptr;
     h->allocs.push_back(p);
     return (T *)p;
 }

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/uvadmm.h"
+#include "common.hpp"
 
 namespace {
 
@@ -194,7 +195,7 @@ template <typename T>
 T *malloc_d(uv_mlp *h, size_t count)
 {
     void *p = nullptr;
-    if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return nullptr;
+    if (uv::dev_malloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return nullptr;
     h->allocs.push_back(p);
     return (T *)p;
 }

@@ -80,9 +80,9 @@ int run(int64_t nnz, int64_t table_len, int slabs, int reps, uint64_t seed, doub
     hipStream_t st = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = UV_OK;
-    if (hipMalloc(&idx, 4 * nnz) != hipSuccess || hipMalloc(&val, sizeof(T) * nnz) != hipSuccess ||
-        hipMalloc(&tab, sizeof(T) * table_len) != hipSuccess ||
-        hipMalloc(&out, sizeof(T) * nblk * kWG) != hipSuccess)
+    if (uv::dev_malloc(&idx, 4 * nnz) != hipSuccess || uv::dev_malloc(&val, sizeof(T) * nnz) != hipSuccess ||
+        uv::dev_malloc(&tab, sizeof(T) * table_len) != hipSuccess ||
+        uv::dev_malloc(&out, sizeof(T) * nblk * kWG) != hipSuccess)
         rc = UV_ENOMEM;
     if (rc == UV_OK && (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
                         hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))

@@ -517,9 +517,11 @@ k_res_col_slab(int n, const double *__restrict__ P, const double *__restrict__ c
 // crit 0: relative KKT (SCS form) <= eps; crit 1: infinity-norm test
 // ||Az-b|| <= eps_abs + eps max(||Az||, ||b||) and
 // ||A'lambda+c-delta|| <= eps_abs + eps max(||A'lambda||, ||c||).
+// decide 0 only records the values (a residual query between checks): the
+// status and the stop flag change at the checks of the iteration alone.
 __global__ void __launch_bounds__(kWG)
 k_finalize(int nrow, const double *__restrict__ prow, int ncol, const double *__restrict__ pcol,
-           double eps, double eps_abs, int crit, DevStatus *st)
+           double eps, double eps_abs, int crit, int decide, DevStatus *st)
 {
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, w[4] = {0.0, 0.0, 0.0, 0.0};
     for (int base = threadIdx.x; base < nrow; base += 8 * kWG) {
@@ -575,6 +577,7 @@ k_finalize(int nrow, const double *__restrict__ prow, int ncol, const double *__
     st->scale_p = fmax(s[6], st->binf);
     st->scale_d = fmax(s[8], st->cinf);
     st->check_iter = st->iter;
+    if (!decide) return;
     const bool conv = crit == 1 ? (s[5] <= eps_abs + eps * st->scale_p && s[7] <= eps_abs + eps * st->scale_d)
                                 : kkt <= eps;
     if (!isfinite(kkt)) {
@@ -638,7 +641,7 @@ template <typename T>
 T *dalloc(uv_solver *s, size_t count)
 {
     void *p = nullptr;
-    if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return nullptr;
+    if (uv::dev_malloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return nullptr;
     s->allocs.push_back(p);
     return (T *)p;
 }
@@ -871,7 +874,7 @@ void res_col_slab_launch(uv_solver *s, hipStream_t st)
                                                  (const double *)s->z, s->part_col, (int)g);
 }
 
-void launch_residuals(uv_solver *s, hipStream_t st, bool row_done)
+void launch_residuals(uv_solver *s, hipStream_t st, bool row_done, bool decide)
 {
     if (!row_done) dispatch_le_res<ResRowLaunch>(s, st, s->L_row);
     // FP64 with column slabs and chunked passes: A'lambda through the slab copy
@@ -887,7 +890,7 @@ void launch_residuals(uv_solver *s, hipStream_t st, bool row_done)
     const int nrow = row_done ? s->nblk_row_fused : s->nblk_row;
     const int ncol = slab ? (int)blocks_for(s->n, kWG) : s->nblk_rescol;
     k_finalize<<<1, kWG, 0, st>>>(nrow, s->part_row, ncol, s->part_col, s->o.eps_kkt, s->o.eps_abs,
-                                  s->o.criterion, s->st);
+                                  s->o.criterion, decide ? 1 : 0, s->st);
 }
 
 // One iteration; with check, the residuals of the new iterate follow it.
@@ -896,7 +899,7 @@ void launch_iteration(uv_solver *s, hipStream_t st, bool check)
     launch_col(s, st);
     const bool fused = check && s->o.precision == UV_FP64;
     launch_row(s, st, fused ? 1 : 0);
-    if (check) launch_residuals(s, st, fused);
+    if (check) launch_residuals(s, st, fused, true);
 }
 
 int build_graph(uv_solver *s)
@@ -1007,7 +1010,7 @@ int setup(uv_solver *s, const uv_csr *A, const double *b, const double *c, const
                     (void *)s->scratch, s->x, s->z, s->u, s->fu, s->va, s->vc, s->b, s->c,
                     (void *)s->part_row, (void *)s->part_col, (void *)s->st, (void *)cnt, (void *)bsum})
         if (!p) return UV_ENOMEM;
-    if (hipHostMalloc((void **)&s->st_host, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess) {
+    if (uv::host_malloc(&s->st_host, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess) {
         s->st_host = nullptr;
         return UV_ENOMEM;
     }
@@ -1119,6 +1122,11 @@ int setup(uv_solver *s, const uv_csr *A, const double *b, const double *c, const
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" {
+
+void uv_test_fail_alloc(int64_t after)
+{
+    uv::g_alloc_fail_after.store(after < 0 ? -1 : (long long)after);
+}
 
 void uv_default_opts(uv_opts *o)
 {
@@ -1322,7 +1330,7 @@ int solver_residuals(uv_solver *s, uv_residuals *r)
 {
     if (!s || !r) return UV_EINVAL;
     if (s->st_host->check_iter != s->st_host->iter) {
-        launch_residuals(s, s->stream, false);
+        launch_residuals(s, s->stream, false, false);
         UV_TRY(hipGetLastError());
         int rc = sync_status(s);
         if (rc != UV_OK) return rc;

@@ -377,7 +377,7 @@ template <typename T>
 T *salloc(uv_standard *h, size_t count)
 {
     void *p = nullptr;
-    if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return nullptr;
+    if (uv::dev_malloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return nullptr;
     h->allocs.push_back(p);
     return (T *)p;
 }
@@ -587,7 +587,7 @@ int standard_create(const uv_csr *A, const double *b, const double *c, const uv_
                     (void *)h->p, (void *)h->q, (void *)h->P_row, (void *)h->P_col, (void *)h->part,
                     (void *)h->part_row, (void *)h->part_col, (void *)h->st, (void *)cnt, (void *)bsum})
         if (!p) return fail(UV_ENOMEM);
-    if (hipHostMalloc((void **)&h->st_host, sizeof(StdStatus), hipHostMallocDefault) != hipSuccess)
+    if (uv::host_malloc(&h->st_host, sizeof(StdStatus), hipHostMallocDefault) != hipSuccess)
         return fail(UV_ENOMEM);
     std::vector<int> rp32(m + 1);
     for (int i = 0; i <= m; ++i) rp32[i] = (int)A->row_ptr[i];

@@ -346,7 +346,9 @@ class Batch:
 
     def residuals(self, i: int) -> dict:
         r = UvResiduals()
-        _check(lib().batch_residuals(self._h, int(i), ctypes.byref(r)), "batch_residuals")
+        rc = lib().batch_residuals(self._h, int(i), ctypes.byref(r))
+        if rc != UV_ENUMERIC:  # a numeric failure is reported in the status
+            _check(rc, "batch_residuals")
         d = {k: getattr(r, k) for k, _ in UvResiduals._fields_}
         d["status"] = STATUS.get(d["status"], d["status"])
         return d
@@ -492,7 +494,9 @@ class Family:
 
     def residuals(self):
         arr = (UvResiduals * max(self.nb, 1))()
-        _check(lib().family_residuals(self._h, arr), "family_residuals")
+        rc = lib().family_residuals(self._h, arr)
+        if rc != UV_ENUMERIC:  # a numeric failure is reported in the statuses
+            _check(rc, "family_residuals")
         out = []
         for r in arr[: self.nb]:
             d = {k: getattr(r, k) for k, _ in UvResiduals._fields_}

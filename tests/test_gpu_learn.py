@@ -88,11 +88,17 @@ def test_mlp_forward_and_gradients(torch_cuda):
         e_bf = np.linalg.norm(gwl[l] - gws[l]) / np.linalg.norm(gws[l])
         e_64 = np.linalg.norm(gwl[l] - gws64[l]) / np.linalg.norm(gws64[l])
         say(f"layer {l}: dW rel err vs bf16 oracle {e_bf:.2e}, vs fp64 oracle {e_64:.2e}")
-        # sharp: same BF16 rounding points, only the FP32 summation order differs
+        # Against the oracle that rounds to BF16 at the same points: where both
+        # sides round the same value the difference is the FP32 summation order
+        # (about K * 2^-24, K <= 128 here, so below 1e-5).  A value that lands
+        # within that distance of a BF16 rounding boundary (or a pre-activation
+        # within it of zero, a ReLU mask) can round the other way on one side,
+        # a change of one BF16 spacing (2^-7 relative) in that one element;
+        # 2e-3 in norm leaves room for such flips in a few percent of the
+        # gradient's weight, far above what is seen (~1e-7).  The error against
+        # the unrounded FP64 gradient measures BF16 itself, not the kernels, and
+        # is reported only.
         assert e_bf <= 2e-3, (l, e_bf)
-        # loose: the effect of BF16 operands (2^-9 relative per element, through
-        # three layers of products) on the exact FP64 gradient
-        assert e_64 <= 1e-1, (l, e_64)
         np.testing.assert_allclose(gbl[l], gbs[l], rtol=2e-3, atol=2e-3 * np.abs(gbs[l]).max())
 
 
@@ -112,6 +118,21 @@ def test_mlp_adam_step_and_training(torch_cuda):
     w1, b1 = net.params()
     pw, _, _ = M.adam_step(w0.astype(np.float64), gw.astype(np.float64), 0, 0, 1, lr=1e-2)
     np.testing.assert_allclose(w1, pw, rtol=1e-5, atol=1e-6)
+    # steps 2..8: the moments accumulate across steps; each step's gradient
+    # is the kernels' own at the current weights, fed to the oracle's Adam
+    m_w, v_w = (1 - 0.9) * gw.astype(np.float64), (1 - 0.999) * gw.astype(np.float64) ** 2
+    m_b, v_b = (1 - 0.9) * gb.astype(np.float64), (1 - 0.999) * gb.astype(np.float64) ** 2
+    pw, pb = w1.astype(np.float64), net.params()[1].astype(np.float64)
+    for step in range(2, 9):
+        gw, gb, _ = net.gradients(xd, td)
+        net.train_step(xd, td, lr=1e-2)
+        pw, m_w, v_w = M.adam_step(pw, gw.astype(np.float64), m_w, v_w, step, lr=1e-2)
+        pb, m_b, v_b = M.adam_step(pb, gb.astype(np.float64), m_b, v_b, step, lr=1e-2)
+        w_gpu, b_gpu = net.params()
+        # FP32 state on the GPU: a step moves a weight by at most lr (1e-2)
+        np.testing.assert_allclose(w_gpu, pw, rtol=1e-5, atol=1e-6 * step)
+        np.testing.assert_allclose(b_gpu, pb, rtol=1e-5, atol=1e-6 * step)
+        pw, pb = w_gpu.astype(np.float64), b_gpu.astype(np.float64)
     losses = [net.train_step(xd, td, lr=3e-3) for _ in range(400)]
     say(f"training loss {losses[0]:.4f} -> {losses[-1]:.5f}")
     assert losses[-1] < 0.05 * losses[0]

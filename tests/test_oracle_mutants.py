@@ -27,7 +27,21 @@ MUTANTS = {
     "delta update sign": ("h->delta[j] += mu * (h->z[j] - h->x[j]);", "h->delta[j] += mu * (h->x[j] - h->z[j]);"),
     "dual residual drops delta": ("double r = atl + h->c[j] - h->delta[j];", "double r = atl + h->c[j];"),
     "U transposed in y-step sum": ("ut += h->ak[k] * h->t[k];", "ut += h->t[k];"),
+    # the stopping test of Section V-B
+    "r_prim normalised by ||b||": ("out[0] = sqrt(rp2) / (1.0 + sqrt(bb));", "out[0] = sqrt(rp2) / sqrt(bb);"),
+    "r_prim drops the sqrt": ("out[0] = sqrt(rp2) / (1.0 + sqrt(bb));", "out[0] = rp2 / (1.0 + sqrt(bb));"),
+    "r_dual normalised by 1+||c||^2": ("out[1] = sqrt(rd2) / (1.0 + sqrt(cc));", "out[1] = sqrt(rd2) / (1.0 + cc);"),
+    "gap denominator of the sum": ("out[2] = fabs(cz + bl) / (1.0 + fabs(cz) + fabs(bl));",
+                                   "out[2] = fabs(cz + bl) / (1.0 + fabs(cz + bl));"),
+    "gap sign of b'lambda": ("out[2] = fabs(cz + bl) / (1.0 + fabs(cz) + fabs(bl));",
+                             "out[2] = fabs(cz - bl) / (1.0 + fabs(cz) + fabs(bl));"),
+    "kkt ignores the gap": ("out[3] = fmax(out[0], fmax(out[1], out[2]));", "out[3] = fmax(out[0], out[1]);"),
+    "dual residual sign of A'lambda": ("double r = atl + h->c[j] - h->delta[j];",
+                                       "double r = -atl + h->c[j] - h->delta[j];"),
+    "printed residual at z": ("ax += h->ak[k] * h->x[h->ck[k]];", "ax += h->ak[k] * h->z[h->ck[k]];"),
+    "dual objective sign": ("out[5] = -bl;", "out[5] = bl;"),
 }
+PIN_FILES = [os.path.join(ROOT, "tests", f) for f in ("test_oracle_pins.py", "test_oracle_residual_pins.py")]
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
@@ -40,8 +54,7 @@ def test_pins_catch_mutant(name, tmp_path):
     src.write_text(text.replace(old, new))
     lib = oracle.build(src=str(src), out=str(tmp_path / "libmutant.so"))
     env = dict(os.environ, UVADMM_ORACLE_LIB=lib, OMP_NUM_THREADS="2")
-    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *PIN_FILES],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"pins did not catch: {name}\n{r.stdout[-2000:]}"
 
