@@ -391,7 +391,7 @@ k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__
                     const double rdu = sqrt(a[3]) / (1.0 + sqrt(I->cnorm2));
                     const double cz = a[4], bl = a[1];
                     const double rg = fabs(cz + bl) / (1.0 + fabs(cz) + fabs(bl));
-                    const double kkt = fmax(rpr, fmax(rdu, rg));
+                    const double kkt = uv::kkt_of(rpr, rdu, rg);
                     I->r_prim = rpr;
                     I->r_dual = rdu;
                     I->r_gap = rg;

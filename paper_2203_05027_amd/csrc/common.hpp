@@ -43,6 +43,15 @@ inline hipError_t host_malloc(T **p, size_t bytes, unsigned flags)
     return hipHostMalloc((void **)p, bytes, flags);
 }
 
+// Relative KKT residual: the largest of the three relative residuals, and
+// NaN when any of them is NaN (fmax alone would drop a NaN operand and hide
+// a numeric failure behind the other two).
+__device__ __forceinline__ double kkt_of(double rp, double rd, double rg)
+{
+    const double k = fmax(rp, fmax(rd, rg));
+    return (isnan(rp) || isnan(rd) || isnan(rg)) ? __builtin_nan("") : k;
+}
+
 constexpr int kWG = 256;      // threads per workgroup for every sweep kernel
 constexpr int kWave = 64;     // CDNA wavefront width
 

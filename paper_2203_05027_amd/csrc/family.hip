@@ -259,7 +259,7 @@ k_fam_finalize(int B, int nblk, const double *__restrict__ red, double eps, long
             const double rdu = sqrt(a[3]) / (1.0 + sqrt(sh->cnorm2));
             const double cz = a[4], bl = a[1];
             const double rg = fabs(cz + bl) / (1.0 + fabs(cz) + fabs(bl));
-            const double kkt = fmax(rpr, fmax(rdu, rg));
+            const double kkt = uv::kkt_of(rpr, rdu, rg);
             I.r_prim = rpr;
             I.r_dual = rdu;
             I.r_gap = rg;

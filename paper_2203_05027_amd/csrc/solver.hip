@@ -184,10 +184,30 @@ k_res_row(int m, const int *__restrict__ rp, const int *__restrict__ ci, const d
         const double bi = b[row], li = lam[row];
         const int beg = rp[row], end = rp[row + 1];
         double qx = 0.0, qz = 0.0;
-        for (int k = beg + lane; k < end; k += L) {
-            const int j = ci[k];
-            qx += va[k] * (double)x[j];
-            qz += va[k] * (double)z[j];
+        constexpr int E = 4;  // entries per lane with their gathers in flight
+        for (int base = beg + lane; base < end; base += L * E) {
+            int j[E];
+            double v[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int k = base + e * L;
+                const int kk = k < end ? k : end - 1;
+                j[e] = ci[kk];
+                v[e] = va[kk];
+            }
+            T gx[E], gz[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                gx[e] = x[j[e]];
+                gz[e] = z[j[e]];
+            }
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                if (base + e * L < end) {
+                    qx += v[e] * (double)gx[e];
+                    qz += v[e] * (double)gz[e];
+                }
+            }
         }
         qx = uv::group_sum<L>(qx);
         qz = uv::group_sum<L>(qz);
@@ -212,17 +232,28 @@ __device__ __forceinline__ T x_step(int cnt, T xo, T zo, T atu, T dm, T cj, doub
 }
 
 // A'u for column col: the L-lane segment product over the column (S == 1)
-// or the sum of the S slab partials P[s * n + col] in slab order (S > 1).
+// or the tree sum of the S slab partials P[s * n + col] (S > 1).
 template <int L, int E, int S, typename T>
 __device__ __forceinline__ T col_atu(int col, int beg, int end, int lane, const int *__restrict__ ri,
                                      const T *__restrict__ vc, const T *__restrict__ u, const T *__restrict__ P,
                                      int n)
 {
     if (S == 1) return seg_dot<L, E>(beg, end, lane, ri, vc, u);
-    T a = 0;
-#pragma unroll
-    for (int s = 0; s < S; ++s) a += P[(size_t)s * n + col];
-    return a;
+    return slab_tree_sum<S>(P, n, col);
+}
+
+// x-step, projection onto the orthant and delta update of one column.
+template <typename T>
+__device__ __forceinline__ void orth_step(int col, int cnt, T xo, T zo, T cj, double d, T atu, T *__restrict__ x,
+                                          T *__restrict__ z, double *__restrict__ delta, double mu, double inv_mu)
+{
+    const T dm = (T)(d * inv_mu);
+    const T xn = x_step<T>(cnt, xo, zo, atu, dm, cj, inv_mu);
+    const T v = xn - dm;
+    const T zn = v > (T)0 ? v : (T)0;
+    x[col] = xn;
+    z[col] = zn;
+    delta[col] = d + mu * ((double)zn - (double)xn);
 }
 
 // Column pass over the orthant columns [0, n_orth).
@@ -240,15 +271,7 @@ k_col_orth(int n_orth, const int *__restrict__ cp, const int *__restrict__ ri, c
     const double d = delta[col];
     const int beg = cp[col], end = cp[col + 1];
     const T atu = col_atu<L, E, S>(col, beg, end, lane, ri, vc, u, P, n);
-    if (lane == 0) {
-        const T dm = (T)(d * inv_mu);
-        const T xn = x_step<T>(end - beg, xo, zo, atu, dm, cj, inv_mu);
-        const T v = xn - dm;
-        const T zn = v > (T)0 ? v : (T)0;
-        x[col] = xn;
-        z[col] = zn;
-        delta[col] = d + mu * ((double)zn - (double)xn);
-    }
+    if (lane == 0) orth_step<T>(col, end - beg, xo, zo, cj, d, atu, x, z, delta, mu, inv_mu);
 }
 
 // Column pass over second-order cones.  Workgroup t owns whole cones
@@ -411,37 +434,53 @@ k_row_slab(int m, const int *__restrict__ srp, const int *__restrict__ sci, cons
     }
 }
 
-// Row update from slab partials; the MODEs of k_row.
+// Block-2 update of one row from q = (A x)_row: e = F_U (b - q), lambda and
+// u; MODE 1 adds the row residual terms from qd (A x in FP64) and the FP64
+// partials of A z.
 template <typename T, int S, int MODE>
+__device__ __forceinline__ void row_step(int row, int m, T q, double qd, const double *__restrict__ Pz,
+                                         const T *__restrict__ b,
+                                         const double *__restrict__ b64, const T *__restrict__ fu,
+                                         double *__restrict__ lam, T *__restrict__ u, double mu, double inv_mu,
+                                         double (&acc)[3], double (&mx)[2])
+{
+    const T bi = b[row], fi = fu[row];
+    const double l0 = lam[row];
+    const T e = fi * (bi - q);
+    const double li = (MODE == 2) ? l0 : l0 - mu * (double)e;
+    if (MODE != 2) lam[row] = li;
+    u[row] = (T)((double)e - li * inv_mu);
+    if (MODE == 1) {
+        double qz = 0.0;
+#pragma unroll
+        for (int sl = 0; sl < S; ++sl) qz += Pz[(size_t)sl * m + row];
+        const double bd = b64[row];
+        const double rz = qz - bd, rx = qd - bd;
+        acc[0] = rz * rz;
+        acc[1] = bd * li;
+        acc[2] = rx * rx;
+        mx[0] = fabs(rz);
+        mx[1] = fabs(qz);
+    }
+}
+
+// Row update from slab partials P (type TP); the MODEs of k_row.  MODE 1
+// also forms the row residual partials: a check's products of A x and A z
+// are both FP64 (FP64 values of A, FP64 sums, TP = double in both
+// precisions), and the mixed form's iteration goes on from A x rounded to
+// FP32.
+template <typename T, typename TP, int S, int MODE>
 __global__ void __launch_bounds__(kWG)
-k_row_combine(int m, const T *__restrict__ P, const T *__restrict__ b, const T *__restrict__ fu,
-              double *__restrict__ lam, T *__restrict__ u, double mu, double inv_mu, double *__restrict__ part,
-              int pstride, DevStatus *st)
+k_row_combine(int m, const TP *__restrict__ P, const double *__restrict__ Pz, const T *__restrict__ b,
+              const double *__restrict__ b64, const T *__restrict__ fu, double *__restrict__ lam, T *__restrict__ u,
+              double mu, double inv_mu, double *__restrict__ part, int pstride, DevStatus *st)
 {
     if (MODE != 2 && st->done) return;
     const int row = blockIdx.x * kWG + threadIdx.x;
     double acc[3] = {0.0, 0.0, 0.0}, mx[2] = {0.0, 0.0};
     if (row < m) {
-        const T bi = b[row], fi = fu[row];
-        const double l0 = lam[row];
-        T q = 0, qz = 0;
-#pragma unroll
-        for (int sl = 0; sl < S; ++sl) {
-            q += P[(size_t)sl * m + row];
-            if (MODE == 1) qz += P[(size_t)(S + sl) * m + row];
-        }
-        const T e = fi * (bi - q);
-        const double li = (MODE == 2) ? l0 : l0 - mu * (double)e;
-        if (MODE != 2) lam[row] = li;
-        u[row] = (T)((double)e - li * inv_mu);
-        if (MODE == 1) {
-            const double rz = (double)qz - (double)bi, rx = (double)q - (double)bi;
-            acc[0] = rz * rz;
-            acc[1] = (double)bi * li;
-            acc[2] = rx * rx;
-            mx[0] = fabs(rz);
-            mx[1] = fabs((double)qz);
-        }
+        const TP q = slab_tree_sum<S>(P, m, row);
+        row_step<T, S, MODE>(row, m, (T)q, (double)q, Pz, b, b64, fu, lam, u, mu, inv_mu, acc, mx);
     }
     if (MODE != 2 && blockIdx.x == 0 && threadIdx.x == 0) st->iter += 1;
     if (MODE == 1) uv::block_sum_max<3, 2>(acc, mx, part + blockIdx.x, pstride);
@@ -564,7 +603,7 @@ k_finalize(int nrow, const double *__restrict__ prow, int ncol, const double *__
     const double rd = sqrt(s[3]) / (1.0 + sqrt(st->cnorm2));
     const double cz = s[4], bl = s[1];
     const double rg = fabs(cz + bl) / (1.0 + fabs(cz) + fabs(bl));
-    const double kkt = fmax(rp, fmax(rd, rg));
+    const double kkt = uv::kkt_of(rp, rd, rg);
     st->r_prim = rp;
     st->r_dual = rd;
     st->r_gap = rg;
@@ -629,6 +668,8 @@ struct uv_solver {
     int *scp = nullptr, *sri = nullptr;  // column-pass slab copy (S_col * n + 1 offsets)
     void *svc = nullptr;
     void *P_row = nullptr, *P_col = nullptr;  // slab partials (2 S_row m, S_col n)
+    double *sva64 = nullptr, *svc64 = nullptr;  // FP64 values of the slab copies
+    double *P_res = nullptr;    // FP64 slab partials of the mixed form's checks
     int nblk_row_fused = 0;     // row-residual partial blocks written by the check row pass
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -670,12 +711,27 @@ bool slabs_ok(int S) { return S == 0 || S == 1 || S == 2 || S == 4 || S == 8; }
 // ---- launch helpers (dispatch on precision, lanes L and unroll E) ----
 
 // Chunked slab product with the batch depth chosen at create time.
-template <typename T, int S>
+template <typename T, int S, typename G = T>
 void seg_chunk_launch(const uv_solver *s, unsigned grid, hipStream_t st, int nseg, const int *ptr, const int *idx,
-                      const T *val, const T *vec, T *out, const int *skip)
+                      const T *val, const G *vec, T *out, const int *skip)
 {
-    if (s->batch8) k_seg_chunk<T, T, S, 8><<<grid, kWG, 0, st>>>(nseg, ptr, idx, val, vec, out, skip);
-    else k_seg_chunk<T, T, S, 4><<<grid, kWG, 0, st>>>(nseg, ptr, idx, val, vec, out, skip);
+    if (s->batch8) k_seg_chunk<T, T, S, 8, G><<<grid, kWG, 0, st>>>(nseg, ptr, idx, val, vec, out, skip);
+    else k_seg_chunk<T, T, S, 4, G><<<grid, kWG, 0, st>>>(nseg, ptr, idx, val, vec, out, skip);
+}
+
+// FP64 partials of a check's A x (S m values; those of A z follow them):
+// the sweep's own partial buffer in FP64, a buffer of their own in the
+// mixed form.
+template <typename T>
+double *check_px(const uv_solver *s)
+{
+    return sizeof(T) == sizeof(double) ? (double *)s->P_row : s->P_res;
+}
+
+template <typename T, int S>
+double *row_pz(const uv_solver *s)
+{
+    return check_px<T>(s) + (size_t)S * s->m;
 }
 
 template <typename T, int L, int E, int S>
@@ -683,28 +739,39 @@ void row_slab_launch(uv_solver *s, hipStream_t st, int mode)
 {
     const unsigned g = S * blocks_for(s->m, kWG / L), gc = blocks_for(s->m, kWG);
     const double mu = s->o.mu, im = 1.0 / s->o.mu;
+    if (s->chunked && mode == 1) {
+        // a check: A z and A x with FP64 values of A and FP64 sums (the mixed
+        // form gathers its FP32 iterates), then the update from A x
+        const unsigned gk = S * blocks_for(s->m, kWG);
+        double *px = check_px<T>(s);
+        seg_chunk_launch<double, S, T>(s, gk, st, s->m, s->srp, s->sci, s->sva64, (const T *)s->z, row_pz<T, S>(s),
+                                       &s->st->done);
+        seg_chunk_launch<double, S, T>(s, gk, st, s->m, s->srp, s->sci, s->sva64, (const T *)s->x, px,
+                                       &s->st->done);
+        k_row_combine<T, double, S, 1><<<gc, kWG, 0, st>>>(s->m, px, row_pz<T, S>(s), (const T *)s->b, s->b64,
+                                                           (const T *)s->fu, s->lam, (T *)s->u, mu, im,
+                                                           s->part_row, s->nblk_row_fused, s->st);
+        return;
+    }
     if (s->chunked) {
         const unsigned gk = S * blocks_for(s->m, kWG);
         const bool ign = mode == 2;
         seg_chunk_launch<T, S>(s, gk, st, s->m, s->srp, s->sci, (const T *)s->sva, (const T *)s->x, (T *)s->P_row,
                                ign ? nullptr : &s->st->done);
-        if (mode == 1)
-            seg_chunk_launch<T, S>(s, gk, st, s->m, s->srp, s->sci, (const T *)s->sva, (const T *)s->z,
-                                   (T *)s->P_row + (size_t)S * s->m, &s->st->done);
     }
 #define UV_SLAB_ARGS s->m, s->srp, s->sci, (const T *)s->sva, (const T *)s->x, (const T *)s->z, (T *)s->P_row
 #define UV_COMB_ARGS                                                                                       \
-    s->m, (const T *)s->P_row, (const T *)s->b, (const T *)s->fu, s->lam, (T *)s->u, mu, im, s->part_row,  \
-        s->nblk_row_fused, s->st
-    if (mode == 1) {
-        if (!s->chunked) k_row_slab<T, L, E, S, true><<<g, kWG, 0, st>>>(UV_SLAB_ARGS, 0, s->st);
-        k_row_combine<T, S, 1><<<gc, kWG, 0, st>>>(UV_COMB_ARGS);
+    s->m, (const T *)s->P_row, row_pz<T, S>(s), (const T *)s->b, s->b64, (const T *)s->fu, s->lam,         \
+        (T *)s->u, mu, im, s->part_row, s->nblk_row_fused, s->st
+    if (mode == 1) {  // lane-group slab passes (FP64 only)
+        k_row_slab<T, L, E, S, true><<<g, kWG, 0, st>>>(UV_SLAB_ARGS, 0, s->st);
+        k_row_combine<T, T, S, 1><<<gc, kWG, 0, st>>>(UV_COMB_ARGS);
     } else if (mode == 2) {
         if (!s->chunked) k_row_slab<T, L, E, S, false><<<g, kWG, 0, st>>>(UV_SLAB_ARGS, 1, s->st);
-        k_row_combine<T, S, 2><<<gc, kWG, 0, st>>>(UV_COMB_ARGS);
+        k_row_combine<T, T, S, 2><<<gc, kWG, 0, st>>>(UV_COMB_ARGS);
     } else {
         if (!s->chunked) k_row_slab<T, L, E, S, false><<<g, kWG, 0, st>>>(UV_SLAB_ARGS, 0, s->st);
-        k_row_combine<T, S, 0><<<gc, kWG, 0, st>>>(UV_COMB_ARGS);
+        k_row_combine<T, T, S, 0><<<gc, kWG, 0, st>>>(UV_COMB_ARGS);
     }
 #undef UV_SLAB_ARGS
 #undef UV_COMB_ARGS
@@ -853,10 +920,22 @@ void dispatch_le_res(uv_solver *s, hipStream_t st, int L)
 
 void launch_col(uv_solver *s, hipStream_t st) { dispatch<ColLaunch>(s, st, s->L_col, s->E_col, 0); }
 
-// mode: 0 iterate, 1 iterate + residual partials (FP64 only), 2 resume
+// The row pass of a check also forms the row residual partials: in FP64
+// always, in the mixed form when its FP64 A z goes through the chunked slab
+// product (else a separate residual pass follows).
+bool fused_row_check(const uv_solver *s)
+{
+    return s->o.precision == UV_FP64 || (s->S_row > 1 && s->chunked);
+}
+
+// Column residuals by the chunked slab product of A'lambda over the FP64
+// values of the column slab copy.
+bool slab_col_check(const uv_solver *s) { return s->S_col > 1 && s->chunked; }
+
+// mode: 0 iterate, 1 iterate + residual partials, 2 resume
 void launch_row(uv_solver *s, hipStream_t st, int mode)
 {
-    if (s->o.precision == UV_MIXED && mode == 1) mode = 0;
+    if (mode == 1 && !fused_row_check(s)) mode = 0;
     dispatch<RowLaunch>(s, st, s->L_row, s->E_row, mode);
 }
 
@@ -868,18 +947,23 @@ template <int S>
 void res_col_slab_launch(uv_solver *s, hipStream_t st)
 {
     const unsigned g = blocks_for(s->n, kWG);
-    seg_chunk_launch<double, S>(s, S * g, st, s->n, s->scp, s->sri, (const double *)s->svc, s->lam,
-                                (double *)s->P_col, nullptr);
-    k_res_col_slab<double, S><<<g, kWG, 0, st>>>(s->n, (const double *)s->P_col, s->c64, s->delta,
-                                                 (const double *)s->z, s->part_col, (int)g);
+    const bool mixed = s->o.precision == UV_MIXED;
+    double *P = mixed ? s->P_res : (double *)s->P_col;
+    seg_chunk_launch<double, S>(s, S * g, st, s->n, s->scp, s->sri, s->svc64, s->lam, P, nullptr);
+    if (mixed)
+        k_res_col_slab<float, S><<<g, kWG, 0, st>>>(s->n, P, s->c64, s->delta, (const float *)s->z, s->part_col,
+                                                    (int)g);
+    else
+        k_res_col_slab<double, S><<<g, kWG, 0, st>>>(s->n, P, s->c64, s->delta, (const double *)s->z,
+                                                     s->part_col, (int)g);
 }
 
 void launch_residuals(uv_solver *s, hipStream_t st, bool row_done, bool decide)
 {
     if (!row_done) dispatch_le_res<ResRowLaunch>(s, st, s->L_row);
-    // FP64 with column slabs and chunked passes: A'lambda through the slab copy
-    // (its values are the FP64 ones), else the plain column residual pass
-    const bool slab = s->o.precision == UV_FP64 && s->S_col > 1 && s->chunked;
+    // with column slabs and chunked passes A'lambda goes through the slab copy
+    // (FP64 values in both precisions), else the plain column residual pass
+    const bool slab = slab_col_check(s);
     if (slab) {
         if (s->S_col == 2) res_col_slab_launch<2>(s, st);
         else if (s->S_col == 4) res_col_slab_launch<4>(s, st);
@@ -897,7 +981,7 @@ void launch_residuals(uv_solver *s, hipStream_t st, bool row_done, bool decide)
 void launch_iteration(uv_solver *s, hipStream_t st, bool check)
 {
     launch_col(s, st);
-    const bool fused = check && s->o.precision == UV_FP64;
+    const bool fused = check && fused_row_check(s);
     launch_row(s, st, fused ? 1 : 0);
     if (check) launch_residuals(s, st, fused, true);
 }
@@ -1094,8 +1178,15 @@ int setup(uv_solver *s, const uv_csr *A, const double *b, const double *c, const
             if (!sval) return UV_ENOMEM;
             if (nnz > 0) k_narrow<float><<<blocks_for(nnz, kWG), kWG, 0, st>>>(nnz, sval64, (float *)sval);
         }
-        if (pass == 0) { s->srp = off; s->sci = sidx; s->sva = sval; s->P_row = part; }
-        else { s->scp = off; s->sri = sidx; s->svc = sval; s->P_col = part; }
+        if (pass == 0) { s->srp = off; s->sci = sidx; s->sva = sval; s->sva64 = sval64; s->P_row = part; }
+        else { s->scp = off; s->sri = sidx; s->svc = sval; s->svc64 = sval64; s->P_col = part; }
+    }
+    if (mixed && (s->S_row > 1 || s->S_col > 1)) {
+        // FP64 partials of the checks' A z and A'lambda
+        const size_t pr = s->S_row > 1 ? 2 * (size_t)s->S_row * m : 0;
+        const size_t pc = s->S_col > 1 ? (size_t)s->S_col * n : 0;
+        s->P_res = dalloc<double>(s, std::max(pr, pc));
+        if (!s->P_res) return UV_ENOMEM;
     }
 
     // F_U, narrowed copies, norms.

@@ -22,18 +22,22 @@ using uv::kWG;
 // S * ceil(nseg / kWG) workgroups; workgroup w works on slab w % S.
 constexpr int kChunkCap = 512;  // LDS products per wavefront and round
 
-template <typename T, typename TV, int S, int U = 4>
-__global__ void __launch_bounds__(kWG)
-k_seg_chunk(int nseg, const int *__restrict__ ptr, const int *__restrict__ idx, const TV *__restrict__ val,
-            const T *__restrict__ vec, T *__restrict__ out, const int *skip)
+// One workgroup's share of the chunked product: wavefront w of workgroup
+// group `grp` owns segments (grp * 4 + w) * 64 + lane of slab `sl` and the
+// function returns that segment's sum (0 past nseg).  No early exit, so a
+// caller may synchronise the workgroup afterwards.  G is the type of the
+// gathered vector (the FP64 residual products of the mixed-precision form
+// gather FP32 iterates); products and sums are in T.
+template <typename T, typename TV, int S, int U, typename G>
+__device__ __forceinline__ T chunk_sum(int nseg, int sl, int grp, const int *__restrict__ ptr,
+                                       const int *__restrict__ idx, const TV *__restrict__ val,
+                                       const G *__restrict__ vec, T (*buf)[kChunkCap])
 {
     static_assert(kChunkCap % (64 * U) == 0, "a round holds whole batches");
-    if (skip && *skip) return;  // a device flag (stop, or nothing left to do)
-    __shared__ T buf[kWG / 64][kChunkCap];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int sl = blockIdx.x % S;
-    const int g0 = ((blockIdx.x / S) * (kWG / 64) + w) * 64;
-    if (g0 >= nseg) return;  // the whole wavefront leaves
+    const int g0 = (grp * (kWG / 64) + w) * 64;
+    T acc = 0;
+    if (g0 >= nseg) return acc;  // the whole wavefront has no segment
     const int *p = ptr + (size_t)sl * nseg;  // p[nseg] is the slab's end
     const int gl = g0 + lane;
     const int beg = p[gl < nseg ? gl : nseg];
@@ -41,7 +45,6 @@ k_seg_chunk(int nseg, const int *__restrict__ ptr, const int *__restrict__ idx, 
     int end = __shfl_down(beg, 1);
     if (lane == 63) end = e_last;
     const int E0 = __shfl(beg, 0), E1 = e_last;
-    T acc = 0;
     for (int P0 = E0; P0 < E1; P0 += kChunkCap) {
         const int P1 = min(P0 + kChunkCap, E1);
         for (int b = P0; b < P1; b += 64 * U) {  // U coalesced 64-entry steps in flight
@@ -54,13 +57,13 @@ k_seg_chunk(int nseg, const int *__restrict__ ptr, const int *__restrict__ idx, 
                 j[u] = __builtin_nontemporal_load(idx + kk);
                 v[u] = __builtin_nontemporal_load(val + kk);
             }
-            T g[U];
+            G g[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) g[u] = vec[j[u]];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int k = b + u * 64 + lane;
-                if (k < P1) buf[w][k - P0] = (T)v[u] * g[u];
+                if (k < P1) buf[w][k - P0] = (T)v[u] * (T)g[u];
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -72,7 +75,37 @@ k_seg_chunk(int nseg, const int *__restrict__ ptr, const int *__restrict__ idx, 
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    return acc;
+}
+
+template <typename T, typename TV, int S, int U = 4, typename G = T>
+__global__ void __launch_bounds__(kWG)
+k_seg_chunk(int nseg, const int *__restrict__ ptr, const int *__restrict__ idx, const TV *__restrict__ val,
+            const G *__restrict__ vec, T *__restrict__ out, const int *skip)
+{
+    if (skip && *skip) return;  // a device flag (stop, or nothing left to do)
+    __shared__ T buf[kWG / 64][kChunkCap];
+    const int sl = blockIdx.x % S, grp = blockIdx.x / S;
+    const T acc = chunk_sum<T, TV, S, U, G>(nseg, sl, grp, ptr, idx, val, vec, buf);
+    const int gl = grp * kWG + threadIdx.x;
     if (gl < nseg) out[(size_t)sl * nseg + gl] = acc;
+}
+
+// Sum of the S slab partials of one segment in a fixed pairwise tree:
+// leaves 0 + p_s (a lone -0 becomes +0, as in a running sum from zero),
+// then (p0 + p1), (p2 + p3), ... and so on up; every update kernel adds the
+// partials this way, so results do not depend on the kernel.
+template <int S, typename T>
+__device__ __forceinline__ T slab_tree_sum(const T *__restrict__ P, size_t stride, size_t i)
+{
+    T v[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) v[q] = (T)0 + P[(size_t)q * stride + i];
+#pragma unroll
+    for (int w = S; w > 1; w >>= 1)
+#pragma unroll
+        for (int k = 0; k < w / 2; ++k) v[k] = v[2 * k] + v[2 * k + 1];
+    return v[0];
 }
 
 // Slabs of the gathered vector (`bytes` long) for the row pass (x gathered,

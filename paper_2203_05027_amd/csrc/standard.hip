@@ -326,7 +326,7 @@ k_std_finalize(int nr, const double *__restrict__ prow, int nc, const double *__
     st->r_prim = sqrt(s[0]) / (1.0 + sqrt(st->bnorm2));
     st->r_dual = sqrt(s[2]) / (1.0 + sqrt(st->cnorm2));
     st->r_gap = fabs(cz + bl) / (1.0 + fabs(cz) + fabs(bl));
-    st->kkt = fmax(st->r_prim, fmax(st->r_dual, st->r_gap));
+    st->kkt = uv::kkt_of(st->r_prim, st->r_dual, st->r_gap);
     st->pobj = cz;
     st->dobj = -bl;
     st->check_iter = st->iter;

@@ -327,3 +327,52 @@ def test_mixed_precision_socp():
     say(f"mixed socp: {r}")
     assert r["status"] == "converged" and r["kkt"] <= 1e-4
     assert inst["d_lower"] - 1e-3 <= r["pobj"] <= inst["p_upper"] + 1e-3
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("slabs", [(2, 2), (4, 2), (8, 8), (2, 1), (1, 4)])
+def test_chunk_depths_bitwise(precision, slabs):
+    """Four or eight 64-entry steps in flight per wavefront change only the
+    schedule of the chunked slab product, never its sums: bitwise the same
+    iterates and residuals, on a ragged LP and on a conic problem, and the
+    FP64 ones match the oracle."""
+    lp = I.lp_instance(1003, 2411, 5, seed=31)
+    conic = I.conic_instance(1003, 411, [3, 7, 50, 1, 260] + [5] * 40, 4, seed=23)
+    for inst in (lp, conic):
+        outs = []
+        for kernel in ("chunked", "chunked4", "auto"):
+            say(f"{precision} slabs={slabs} kernel={kernel} m={inst['m']} n={inst['n']}")
+            with Solver.from_instance(inst, eps=0.0, precision=precision, slabs_row=slabs[0],
+                                      slabs_col=slabs[1], check_every=9, slab_kernel=kernel) as s:
+                s.iterate(200)
+                outs.append((s.solution(), s.residuals()))
+        for sol, res in outs[1:]:
+            for k in KEYS:
+                assert np.array_equal(sol[k], outs[0][0][k]), k
+            assert res == outs[0][1]
+        if precision == "fp64":
+            orc = oracle.Oracle.from_instance(inst)
+            orc.iterate(200)
+            assert_parity(outs[0][0], orc.state())
+
+
+@pytest.mark.parametrize("slabs", [(4, 2), (1, 1), (2, 8)])
+@pytest.mark.parametrize("conic", [False, True])
+def test_mixed_check_residuals_at_the_state(slabs, conic):
+    """The mixed form's checks (FP64 values of A through the slab copies, FP64
+    sums) equal the oracle's residuals evaluated at the GPU's own iterate."""
+    inst = (I.conic_instance(2003, 911, [3, 7, 50, 1, 260] + [5] * 100, 4, seed=33) if conic
+            else I.lp_instance(3001, 6100, 6, seed=32))
+    with Solver.from_instance(inst, eps=0.0, precision="mixed", slabs_row=slabs[0], slabs_col=slabs[1],
+                              check_every=10) as s:
+        s.iterate(60)
+        g = s.solution()
+        gr = s.residuals()
+    assert gr["iter"] == 60
+    orc = oracle.Oracle.from_instance(inst)
+    orc.set_state(x=g["x"], z=g["z"], delta=g["delta"], lam=g["lambda"])
+    ro = orc.residuals()
+    say(f"mixed check slabs={slabs} conic={conic}: gpu kkt {gr['kkt']:.6e} oracle {ro['kkt']:.6e}")
+    for k in ("r_prim", "r_dual", "r_gap", "kkt", "pobj", "dobj", "res_ax_b", "prim_inf", "dual_inf",
+              "scale_p", "scale_d"):
+        assert abs(gr[k] - ro[k]) <= 1e-11 * max(abs(ro[k]), 1e-12), (k, gr[k], ro[k])
