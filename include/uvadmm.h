@@ -114,20 +114,30 @@ typedef struct {
     int32_t slabs_col;    /* XCD slabs of u in the A'u pass: 0 = automatic
                              (none up to 2 MiB of u, two up to 16 MiB, else
                              four), 1 = none, 2, 4, 8 */
-    int32_t criterion;    /* UV_CRIT_KKT or UV_CRIT_INF (see uv_residuals) */
-    double eps_abs;       /* absolute tolerance of UV_CRIT_INF */
+    int32_t criterion;    /* UV_CRIT_KKT, UV_CRIT_INF or UV_CRIT_POGS */
+    double eps_abs;       /* absolute tolerance of UV_CRIT_INF; the bound
+                             on ||A x - b||_2 of UV_CRIT_POGS */
     int32_t slab_kernel;  /* slab passes: 0 = automatic (= 1), 1 = 64-segment
                              chunks per wavefront (eight 64-entry steps in
                              flight), 2 = lane group per segment, 3 = chunks
                              with four steps in flight */
+    double eps_gap;       /* bound on |c'x + b'lambda| of UV_CRIT_POGS, and
+                             an extra condition of UV_CRIT_INF when > 0
+                             (0 = none); >= 0 */
 } uv_opts;
 
 /* Stopping tests (Section V): UV_CRIT_KKT stops when kkt <= eps_kkt (the
  * SCS-form relative residuals of Section V-B); UV_CRIT_INF stops when
  * prim_inf <= eps_abs + eps_kkt * scale_p and dual_inf <= eps_abs +
- * eps_kkt * scale_d (the infinity-norm test of Section V-A1). */
-#define UV_CRIT_KKT 0
-#define UV_CRIT_INF 1
+ * eps_kkt * scale_d (the infinity-norm test of the OSQP comparison, Section
+ * V-A1), and, when eps_gap > 0, gap_x < eps_gap (that comparison's gap
+ * condition); UV_CRIT_POGS stops when res_ax_b < eps_abs and gap_x <
+ * eps_gap (the test of the POGS comparison, Section V-A2, eq. stopcri, whose
+ * two bounds are the competitor's ||A x - b||_2 and |c'x + b'lambda|, given
+ * here by the caller).  Each is evaluated at the checks only. */
+#define UV_CRIT_KKT  0
+#define UV_CRIT_INF  1
+#define UV_CRIT_POGS 2
 
 /* Residuals at the last check, evaluated at (z, lambda, delta), all FP64
  * (the SCS-form test of Section V-B, with the dual residual taken for
@@ -136,7 +146,8 @@ typedef struct {
  *   r_dual = ||A'lambda + c - delta|| / (1 + ||c||)
  *   r_gap  = |c'z + b'lambda| / (1 + |c'z| + |b'lambda|)
  *   kkt    = max(r_prim, r_dual, r_gap)
- * pobj = c'z, dobj = -b'lambda, res_ax_b = ||A x - b|| (at x, as printed). */
+ * pobj = c'z, dobj = -b'lambda, res_ax_b = ||A x - b|| (at x, as printed),
+ * pobj_x = c'x and gap_x = |c'x + b'lambda| (the gap at x of Section V-A). */
 typedef struct {
     double r_prim, r_dual, r_gap, kkt;
     double pobj, dobj;
@@ -147,6 +158,8 @@ typedef struct {
     double scale_d;       /* max(||A'lambda||_inf, ||c||_inf) */
     int64_t iter;         /* iterations done when these were evaluated */
     int32_t status;       /* UV_STATUS_* */
+    double pobj_x;        /* c'x */
+    double gap_x;         /* |c'x + b'lambda| */
 } uv_residuals;
 
 typedef struct uv_solver uv_solver;
@@ -252,8 +265,8 @@ int batch_create(int32_t count, const uv_csr *A, const double *const *b,
 int batch_iterate(uv_batch *h, int64_t k, int32_t *n_active);
 
 /* Residuals / status of instance i at its last check (see uv_residuals;
- * the infinity-norm fields are not evaluated by the batched solver and read
- * 0).  Returns UV_ENUMERIC (with *r filled) when that instance stopped on a
+ * the infinity-norm fields, pobj_x and gap_x are not evaluated by the
+ * batched solver and read 0).  Returns UV_ENUMERIC (with *r filled) when that instance stopped on a
  * NaN or Inf. */
 int batch_residuals(uv_batch *h, int32_t i, uv_residuals *r);
 
@@ -328,7 +341,7 @@ int family_set_start_predicted(uv_family *h, const float *xl_dev, int64_t ld,
 int family_iterate(uv_family *h, int64_t k, int32_t *n_active);
 
 /* Residuals of the nb current instances into r[0..nb-1] (infinity-norm
- * fields not evaluated: 0).  Returns UV_ENUMERIC (with r filled) when any of
+ * fields, pobj_x and gap_x not evaluated: 0).  Returns UV_ENUMERIC (with r filled) when any of
  * them stopped on a NaN or Inf. */
 int family_residuals(uv_family *h, uv_residuals *r);
 

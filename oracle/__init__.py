@@ -93,7 +93,7 @@ def num_threads() -> int:
 
 
 RESIDUAL_KEYS = ("r_prim", "r_dual", "r_gap", "kkt", "pobj", "dobj",
-                 "res_ax_b", "res_x_z", "prim_inf", "dual_inf", "scale_p", "scale_d")
+                 "res_ax_b", "res_x_z", "prim_inf", "dual_inf", "scale_p", "scale_d", "pobj_x")
 
 
 def project(w, n_orth: int, soc_sizes=()) -> np.ndarray:
@@ -194,12 +194,12 @@ class Oracle:
         self._lib.orc_iterate(self._h, int(k))
 
     def residuals(self) -> dict:
-        out = np.empty(12)
+        out = np.empty(len(RESIDUAL_KEYS))
         self._lib.orc_residuals(self._h, _ptr(out))
         return dict(zip(RESIDUAL_KEYS, out.tolist()))
 
     def solve(self, eps: float, check_every: int = 10, max_iter: int = 100000):
-        out = np.empty(12)
+        out = np.empty(len(RESIDUAL_KEYS))
         it = self._lib.orc_solve(self._h, float(eps), int(check_every),
                                  int(max_iter), _ptr(out))
         r = dict(zip(RESIDUAL_KEYS, out.tolist()))

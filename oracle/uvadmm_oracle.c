@@ -406,6 +406,9 @@ static double serial_sum(const double *v, int64_t len)
  *   out[7] ||x - z||_2
  *   out[8] ||A z - b||_inf,  out[9] ||A'lambda + c - delta||_inf,
  *   out[10] max(||A z||_inf, ||b||_inf), out[11] max(||A'lambda||_inf, ||c||_inf)
+ *   out[12] c'x   (the objective at x, which the stopping test of the POGS
+ *                  comparison, Section V-A2, eq. stopcri, takes in its gap
+ *                  |c'x + b'lambda| beside ||A x - b||_2)
  *          (the infinity-norm termination test of Section V-A1, eq.
  *          stopcri_osqp, with the same readings: at z, delta subtracted)
  * Readings: the printed dual residual ||A'lambda + c|| is the one for free x;
@@ -454,9 +457,9 @@ void orc_residuals(orc_t *h, double *out)
     }
     free(azv);
     free(atlv);
-    double bb = 0.0, cc = 0.0, cz = 0.0, bl = 0.0;
+    double bb = 0.0, cc = 0.0, cz = 0.0, bl = 0.0, cx = 0.0;
     for (int32_t i = 0; i < m; ++i) { bb += h->b[i] * h->b[i]; bl += h->b[i] * h->lambda[i]; }
-    for (int32_t j = 0; j < n; ++j) { cc += h->c[j] * h->c[j]; cz += h->c[j] * h->z[j]; }
+    for (int32_t j = 0; j < n; ++j) { cc += h->c[j] * h->c[j]; cz += h->c[j] * h->z[j]; cx += h->c[j] * h->x[j]; }
 
     #pragma omp parallel for schedule(static) if (m >= ORC_PAR_MIN)
     for (int32_t i = 0; i < m; ++i) {
@@ -480,13 +483,14 @@ void orc_residuals(orc_t *h, double *out)
     out[9] = dinf;
     out[10] = fmax(azinf, binf);
     out[11] = fmax(atlinf, cinf);
+    out[12] = cx;
 }
 
 /* Runs until kkt <= eps at a check (every check_every iterations) or until
  * max_iter iterations; returns the iteration count at the stop. */
 int64_t orc_solve(orc_t *h, double eps, int64_t check_every, int64_t max_iter, double *res_out)
 {
-    double r[12];
+    double r[13];
     if (check_every < 1) check_every = 1;
     while (h->iter < max_iter) {
         int64_t k = check_every;

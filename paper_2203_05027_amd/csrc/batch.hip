@@ -860,6 +860,7 @@ int batch_residuals(uv_batch *h, int32_t i, uv_residuals *r)
     r->dobj = I.dobj;
     r->res_ax_b = I.res_ax_b;
     r->prim_inf = r->dual_inf = r->scale_p = r->scale_d = 0.0;
+    r->pobj_x = r->gap_x = 0.0;
     r->iter = I.iter;
     r->status = I.status;
     return I.status == UV_STATUS_NUMERIC ? UV_ENUMERIC : UV_OK;

@@ -786,6 +786,7 @@ int family_residuals(uv_family *h, uv_residuals *r)
         r[l].dobj = I.dobj;
         r[l].res_ax_b = I.res_ax_b;
         r[l].prim_inf = r[l].dual_inf = r[l].scale_p = r[l].scale_d = 0.0;
+        r[l].pobj_x = r[l].gap_x = 0.0;
         r[l].iter = I.status == UV_STATUS_RUNNING ? h->host_iter : I.iter;
         r[l].status = I.status;
         if (I.status == UV_STATUS_NUMERIC) rc = UV_ENUMERIC;

@@ -44,6 +44,7 @@ struct DevStatus {
     double bnorm2, cnorm2;
     double prim_inf, dual_inf, scale_p, scale_d;  // infinity-norm measures
     double binf, cinf;
+    double pobj_x, gap_x;  // c'x and |c'x + b'lambda| (the POGS-form test)
     long long iter;        // iterations done
     long long check_iter;  // iteration count at the last residual evaluation
     int done;              // 1 = stop: every sweep kernel returns at once
@@ -500,29 +501,30 @@ k_col_slab(int n, const int *__restrict__ scp, const int *__restrict__ sri, cons
     if (lane == 0) P[(size_t)sl * n + col] = a;
 }
 
-// Residual-only column pass: ||A'lambda + c - delta||^2 and c'z partials,
-// FP64 values of A.
+// Residual-only column pass: ||A'lambda + c - delta||^2, c'z and c'x
+// partials, FP64 values of A.
 template <typename T, int L>
 __global__ void __launch_bounds__(kWG)
 k_res_col(int n, const int *__restrict__ cp, const int *__restrict__ ri, const double *__restrict__ vc,
           const double *__restrict__ lam, const double *__restrict__ c, const double *__restrict__ delta,
-          const T *__restrict__ z, double *__restrict__ part, int pstride)
+          const T *__restrict__ z, const T *__restrict__ x, double *__restrict__ part, int pstride)
 {
     const int lane = threadIdx.x & (L - 1);
     const int col = blockIdx.x * (kWG / L) + threadIdx.x / L;
-    double acc[2] = {0.0, 0.0}, mx[2] = {0.0, 0.0};
+    double acc[3] = {0.0, 0.0, 0.0}, mx[2] = {0.0, 0.0};
     if (col < n) {
-        const double cj = c[col], dj = delta[col], zj = (double)z[col];
+        const double cj = c[col], dj = delta[col], zj = (double)z[col], xj = (double)x[col];
         const double a = seg_dot<L, 4>(cp[col], cp[col + 1], lane, ri, vc, lam);
         if (lane == 0) {
             const double r = a + cj - dj;
             acc[0] = r * r;
             acc[1] = cj * zj;
+            acc[2] = cj * xj;
             mx[0] = fabs(r);
             mx[1] = fabs(a);
         }
     }
-    uv::block_sum_max<2, 2>(acc, mx, part + blockIdx.x, pstride);
+    uv::block_sum_max<3, 2>(acc, mx, part + blockIdx.x, pstride);
 }
 
 // Column residual partials from the slab partials of A'lambda (FP64 slab
@@ -530,10 +532,10 @@ k_res_col(int n, const int *__restrict__ cp, const int *__restrict__ ri, const d
 template <typename T, int S>
 __global__ void __launch_bounds__(kWG)
 k_res_col_slab(int n, const double *__restrict__ P, const double *__restrict__ c, const double *__restrict__ delta,
-               const T *__restrict__ z, double *__restrict__ part, int pstride)
+               const T *__restrict__ z, const T *__restrict__ x, double *__restrict__ part, int pstride)
 {
     const int col = blockIdx.x * kWG + threadIdx.x;
-    double acc[2] = {0.0, 0.0}, mx[2] = {0.0, 0.0};
+    double acc[3] = {0.0, 0.0, 0.0}, mx[2] = {0.0, 0.0};
     if (col < n) {
         double a = 0.0;
 #pragma unroll
@@ -542,27 +544,30 @@ k_res_col_slab(int n, const double *__restrict__ P, const double *__restrict__ c
         const double r = a + cj - delta[col];
         acc[0] = r * r;
         acc[1] = cj * (double)z[col];
+        acc[2] = cj * (double)x[col];
         mx[0] = fabs(r);
         mx[1] = fabs(a);
     }
-    uv::block_sum_max<2, 2>(acc, mx, part + blockIdx.x, pstride);
+    uv::block_sum_max<3, 2>(acc, mx, part + blockIdx.x, pstride);
 }
 
 // Adds the partials in a fixed order (eight independent loads in flight
 // per thread), forms the residuals and decides whether to stop.  Partials
 // are stored component-major: prow[k * nrow + block], rows: sums of
 // (Az-b)^2, b'lambda, (Ax-b)^2, then maxima of |Az-b|, |Az|; columns: sums of
-// (A'lambda+c-delta)^2, c'z, then maxima of |A'lambda+c-delta|, |A'lambda|.
-// crit 0: relative KKT (SCS form) <= eps; crit 1: infinity-norm test
-// ||Az-b|| <= eps_abs + eps max(||Az||, ||b||) and
-// ||A'lambda+c-delta|| <= eps_abs + eps max(||A'lambda||, ||c||).
+// (A'lambda+c-delta)^2, c'z, c'x, then maxima of |A'lambda+c-delta|,
+// |A'lambda|.  crit 0: relative KKT (SCS form) <= eps; crit 1: infinity-norm
+// test ||Az-b|| <= eps_abs + eps max(||Az||, ||b||) and
+// ||A'lambda+c-delta|| <= eps_abs + eps max(||A'lambda||, ||c||), and
+// |c'x + b'lambda| < eps_gap when eps_gap > 0; crit 2 (POGS form):
+// ||Ax-b||_2 < eps_abs and |c'x + b'lambda| < eps_gap.
 // decide 0 only records the values (a residual query between checks): the
 // status and the stop flag change at the checks of the iteration alone.
 __global__ void __launch_bounds__(kWG)
 k_finalize(int nrow, const double *__restrict__ prow, int ncol, const double *__restrict__ pcol,
-           double eps, double eps_abs, int crit, int decide, DevStatus *st)
+           double eps, double eps_abs, double eps_gap, int crit, int decide, DevStatus *st)
 {
-    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, w[4] = {0.0, 0.0, 0.0, 0.0};
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, w[4] = {0.0, 0.0, 0.0, 0.0};
     for (int base = threadIdx.x; base < nrow; base += 8 * kWG) {
         double a[5][8];
 #pragma unroll
@@ -581,44 +586,56 @@ k_finalize(int nrow, const double *__restrict__ prow, int ncol, const double *__
         }
     }
     for (int base = threadIdx.x; base < ncol; base += 8 * kWG) {
-        double a[4][8];
+        double a[5][8];
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const int i = base + r * kWG;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) a[k][r] = i < ncol ? pcol[k * ncol + i] : 0.0;
+            for (int k = 0; k < 5; ++k) a[k][r] = i < ncol ? pcol[k * ncol + i] : 0.0;
         }
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             v[3] += a[0][r];
             v[4] += a[1][r];
-            w[2] = fmax(w[2], a[2][r]);
-            w[3] = fmax(w[3], a[3][r]);
+            v[5] += a[2][r];
+            w[2] = fmax(w[2], a[3][r]);
+            w[3] = fmax(w[3], a[4][r]);
         }
     }
-    double s[9];
-    uv::block_sum_max<5, 4>(v, w, s, 1);
+    double s[10];
+    uv::block_sum_max<6, 4>(v, w, s, 1);
     if (threadIdx.x != 0) return;
     const double rp = sqrt(s[0]) / (1.0 + sqrt(st->bnorm2));
     const double rd = sqrt(s[3]) / (1.0 + sqrt(st->cnorm2));
-    const double cz = s[4], bl = s[1];
+    const double cz = s[4], bl = s[1], cx = s[5];
     const double rg = fabs(cz + bl) / (1.0 + fabs(cz) + fabs(bl));
     const double kkt = uv::kkt_of(rp, rd, rg);
+    const double res_ax_b = sqrt(s[2]), gap_x = fabs(cx + bl);
     st->r_prim = rp;
     st->r_dual = rd;
     st->r_gap = rg;
     st->kkt = kkt;
     st->pobj = cz;
     st->dobj = -bl;
-    st->res_ax_b = sqrt(s[2]);
-    st->prim_inf = s[5];
-    st->dual_inf = s[7];
-    st->scale_p = fmax(s[6], st->binf);
-    st->scale_d = fmax(s[8], st->cinf);
+    st->res_ax_b = res_ax_b;
+    st->prim_inf = s[6];
+    st->dual_inf = s[8];
+    st->scale_p = fmax(s[7], st->binf);
+    st->scale_d = fmax(s[9], st->cinf);
+    st->pobj_x = cx;
+    st->gap_x = gap_x;
     st->check_iter = st->iter;
     if (!decide) return;
-    const bool conv = crit == 1 ? (s[5] <= eps_abs + eps * st->scale_p && s[7] <= eps_abs + eps * st->scale_d)
-                                : kkt <= eps;
+    // crit 1 adds the gap condition when eps_gap > 0; crit 2 is the POGS
+    // form (strict inequalities as printed)
+    bool conv;
+    if (crit == 1)
+        conv = s[6] <= eps_abs + eps * st->scale_p && s[8] <= eps_abs + eps * st->scale_d &&
+               (eps_gap <= 0.0 || gap_x < eps_gap);
+    else if (crit == 2)
+        conv = res_ax_b < eps_abs && gap_x < eps_gap;
+    else
+        conv = kkt <= eps;
     if (!isfinite(kkt)) {
         st->status = UV_STATUS_NUMERIC;
         st->done = 1;
@@ -863,7 +880,7 @@ struct ResColLaunch {
     {
         const unsigned g = blocks_for(s->n, kWG / L);
         k_res_col<T, L><<<g, kWG, 0, st>>>(s->n, s->cp, s->ri, s->vc64, s->lam, s->c64, s->delta,
-                                           (const T *)s->z, s->part_col, s->nblk_rescol);
+                                           (const T *)s->z, (const T *)s->x, s->part_col, s->nblk_rescol);
     }
 };
 
@@ -951,11 +968,11 @@ void res_col_slab_launch(uv_solver *s, hipStream_t st)
     double *P = mixed ? s->P_res : (double *)s->P_col;
     seg_chunk_launch<double, S>(s, S * g, st, s->n, s->scp, s->sri, s->svc64, s->lam, P, nullptr);
     if (mixed)
-        k_res_col_slab<float, S><<<g, kWG, 0, st>>>(s->n, P, s->c64, s->delta, (const float *)s->z, s->part_col,
-                                                    (int)g);
+        k_res_col_slab<float, S><<<g, kWG, 0, st>>>(s->n, P, s->c64, s->delta, (const float *)s->z,
+                                                    (const float *)s->x, s->part_col, (int)g);
     else
         k_res_col_slab<double, S><<<g, kWG, 0, st>>>(s->n, P, s->c64, s->delta, (const double *)s->z,
-                                                     s->part_col, (int)g);
+                                                     (const double *)s->x, s->part_col, (int)g);
 }
 
 void launch_residuals(uv_solver *s, hipStream_t st, bool row_done, bool decide)
@@ -974,7 +991,7 @@ void launch_residuals(uv_solver *s, hipStream_t st, bool row_done, bool decide)
     const int nrow = row_done ? s->nblk_row_fused : s->nblk_row;
     const int ncol = slab ? (int)blocks_for(s->n, kWG) : s->nblk_rescol;
     k_finalize<<<1, kWG, 0, st>>>(nrow, s->part_row, ncol, s->part_col, s->o.eps_kkt, s->o.eps_abs,
-                                  s->o.criterion, decide ? 1 : 0, s->st);
+                                  s->o.eps_gap, s->o.criterion, decide ? 1 : 0, s->st);
 }
 
 // One iteration; with check, the residuals of the new iterate follow it.
@@ -1010,7 +1027,7 @@ int validate(const uv_csr *A, const double *b, const double *c, const uv_cones *
     if (!(o->mu > 0.0) || !std::isfinite(o->mu)) return UV_EINVAL;
     if (o->precision != UV_FP64 && o->precision != UV_MIXED) return UV_EINVAL;
     if (o->check_every < 1 || !(o->eps_kkt >= 0.0) || o->max_iter < 0) return UV_EINVAL;
-    if ((o->criterion != 0 && o->criterion != 1) || !(o->eps_abs >= 0.0)) return UV_EINVAL;
+    if (o->criterion < 0 || o->criterion > 2 || !(o->eps_abs >= 0.0) || !(o->eps_gap >= 0.0)) return UV_EINVAL;
     if (!lanes_ok(o->lanes_row) || !lanes_ok(o->lanes_col)) return UV_EINVAL;
     if (!unroll_ok(o->unroll_row) || !unroll_ok(o->unroll_col)) return UV_EINVAL;
     if (!slabs_ok(o->slabs_row) || !slabs_ok(o->slabs_col)) return UV_EINVAL;
@@ -1084,7 +1101,7 @@ int setup(uv_solver *s, const uv_csr *A, const double *b, const double *c, const
     s->nblk_row_fused = s->S_row > 1 ? (int)blocks_for(m, kWG) : s->nblk_row;
     s->nblk_rescol = (int)blocks_for(n, kWG / s->L_col);
     s->part_row = dalloc<double>(s, 5 * (size_t)std::max(s->nblk_row, s->nblk_row_fused));
-    s->part_col = dalloc<double>(s, 4 * std::max((size_t)s->nblk_rescol, (size_t)blocks_for(n, kWG)));
+    s->part_col = dalloc<double>(s, 5 * std::max((size_t)s->nblk_rescol, (size_t)blocks_for(n, kWG)));
     s->st = dalloc<DevStatus>(s, 1);
     const size_t ncnt = std::max({(size_t)n, (size_t)s->S_row * m, (size_t)s->S_col * n});
     int *cnt = dalloc<int>(s, ncnt);
@@ -1239,6 +1256,7 @@ void uv_default_opts(uv_opts *o)
     o->criterion = 0;
     o->eps_abs = 0.0;
     o->slab_kernel = 0;
+    o->eps_gap = 0.0;
 }
 
 const char *solver_strerror(int code)
@@ -1440,6 +1458,8 @@ int solver_residuals(uv_solver *s, uv_residuals *r)
     r->scale_d = h->scale_d;
     r->iter = h->iter;
     r->status = h->status;
+    r->pobj_x = h->pobj_x;
+    r->gap_x = h->gap_x;
     return UV_OK;
 }
 

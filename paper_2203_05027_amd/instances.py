@@ -288,6 +288,12 @@ CONFIGS = {
     "lp_parametric": dict(kind="param", m=50_000, n=100_000, k=8, p=64, seed=4),
     "paper_lp": dict(kind="paper", m=20_000, n=100_000, density=0.005, cone="lp", seed=5),
     "paper_socp": dict(kind="paper", m=20_000, n=100_000, density=0.005, cone="socp", seed=6),
+    # the section's other two densities, at its largest entry count (1e7)
+    # for 1.0 % and 2e6 entries for 0.1 %
+    "paper_lp_0p1": dict(kind="paper", m=20_000, n=100_000, density=0.001, cone="lp", seed=7),
+    "paper_socp_0p1": dict(kind="paper", m=20_000, n=100_000, density=0.001, cone="socp", seed=8),
+    "paper_lp_1p0": dict(kind="paper", m=10_000, n=100_000, density=0.01, cone="lp", seed=9),
+    "paper_socp_1p0": dict(kind="paper", m=10_000, n=100_000, density=0.01, cone="socp", seed=10),
 }
 
 

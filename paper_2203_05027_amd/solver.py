@@ -38,7 +38,8 @@ class UvOpts(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("unroll_row", ctypes.c_int32),
                 ("unroll_col", ctypes.c_int32), ("slabs_row", ctypes.c_int32),
                 ("slabs_col", ctypes.c_int32), ("criterion", ctypes.c_int32),
-                ("eps_abs", ctypes.c_double), ("slab_kernel", ctypes.c_int32)]
+                ("eps_abs", ctypes.c_double), ("slab_kernel", ctypes.c_int32),
+                ("eps_gap", ctypes.c_double)]
 
 
 class UvResiduals(ctypes.Structure):
@@ -48,7 +49,8 @@ class UvResiduals(ctypes.Structure):
                 ("res_ax_b", ctypes.c_double), ("prim_inf", ctypes.c_double),
                 ("dual_inf", ctypes.c_double), ("scale_p", ctypes.c_double),
                 ("scale_d", ctypes.c_double), ("iter", ctypes.c_int64),
-                ("status", ctypes.c_int32)]
+                ("status", ctypes.c_int32), ("pobj_x", ctypes.c_double),
+                ("gap_x", ctypes.c_double)]
 
 
 class UvError(RuntimeError):
@@ -156,7 +158,7 @@ class Solver:
     def __init__(self, m, n, row_ptr, col_idx, val, b, c, n_orth, soc_sizes=(), *,
                  mu=1.0, precision="fp64", check_every=10, eps=1e-4, max_iter=0,
                  lanes_row=0, lanes_col=0, unroll_row=0, unroll_col=0, slabs_row=0, slabs_col=0,
-                 criterion="kkt", eps_abs=0.0, slab_kernel="auto", use_graph=True, stream=None):
+                 criterion="kkt", eps_abs=0.0, eps_gap=0.0, slab_kernel="auto", use_graph=True, stream=None):
         L = lib()
         self.m, self.n = int(m), int(n)
         rp, ci, va, nnz = _csr(self.m, row_ptr, col_idx, val)
@@ -173,7 +175,8 @@ class Solver:
         o.lanes_row, o.lanes_col = int(lanes_row), int(lanes_col)
         o.unroll_row, o.unroll_col = int(unroll_row), int(unroll_col)
         o.slabs_row, o.slabs_col = int(slabs_row), int(slabs_col)
-        o.criterion = {"kkt": 0, "inf": 1}[criterion]
+        o.criterion = {"kkt": 0, "inf": 1, "pogs": 2}[criterion]
+        o.eps_gap = float(eps_gap)
         o.slab_kernel = {"auto": 0, "chunked": 1, "lanes": 2, "chunked4": 3}[slab_kernel]
         o.eps_abs = float(eps_abs)
         o.use_graph = 1 if use_graph else 0

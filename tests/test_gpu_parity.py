@@ -56,8 +56,10 @@ def test_small_lp_200_iterations():
     g, o, gr, orr = run_pair(I.config_instance("lp_small"), 200)
     assert_parity(g, o)
     for k in ("r_prim", "r_dual", "r_gap", "kkt", "pobj", "dobj", "res_ax_b", "prim_inf", "dual_inf",
-              "scale_p", "scale_d"):
+              "scale_p", "scale_d", "pobj_x"):
         assert abs(gr[k] - orr[k]) <= 1e-9 * max(abs(orr[k]), 1e-12), k
+    gap_x = abs(orr["pobj_x"] - orr["dobj"])
+    assert abs(gr["gap_x"] - gap_x) <= 1e-9 * max(gap_x, 1e-12)
     assert gr["iter"] == 200
 
 
@@ -77,6 +79,55 @@ def test_infinity_norm_criterion_stops_like_oracle():
         assert s.iterate(60_000)
         g = s.residuals()
     say(f"inf criterion: gpu {g['iter']} oracle {it}")
+    assert g["status"] == "converged" and g["iter"] == it
+
+
+def _oracle_stop(inst, test, cap=60_000):
+    """Iteration at which `test(residuals)` first holds on the oracle's
+    iterates, checked every 10 iterations."""
+    orc = oracle.Oracle.from_instance(inst)
+    it = 0
+    while it < cap:
+        orc.iterate(10)
+        it += 10
+        if test(orc.residuals()):
+            return it
+    return None
+
+
+@pytest.mark.parametrize("slabs", [1, 4])
+def test_pogs_criterion_stops_like_oracle(slabs):
+    """The stopping test of the POGS comparison (Section V-A2, eq. stopcri):
+    ||Ax - b||_2 and |c'x + b'lambda| below given bounds (there the
+    competitor's values; here fixed ones), at the same check as the same test
+    on the oracle's iterates."""
+    inst = I.config_instance("lp_small")
+    tp = 1e-3 * (1.0 + float(np.linalg.norm(inst["b"])))
+    tg = 1e-3 * (1.0 + abs(inst["p_star"]))
+    it = _oracle_stop(inst, lambda r: r["res_ax_b"] < tp and abs(r["pobj_x"] - r["dobj"]) < tg)
+    with Solver.from_instance(inst, eps=0.0, eps_abs=tp, eps_gap=tg, criterion="pogs",
+                              slabs_row=slabs, slabs_col=slabs) as s:
+        assert s.iterate(60_000)
+        g = s.residuals()
+    say(f"pogs criterion: gpu {g['iter']} oracle {it}")
+    assert g["status"] == "converged" and g["iter"] == it
+    assert g["res_ax_b"] < tp and g["gap_x"] < tg
+
+
+def test_infinity_norm_criterion_with_gap_stops_like_oracle():
+    """The OSQP comparison's test (Section V-A1) with its extra gap
+    condition |c'x + b'lambda| < eps_gap."""
+    inst = I.config_instance("lp_small")
+    tg = 3e-4 * (1.0 + abs(inst["p_star"]))
+
+    def test(r):
+        return (r["prim_inf"] <= 1e-4 + 1e-3 * r["scale_p"] and r["dual_inf"] <= 1e-4 + 1e-3 * r["scale_d"]
+                and abs(r["pobj_x"] - r["dobj"]) < tg)
+    it = _oracle_stop(inst, test)
+    with Solver.from_instance(inst, eps=1e-3, eps_abs=1e-4, eps_gap=tg, criterion="inf") as s:
+        assert s.iterate(60_000)
+        g = s.residuals()
+    say(f"inf + gap criterion: gpu {g['iter']} oracle {it}")
     assert g["status"] == "converged" and g["iter"] == it
 
 
@@ -278,7 +329,8 @@ def test_bitwise_reproducible():
             assert np.array_equal(o[k], outs[0][k])
 
 
-@pytest.mark.parametrize("name", ["lp_large", "socp_large", "paper_lp", "paper_socp"])
+@pytest.mark.parametrize("name", ["lp_large", "socp_large", "paper_lp", "paper_socp", "paper_lp_0p1",
+                                  "paper_socp_0p1", "paper_lp_1p0", "paper_socp_1p0"])
 def test_full_size_sampled_parity(name):
     """The full-size workloads in the launch configuration the benchmark
     times (automatic lanes, unroll and XCD slabs, graph replay): 3 iterations

@@ -44,7 +44,7 @@ def test_example1_hand_residuals(precision, slabs):
         r = s.residuals()
     want = {"r_prim": sqrt(2) / 4, "r_dual": sqrt(130) / 6, "r_gap": 2 / 5, "kkt": sqrt(130) / 6,
             "pobj": 1.0, "dobj": 3.0, "res_ax_b": sqrt(11), "prim_inf": 1.0, "dual_inf": 8.0,
-            "scale_p": 2.0, "scale_d": 9.0}
+            "scale_p": 2.0, "scale_d": 9.0, "pobj_x": 3.0, "gap_x": 0.0}
     for k, v in want.items():
         assert r[k] == pytest.approx(v, rel=1e-14, abs=1e-15), (k, r[k], v)
 

@@ -40,6 +40,8 @@ MUTANTS = {
                                        "double r = -atl + h->c[j] - h->delta[j];"),
     "printed residual at z": ("ax += h->ak[k] * h->x[h->ck[k]];", "ax += h->ak[k] * h->z[h->ck[k]];"),
     "dual objective sign": ("out[5] = -bl;", "out[5] = bl;"),
+    # the objective at x of the POGS-form test (Section V-A2)
+    "objective at x takes z": ("cx += h->c[j] * h->x[j];", "cx += h->c[j] * h->z[j];"),
 }
 PIN_FILES = [os.path.join(ROOT, "tests", f) for f in ("test_oracle_pins.py", "test_oracle_residual_pins.py")]
 

@@ -48,14 +48,15 @@ def test_example1_hand_residuals(oracle_mod):
       c'z = 1,  b'lambda = -2 - 1 + 0 = -3                     -> gap |1 - 3| / (1 + 1 + 3)
       A x = columns 1 + 2 = (1,0,5);  A x - b = (-1,-1,3)     -> sqrt(11)
       x - z = (0,1,0,0,0)                                     -> 1
-      ||Az||_inf = 2, ||b||_inf = 2, ||A'lambda||_inf = 9, ||c||_inf = 4."""
+      ||Az||_inf = 2, ||b||_inf = 2, ||A'lambda||_inf = 9, ||c||_inf = 4
+      c'x = 1 + 2 = 3 (the objective at x of the POGS-form gap)."""
     orc = _example1_oracle(oracle_mod, [2.0, 1.0, 2.0], [1.0, 2.0, 2.0, 0.0, 4.0])
     orc.set_state(x=[1, 1, 0, 0, 0], z=[1, 0, 0, 0, 0], delta=[0, 1, 0, 2, 0], lam=[-1, -1, 0])
     r = orc.residuals()
     want = {
         "r_prim": sqrt(2) / 4, "r_dual": sqrt(130) / 6, "r_gap": 2 / 5, "kkt": sqrt(130) / 6,
         "pobj": 1.0, "dobj": 3.0, "res_ax_b": sqrt(11), "res_x_z": 1.0,
-        "prim_inf": 1.0, "dual_inf": 8.0, "scale_p": 2.0, "scale_d": 9.0,
+        "prim_inf": 1.0, "dual_inf": 8.0, "scale_p": 2.0, "scale_d": 9.0, "pobj_x": 3.0,
     }
     for k, v in want.items():
         assert r[k] == pytest.approx(v, rel=1e-14, abs=1e-15), (k, r[k], v)
@@ -173,6 +174,6 @@ def test_random_states_against_dense_products(oracle_mod, kind):
         rd = np.linalg.norm(A.T @ lam + c - d) / (1 + np.linalg.norm(c))
         rg = abs(c @ z + b @ lam) / (1 + abs(c @ z) + abs(b @ lam))
         want = dict(r_prim=rp, r_dual=rd, r_gap=rg, kkt=max(rp, rd, rg), pobj=c @ z, dobj=-(b @ lam),
-                    res_ax_b=np.linalg.norm(A @ x - b), res_x_z=np.linalg.norm(x - z))
+                    res_ax_b=np.linalg.norm(A @ x - b), res_x_z=np.linalg.norm(x - z), pobj_x=c @ x)
         for k, v in want.items():
             assert r[k] == pytest.approx(v, rel=1e-12), k
