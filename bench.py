@@ -372,7 +372,13 @@ def bench_family_sweep(args, B=256, iters=300):
           flush=True)
 
 
-def bench_parametric(args):
+def parametric_block(n_train, n_eval, epochs, train_eps=1e-3, train_cap=20_000, ttk_cap=200_000,
+                     parts=("both", "primal", "dual"), projection=True, plain=8, cpu=True):
+    """The learned warm start on the parametric family (A 5e4 x 1e5, theta in
+    R^64): training solves, PCA, MLP training, then the held-out members
+    solved to 1e-4 cold and from the learned starts through the same
+    streaming family driver (B = 256 slots, a stopped member's slot takes the
+    next one at once)."""
     import torch
     from paper_2203_05027_amd import instances as I
     from paper_2203_05027_amd.solver import Solver
@@ -380,12 +386,12 @@ def bench_parametric(args):
 
     t0 = time.time()
     fam = I.ParametricFamily(m=50_000, n=100_000, k=8, p=64, seed=4)
-    train = np.stack([fam.theta(1_000_000 + i) for i in range(args.train)])
-    held = np.stack([fam.theta(2_000_000 + i) for i in range(args.eval)])
+    train = np.stack([fam.theta(1_000_000 + i) for i in range(n_train)])
+    held = np.stack([fam.theta(2_000_000 + i) for i in range(n_eval)])
     log(f"parametric family built in {time.time() - t0:.1f} s")
     ws = WarmStart(fam, k=256, hidden=(512, 512), B=256, log=log)
     t0 = time.time()
-    Y, st = ws.solve_members(train, eps=args.train_eps, max_iter=args.train_cap)
+    Y, st = ws.solve_members(train, eps=train_eps, max_iter=train_cap)
     t_data = time.time() - t0
     Ytrue = Y[: min(512, len(train))].clone()
     t0 = time.time()
@@ -394,14 +400,14 @@ def bench_parametric(args):
     del Y
     torch.cuda.empty_cache()
     t0 = time.time()
-    hist = ws.train(train, coef, epochs=args.epochs, batch=256, lr=1e-3)
+    hist = ws.train(train, coef, epochs=epochs, batch=256, lr=1e-3)
     t_train = time.time() - t0
     fit_err = ws.model_error(ws.predict(train[: len(Ytrue)]), Ytrue)
-    cmp = ws.compare(held, eps=1e-4, max_iter=args.ttk_cap, parts=("both", "primal", "dual"), projection=True)
+    cmp = ws.compare_stream(held, eps=1e-4, max_iter=ttk_cap, parts=parts, projection=projection)
     # plain single-problem solver, cold, on a few held-out members
     tp, ip = 0.0, 0
-    for th in held[: args.plain]:
-        with Solver.from_instance(fam.instance(th), precision="mixed", eps=1e-4, max_iter=args.ttk_cap) as s:
+    for th in held[:plain]:
+        with Solver.from_instance(fam.instance(th), precision="mixed", eps=1e-4, max_iter=ttk_cap) as s:
             t1 = time.perf_counter()
             while not s.iterate(5000):
                 pass
@@ -409,7 +415,7 @@ def bench_parametric(args):
             ip += s.residuals()["iter"]
     ne = len(held)
     cpu_member = None
-    if not args.no_cpu:
+    if cpu:
         import oracle
         orc = oracle.Oracle.from_instance(fam.instance(held[0]), mu=1.0)
         orc.iterate(1)
@@ -419,32 +425,42 @@ def bench_parametric(args):
         cpu_member = {"value": rate, "unit": "iter/s", "cores": oracle.num_threads(), "kind": "oracle",
                       "est_cold_member_s": float(np.median(cmp["cold"]["iters"])) / rate,
                       "sample": "100 FP64 iterations of the literal Algorithm 1 oracle on the first held-out member"}
+
     def summary(v):
         d = cmp[v]
         return {"seconds": d["seconds"], "per_member_s": d["seconds"] / ne,
                 "iters_median": float(np.median(d["iters"])), "iters_mean": float(np.mean(d["iters"])),
-                "converged": int(d["converged"].sum())}
+                "iters_total": int(d["iters"].sum()), "converged": int(d["converged"].sum())}
 
-    line = {
-        "metric": "time to 1e-4 KKT per member, learned warm start vs cold start (parametric LP family)",
-        "value": cmp["cold"]["seconds"] / cmp["both"]["seconds"],
-        "unit": "x (cold time / warm time, batched family solver)",
-        "n_gpus": 1, "higher_is_better": True, "dtype": "f32 sweep / f64 duals / bf16 mlp",
-        "data": "synthetic",
-        "config": {"workload": f"lp_parametric: m={fam.m} n={fam.n} nnz={fam.row_ptr[-1]}, theta in R^64, "
-                               f"{len(train)} training members (eps {args.train_eps}), {ne} held-out, "
-                               "MLP 64-512-512-256, PCA k=256"},
+    out = {
+        "workload": f"lp_parametric: m={fam.m} n={fam.n} nnz={fam.row_ptr[-1]}, theta in R^64, "
+                    f"{len(train)} training members (eps {train_eps}), {ne} held-out, "
+                    "MLP 64-512-512-256, PCA k=256, B=256 streaming slots",
+        "cold_over_warm_time": cmp["cold"]["seconds"] / cmp["both"]["seconds"],
         "train_data_s": t_data, "train_converged": float(st["converged"].mean()),
         "train_iters_median": float(np.median(st["iters"])), "pca_s": t_pca, "train_s": t_train,
         "train_mse_first_last": [hist[0], hist[-1]], "fit_rel_err_median": fit_err,
         "cold": summary("cold"),
         "warm": dict(summary("both"), predict_s=cmp["predict_seconds"]),
-        "warm_primal_only": summary("primal"),
-        "warm_dual_only": summary("dual"),
-        "basis_projection_of_solution": summary("projection"),
-        "plain_gpu_cold": {"members": args.plain, "seconds": tp, "per_member_s": tp / max(args.plain, 1),
-                           "iters": ip},
+        "plain_gpu_cold": {"members": plain, "seconds": tp, "per_member_s": tp / max(plain, 1), "iters": ip},
         "cpu_baseline": cpu_member,
+    }
+    for v, key in (("primal", "warm_primal_only"), ("dual", "warm_dual_only"),
+                   ("projection", "basis_projection_of_solution")):
+        if v in cmp:
+            out[key] = summary(v)
+    return out
+
+
+def bench_parametric(args):
+    out = parametric_block(args.train, args.eval, args.epochs, train_eps=args.train_eps,
+                           train_cap=args.train_cap, ttk_cap=args.ttk_cap, plain=args.plain, cpu=not args.no_cpu)
+    line = {
+        "metric": "time to 1e-4 KKT per member, learned warm start vs cold start (parametric LP family)",
+        "value": out["cold_over_warm_time"],
+        "unit": "x (cold time / warm time, batched family solver)",
+        "n_gpus": 1, "higher_is_better": True, "dtype": "f32 sweep / f64 duals / bf16 mlp",
+        "data": "synthetic", "config": {"workload": out.pop("workload")}, **out,
     }
     print(json.dumps(line), flush=True)
 
@@ -465,6 +481,9 @@ def main():
     ap.add_argument("--no-ttk", action="store_true",
                     help="skip the time-to-1e-4 runs (with --workload lp_batched: the sweep alone)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-workload block")
+    ap.add_argument("--no-parametric", action="store_true", help="skip the reduced learned-warm-start block")
+    ap.add_argument("--param-train", type=int, default=2048, help="reduced warm-start block: training members")
+    ap.add_argument("--param-eval", type=int, default=512, help="reduced warm-start block: held-out members")
     ap.add_argument("--no-standard", action="store_true", help="skip the standard ADMM + CG baseline")
     ap.add_argument("--no-small", action="store_true", help="skip the small-LP block")
     ap.add_argument("--no-literal", action="store_true", help="skip the literal Algorithm 1 ablation")
@@ -569,6 +588,13 @@ def main():
         batched = batched_block(cpu_threads=0 if args.no_cpu else host_threads())
         log(f"batched: {json.dumps(batched)}")
 
+    parametric = None
+    if not args.no_parametric and args.workload == "lp_large":
+        log("learned warm start, reduced set (bench.py --workload lp_parametric runs the full one)")
+        parametric = parametric_block(args.param_train, args.param_eval, args.epochs, parts=("both",),
+                                      projection=False, plain=2, cpu=False)
+        log(f"parametric: {json.dumps(parametric)}")
+
     cpu = None
     if not args.no_cpu:
         log("timing the CPU oracle")
@@ -616,6 +642,7 @@ def main():
                                       "what": "random-gather probe with the same pairs, table and slabs"}},
         "mixed": extra,
         "batched": batched,
+        "learned_warm_start": parametric,
         "standard_admm_cg": standard,
         "small_lp": small,
         "literal_algorithm1": literal,

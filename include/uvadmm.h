@@ -337,6 +337,21 @@ int family_set_start(uv_family *h, const double *x, const double *z,
 int family_set_start_predicted(uv_family *h, const float *xl_dev, int64_t ld,
                                int32_t parts);
 
+/* New members into stopped slots, so that a slot does not idle until the
+ * slowest member of its group stops: slots[0..count-1] (distinct, < nb,
+ * each holding a member that has stopped, else UV_EINVAL) take the
+ * right-hand sides b (count x m, host, instance-major) and either the zero
+ * start (xl_dev NULL) or the predicted start of family_set_start_predicted
+ * from the device FP32 rows xl_dev + q * ld, q < count (ld >= n + m; parts
+ * as there).  Each entering member counts its own iterations from here, is
+ * checked at the family's checks and is capped by max_iter on its own count
+ * (after a refill that cap takes effect at the first check at or past it).
+ * The other members are untouched; a member's iterates do not depend on the
+ * slot it runs in or on the other members. */
+int family_refill(uv_family *h, int32_t count, const int32_t *slots,
+                  const double *b, const float *xl_dev, int64_t ld,
+                  int32_t parts);
+
 /* Up to k more iterations; *n_active = instances still running. */
 int family_iterate(uv_family *h, int64_t k, int32_t *n_active);
 

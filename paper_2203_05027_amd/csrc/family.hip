@@ -26,7 +26,8 @@ namespace {
 constexpr int kResBlocks = 512;  // fixed grid of the residual passes
 
 struct FInst {
-    long long iter;  // iterations when stopped (or last check)
+    long long iter;  // the member's iterations when stopped (or at the last check)
+    long long iter0; // family iteration count when the member started
     double r_prim, r_dual, r_gap, kkt, pobj, dobj, res_ax_b;
     double bnorm2;
     int status;
@@ -267,10 +268,10 @@ k_fam_finalize(int B, int nblk, const double *__restrict__ red, double eps, long
             I.pobj = cz;
             I.dobj = -bl;
             I.res_ax_b = sqrt(a[2]);
-            I.iter = sh->iter;
+            I.iter = sh->iter - I.iter0;
             if (!isfinite(kkt)) I.status = UV_STATUS_NUMERIC;
             else if (kkt <= eps) I.status = UV_STATUS_CONVERGED;
-            else if (max_iter > 0 && sh->iter >= max_iter) I.status = UV_STATUS_MAX_ITER;
+            else if (max_iter > 0 && I.iter >= max_iter) I.status = UV_STATUS_MAX_ITER;
             running = I.status == UV_STATUS_RUNNING;
         }
     }
@@ -345,6 +346,7 @@ k_fam_reset(int B, int nb, FInst *inst, FShared *sh, const double *__restrict__ 
     if (l < B) {
         inst[l].status = l < nb ? UV_STATUS_RUNNING : UV_STATUS_CONVERGED;  // padding lanes never run
         inst[l].iter = 0;
+        inst[l].iter0 = 0;
     }
     if (l == 0) {
         sh->iter = 0;
@@ -393,6 +395,103 @@ __global__ void __launch_bounds__(1024) k_fam_bnorm(int B, const double *__restr
     inst[l].bnorm2 = s;
 }
 
+// Refill: right-hand side of the members entering slots[q] (q < count),
+// from the FP64 rows b[q * m + i] staged on the device.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_fam_slot_rhs(int m, int B, int count, const int *__restrict__ slots, const double *__restrict__ b,
+               T *__restrict__ BV, double *__restrict__ BV64)
+{
+    const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (size_t)count * m) return;
+    const int q = (int)(t / m), i = (int)(t % m);
+    const size_t o = (size_t)i * B + slots[q];
+    BV[o] = (T)b[t];
+    BV64[o] = b[t];
+}
+
+// Refill: start of the entering members, x and lambda from the FP32 rows
+// xl[q * ld + (0..n-1)] and xl[q * ld + n + (0..m-1)] (parts as in
+// family_set_start_predicted), or zero when xl is null.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_fam_slot_xl(int n, int m, int B, int count, const int *__restrict__ slots, const float *__restrict__ xl,
+              long long ld, int parts, T *__restrict__ X, double *__restrict__ LAM)
+{
+    const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const int len = n + m;
+    if (t >= (size_t)count * len) return;
+    const int q = (int)(t / len), j = (int)(t % len);
+    const int sl = slots[q];
+    const bool use = xl && (j < n ? (parts & 1) : (parts & 2));
+    const float v = use ? xl[(size_t)q * ld + j] : 0.0f;
+    if (j < n) X[(size_t)j * B + sl] = (T)v;
+    else LAM[(size_t)(j - n) * B + sl] = (double)v;
+}
+
+// Refill: z = max(x, 0) and delta = max(c + A'lambda, 0) of the entering
+// members (the arithmetic of k_fam_dual_start; zero for a zero start).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_fam_slot_zd(int n, int B, int count, const int *__restrict__ slots, const int *__restrict__ cp,
+              const int *__restrict__ ri, const double *__restrict__ vc, const double *__restrict__ LAM,
+              const double *__restrict__ c, const T *__restrict__ X, T *__restrict__ Z, double *__restrict__ D,
+              int zero)
+{
+    const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (size_t)count * n) return;
+    const int q = (int)(t / n), j = (int)(t % n);
+    const int sl = slots[q];
+    const size_t o = (size_t)j * B + sl;
+    if (zero) {
+        Z[o] = (T)0;
+        D[o] = 0.0;
+        return;
+    }
+    double a = 0.0;
+    for (int k = cp[j]; k < cp[j + 1]; ++k) a += vc[k] * LAM[(size_t)ri[k] * B + sl];
+    const double v = c[j] + a;
+    D[o] = v > 0.0 ? v : 0.0;
+    const T xo = X[o];
+    Z[o] = xo > (T)0 ? xo : (T)0;
+}
+
+// Refill: u = -lambda/mu of the entering members.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_fam_slot_u(int m, int B, int count, const int *__restrict__ slots, const double *__restrict__ LAM,
+             T *__restrict__ U, double inv_mu)
+{
+    const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (size_t)count * m) return;
+    const int q = (int)(t / m), i = (int)(t % m);
+    const size_t o = (size_t)i * B + slots[q];
+    U[o] = (T)(-LAM[o] * inv_mu);
+}
+
+// Refill: the entering members run from the family's current iteration;
+// the running count is taken again.
+__global__ void __launch_bounds__(1024)
+k_fam_slot_reset(int B, int count, const int *__restrict__ slots, FInst *inst, FShared *sh)
+{
+    __shared__ int s_run[1024];
+    const int l = threadIdx.x;
+    if (l < count) {
+        FInst &I = inst[slots[l]];
+        I.status = UV_STATUS_RUNNING;
+        I.iter = 0;
+        I.iter0 = sh->iter;
+    }
+    __syncthreads();
+    s_run[l] = l < B && inst[l].status == UV_STATUS_RUNNING;
+    __syncthreads();
+    if (l == 0) {
+        int t = 0;
+        for (int i = 0; i < (int)blockDim.x; ++i) t += s_run[i];
+        sh->active = t;
+    }
+}
+
 }  // namespace
 
 struct uv_family {
@@ -410,6 +509,8 @@ struct uv_family {
     double *stage = nullptr;  // B * max(m, n) doubles of staging
     FInst *inst = nullptr, *inst_host = nullptr;
     FShared *sh = nullptr, *sh_host = nullptr;
+    int *slots = nullptr;     // slot list of a refill (B entries)
+    bool refilled = false;    // a member entered after the last set_rhs / set_start
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int64_t host_iter = 0;
@@ -596,12 +697,13 @@ int family_create(const uv_csr *A, const double *c, int32_t B, const uv_opts *op
     h->stage = falloc<double>(h, (size_t)B * std::max(m, n));
     h->inst = falloc<FInst>(h, B);
     h->sh = falloc<FShared>(h, 1);
+    h->slots = falloc<int>(h, B);
     int *cnt = falloc<int>(h, n);
     int *bsum = falloc<int>(h, blocks_for(n, 4 * kWG));
     for (void *p : {(void *)h->rp, (void *)h->ci, (void *)h->va64, (void *)h->cp, (void *)h->ri, (void *)h->vc64,
                     (void *)h->c64, h->fu, h->va, h->vc, h->c, h->X, h->Z, h->U, h->BV, (void *)h->LAM,
                     (void *)h->D, (void *)h->BV64, (void *)h->prow, (void *)h->pcol, (void *)h->pred, (void *)h->stage,
-                    (void *)h->inst, (void *)h->sh, (void *)cnt, (void *)bsum})
+                    (void *)h->inst, (void *)h->sh, (void *)h->slots, (void *)cnt, (void *)bsum})
         if (!p) return fail(UV_ENOMEM);
     if (uv::host_malloc(&h->inst_host, sizeof(FInst) * B, hipHostMallocDefault) != hipSuccess) {
         h->inst_host = nullptr;
@@ -684,6 +786,7 @@ int family_set_start(uv_family *h, const double *x, const double *z, const doubl
     if (h->o.precision == UV_MIXED) k_fam_start<float><<<blocks_for(Bm, 256), 256, 0, st>>>(Bm, h->LAM, (float *)h->U, im);
     else k_fam_start<double><<<blocks_for(Bm, 256), 256, 0, st>>>(Bm, h->LAM, (double *)h->U, im);
     k_fam_reset<<<1, 1024, 0, st>>>(h->B, h->nb, h->inst, h->sh, h->BV64);
+    h->refilled = false;
     UV_FTRY(hipGetLastError());
     return fam_sync(h);
 }
@@ -731,7 +834,53 @@ int family_set_start_predicted(uv_family *h, const float *xl_dev, int64_t ld, in
         k_fam_start<double><<<blocks_for(Bm, 256), 256, 0, st>>>(Bm, h->LAM, (double *)h->U, im);
     }
     k_fam_reset<<<1, 1024, 0, st>>>(h->B, h->nb, h->inst, h->sh, h->BV64);
+    h->refilled = false;
     UV_FTRY(hipGetLastError());
+    return fam_sync(h);
+}
+
+int family_refill(uv_family *h, int32_t count, const int32_t *slots, const double *b, const float *xl_dev,
+                  int64_t ld, int32_t parts)
+{
+    if (!h || count < 0 || (count > 0 && (!slots || !b))) return UV_EINVAL;
+    if (count == 0) return UV_OK;
+    if (count > h->nb || (xl_dev && (ld < (int64_t)h->n + h->m || parts < 1 || parts > 3))) return UV_EINVAL;
+    std::vector<char> seen(h->B, 0);
+    for (int q = 0; q < count; ++q) {
+        const int sl = slots[q];
+        if (sl < 0 || sl >= h->nb || seen[sl] || h->inst_host[sl].status == UV_STATUS_RUNNING) return UV_EINVAL;
+        seen[sl] = 1;
+    }
+    hipStream_t st = h->stream;
+    const int B = h->B, m = h->m, n = h->n;
+    const bool mixed = h->o.precision == UV_MIXED;
+    const double im = 1.0 / h->o.mu;
+    UV_FTRY(hipMemcpyAsync(h->slots, slots, sizeof(int) * count, hipMemcpyHostToDevice, st));
+    // b rows through the staging buffer (count <= B rows of m doubles)
+    UV_FTRY(hipMemcpyAsync(h->stage, b, sizeof(double) * (size_t)count * m, hipMemcpyHostToDevice, st));
+    const unsigned gm = blocks_for((int64_t)count * m, 256), gn = blocks_for((int64_t)count * n, 256);
+    const unsigned gx = blocks_for((int64_t)count * (n + m), 256);
+    if (mixed) {
+        k_fam_slot_rhs<float><<<gm, 256, 0, st>>>(m, B, count, h->slots, h->stage, (float *)h->BV, h->BV64);
+        k_fam_slot_xl<float><<<gx, 256, 0, st>>>(n, m, B, count, h->slots, xl_dev, ld, parts, (float *)h->X, h->LAM);
+        k_fam_slot_zd<float><<<gn, 256, 0, st>>>(n, B, count, h->slots, h->cp, h->ri, h->vc64, h->LAM, h->c64,
+                                                 (const float *)h->X, (float *)h->Z, h->D, xl_dev ? 0 : 1);
+        k_fam_slot_u<float><<<gm, 256, 0, st>>>(m, B, count, h->slots, h->LAM, (float *)h->U, im);
+    } else {
+        k_fam_slot_rhs<double><<<gm, 256, 0, st>>>(m, B, count, h->slots, h->stage, (double *)h->BV, h->BV64);
+        k_fam_slot_xl<double><<<gx, 256, 0, st>>>(n, m, B, count, h->slots, xl_dev, ld, parts, (double *)h->X,
+                                                  h->LAM);
+        k_fam_slot_zd<double><<<gn, 256, 0, st>>>(n, B, count, h->slots, h->cp, h->ri, h->vc64, h->LAM, h->c64,
+                                                  (const double *)h->X, (double *)h->Z, h->D, xl_dev ? 0 : 1);
+        k_fam_slot_u<double><<<gm, 256, 0, st>>>(m, B, count, h->slots, h->LAM, (double *)h->U, im);
+    }
+    // ||b||^2 of every slot again (same fixed order as at set_rhs; the
+    // check's row partials serve as scratch)
+    k_fam_bnorm_part<<<blocks_for((int64_t)kBChunks * B, 256), 256, 0, st>>>(m, B, h->BV64, h->prow);
+    k_fam_bnorm<<<1, 1024, 0, st>>>(B, h->prow, h->inst);
+    k_fam_slot_reset<<<1, 1024, 0, st>>>(B, count, h->slots, h->inst, h->sh);
+    UV_FTRY(hipGetLastError());
+    h->refilled = true;
     return fam_sync(h);
 }
 
@@ -739,8 +888,12 @@ int family_iterate(uv_family *h, int64_t k, int32_t *n_active)
 {
     if (!h || k < 0) return UV_EINVAL;
     if (h->sh_host->active > 0) {
+        // without refills every member started at family iteration 0, so
+        // max_iter caps the family's count (the last check falls on it);
+        // after a refill the cap is each member's, applied at the checks
+        const bool cap = h->o.max_iter > 0 && !h->refilled;
         int64_t left = k;
-        if (h->o.max_iter > 0) left = std::min<int64_t>(left, h->o.max_iter - h->host_iter);
+        if (cap) left = std::min<int64_t>(left, h->o.max_iter - h->host_iter);
         int64_t it = h->host_iter, since = 0;
         const int ce = h->o.check_every;
         const int64_t look = 50 * (int64_t)ce;  // read the active count every 50 checks
@@ -751,7 +904,7 @@ int family_iterate(uv_family *h, int64_t k, int32_t *n_active)
                 left -= ce;
                 since += ce;
             } else {
-                fam_iteration(h, h->stream, (it + 1) % ce == 0 || (h->o.max_iter > 0 && it + 1 >= h->o.max_iter));
+                fam_iteration(h, h->stream, (it + 1) % ce == 0 || (cap && it + 1 >= h->o.max_iter));
                 it += 1;
                 left -= 1;
                 since += 1;
@@ -787,7 +940,7 @@ int family_residuals(uv_family *h, uv_residuals *r)
         r[l].res_ax_b = I.res_ax_b;
         r[l].prim_inf = r[l].dual_inf = r[l].scale_p = r[l].scale_d = 0.0;
         r[l].pobj_x = r[l].gap_x = 0.0;
-        r[l].iter = I.status == UV_STATUS_RUNNING ? h->host_iter : I.iter;
+        r[l].iter = I.status == UV_STATUS_RUNNING ? h->host_iter - I.iter0 : I.iter;
         r[l].status = I.status;
         if (I.status == UV_STATUS_NUMERIC) rc = UV_ENUMERIC;
     }

@@ -405,6 +405,8 @@ def _bind_family(L):
     L.family_set_start.restype = ctypes.c_int
     L.family_set_start_predicted.argtypes = [P, P, i64, i32]
     L.family_set_start_predicted.restype = ctypes.c_int
+    L.family_refill.argtypes = [P, i32, P, P, P, i64, i32]
+    L.family_refill.restype = ctypes.c_int
     L.family_iterate.argtypes = [P, i64, ctypes.POINTER(i32)]
     L.family_iterate.restype = ctypes.c_int
     L.family_residuals.argtypes = [P, P]
@@ -489,6 +491,19 @@ class Family:
         code = {"primal": 1, "dual": 2, "both": 3}[parts]
         _check(lib().family_set_start_predicted(self._h, ctypes.c_void_p(dev_ptr), int(ld), code),
                "family_set_start_predicted")
+
+    def refill(self, slots, b, dev_ptr=None, ld=0, parts="both"):
+        """New members into stopped slots: right-hand sides b (len(slots) x m)
+        and the zero start, or the predicted start of the device FP32 rows
+        [x ; lambda] at dev_ptr (row stride ld) for the members in order."""
+        sl = np.ascontiguousarray(slots, dtype=np.int32)
+        b = np.ascontiguousarray(np.atleast_2d(b), dtype=np.float64)
+        if b.shape != (sl.size, self.m):
+            raise ValueError(f"right-hand sides must be ({sl.size}, {self.m})")
+        code = {"primal": 1, "dual": 2, "both": 3}[parts]
+        ptr = ctypes.c_void_p(dev_ptr) if dev_ptr else None
+        _check(lib().family_refill(self._h, int(sl.size), _ptr(sl), _ptr(b), ptr, int(ld), code),
+               "family_refill")
 
     def iterate(self, k: int) -> int:
         a = ctypes.c_int32(0)

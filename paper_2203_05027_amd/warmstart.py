@@ -11,6 +11,11 @@ Pipeline, every numeric step in the library's kernels:
     start z = max(x, 0), delta = max(c + A'lambda, 0) -> iterate; the
     cold-started plain method remains the fallback (a member the warm start
     leaves unconverged is re-solved cold).
+
+Members stream through the family solver's B slots: a slot whose member
+stops takes the next pending member at once (family_refill), so the time to
+solve a set of members follows their total iteration count rather than the
+slowest member of each group of B.
 """
 from __future__ import annotations
 
@@ -20,6 +25,20 @@ import numpy as np
 
 from . import learn
 from .solver import Family
+
+
+class _Rhs:
+    """Right-hand sides b(theta) of a member list, made on demand for the
+    rows asked for (a slice or a list of member indices)."""
+
+    def __init__(self, fam, thetas):
+        self.fam, self.thetas = fam, np.asarray(thetas)
+
+    def __len__(self):
+        return len(self.thetas)
+
+    def __getitem__(self, idx):
+        return np.ascontiguousarray(self.fam.b_many(self.thetas[idx]))
 
 
 class WarmStart:
@@ -46,28 +65,18 @@ class WarmStart:
 
     # 1. training data --------------------------------------------------
     def solve_members(self, thetas, eps=1e-3, max_iter=20_000, out=None):
-        """Cold solves of every theta; rows [z ; lambda] go into the GPU
-        tensor ``out`` (len(thetas) x (n + m)).  Returns per-member stats."""
+        """Cold solves of every theta, streamed through the slots; rows
+        [z ; lambda] go into the GPU tensor ``out`` (len(thetas) x (n + m)).
+        Returns per-member stats."""
         torch = self.torch
         N = len(thetas)
         if out is None:
             out = torch.empty((N, self.D), dtype=torch.float32, device="cuda")
-        iters = np.zeros(N, dtype=np.int64)
-        conv = np.zeros(N, dtype=bool)
         t0 = time.time()
-        with self._family(eps, max_iter) as F:
-            for g0 in range(0, N, self.B):
-                th = thetas[g0: g0 + self.B]
-                F.set_rhs(self.fam.b_many(th))
-                while F.iterate(2000):
-                    pass
-                res = F.residuals()
-                iters[g0: g0 + len(th)] = [r["iter"] for r in res]
-                conv[g0: g0 + len(th)] = [r["status"] == "converged" for r in res]
-                F.solution_device(out[g0:].data_ptr(), self.D)
-                self.log(f"solved {g0 + len(th)}/{N}: median iters {int(np.median(iters[g0:g0 + len(th)]))}, "
-                         f"{time.time() - t0:.1f} s")
-        return out, {"iters": iters, "converged": conv, "seconds": time.time() - t0}
+        st = self.solve_stream(_Rhs(self.fam, thetas), eps=eps, max_iter=max_iter, keep=out)
+        self.log(f"solved {N}: median iters {int(np.median(st['iters']))}, {time.time() - t0:.1f} s")
+        st["seconds"] = time.time() - t0
+        return out, st
 
     # 2. basis ----------------------------------------------------------
     def fit_basis(self, Y, oversample=32, power_iters=2):
@@ -131,6 +140,119 @@ class WarmStart:
         return float(np.median(d))
 
     # 4. warm vs cold ---------------------------------------------------
+    def solve_stream(self, b_all, Yhat=None, parts="both", eps=1e-4, max_iter=100_000, chunk=50,
+                     keep=None):
+        """Solves every member (row of the host array b_all) through the B
+        slots, refilling a slot as soon as its member stops.  With Yhat
+        (device FP32 rows [x ; lambda], one per member) a member starts from
+        its prediction and, if that leaves it unconverged, is queued again
+        with the zero start (the cold fallback; its iterations add up).
+        keep: a device FP32 tensor (len(b_all) x (n + m)) that receives each
+        member's [z ; lambda] when it stops.  Returns {"iters", "converged",
+        "seconds"}; the time runs from the first right-hand side to the last
+        stop (predictions are made beforehand and timed by the caller)."""
+        torch = self.torch
+        N = len(b_all)
+        D = self.D
+        iters = np.zeros(N, np.int64)
+        conv = np.zeros(N, bool)
+        with self._family(eps, max_iter) as F:
+            buf = (torch.empty((self.B, D), dtype=torch.float32, device="cuda") if keep is not None else None)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            nb = min(N, self.B)
+            F.set_rhs(b_all[:nb])
+            if Yhat is not None:
+                F.set_start_predicted(Yhat.data_ptr(), D, parts)
+            owner = list(range(nb))                  # member in each slot (None: idle)
+            warm = [Yhat is not None] * nb           # whether the slot's member started warm
+            nxt, retry = nb, []
+            while True:
+                F.iterate(chunk)
+                res = F.residuals()
+                free, stopped = [], []
+                for sl in range(nb):
+                    mem = owner[sl]
+                    if mem is None:
+                        free.append(sl)
+                        continue
+                    r = res[sl]
+                    if r["status"] == "running":
+                        continue
+                    stopped.append(sl)
+                    iters[mem] += r["iter"]
+                    ok = r["status"] == "converged"
+                    if not ok and warm[sl]:
+                        retry.append(mem)            # the cold fallback
+                    else:
+                        conv[mem] = ok
+                    free.append(sl)
+                if keep is not None and stopped:
+                    F.solution_device(buf.data_ptr(), D)
+                    for sl in stopped:
+                        keep[owner[sl]].copy_(buf[sl])
+                for sl in stopped:
+                    owner[sl] = None
+                # pending members in order (contiguous prediction rows), then cold retries
+                take = min(len(free), N - nxt)
+                if take:
+                    sl_new = free[:take]
+                    ptr = Yhat[nxt].data_ptr() if Yhat is not None else None
+                    F.refill(sl_new, b_all[nxt:nxt + take], dev_ptr=ptr, ld=D, parts=parts)
+                    for q, sl in enumerate(sl_new):
+                        owner[sl], warm[sl] = nxt + q, Yhat is not None
+                    nxt += take
+                    free = free[take:]
+                if retry and free:
+                    r_take = min(len(free), len(retry))
+                    mems, retry = retry[:r_take], retry[r_take:]
+                    F.refill(free[:r_take], b_all[mems])
+                    for sl, mem in zip(free[:r_take], mems):
+                        owner[sl], warm[sl] = mem, False
+                if all(o is None for o in owner) and nxt >= N and not retry:
+                    break
+            torch.cuda.synchronize()
+            seconds = time.perf_counter() - t0
+        return {"iters": iters, "converged": conv, "seconds": seconds}
+
+    def compare_stream(self, thetas, eps=1e-4, max_iter=100_000, parts=("both",), projection=False,
+                       chunk=50):
+        """Cold and learned starts of the same members through the same
+        streaming driver and slots (see solve_stream).  Variants: "cold", one
+        per entry of parts ("both", "primal" or "dual" halves of the
+        prediction) and, with projection=True, "projection": the cold
+        solution projected on the PCA basis (what a perfect network could
+        give with this basis).  A variant's seconds include its prediction
+        time (reported apart as "predict_seconds")."""
+        torch = self.torch
+        N = len(thetas)
+        b_all = np.ascontiguousarray(self.fam.b_many(thetas))
+        keep = torch.empty((N, self.D), dtype=torch.float32, device="cuda") if projection else None
+        out = {"cold": self.solve_stream(b_all, eps=eps, max_iter=max_iter, chunk=chunk, keep=keep)}
+        self.log(f"stream cold: {out['cold']['seconds']:.2f} s, median {int(np.median(out['cold']['iters']))}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Yhat = self.predict(thetas)
+        torch.cuda.synchronize()
+        t_pred = time.perf_counter() - t0
+        for p in parts:
+            r = self.solve_stream(b_all, Yhat=Yhat, parts=p, eps=eps, max_iter=max_iter, chunk=chunk)
+            r["seconds"] += t_pred
+            out[p] = r
+            self.log(f"stream {p}: {r['seconds']:.2f} s, median {int(np.median(r['iters']))}")
+        del Yhat
+        if projection:
+            mb = learn.gemm(self.mean.reshape(1, -1).contiguous(), self.basis, transB=True)
+            neg_mb = torch.from_numpy(-mb.cpu().numpy().reshape(-1)).cuda()
+            coef = learn.gemm(keep, self.basis, transB=True)
+            learn.add_row_vector(coef, neg_mb)
+            Yp = learn.gemm(coef, self.basis)
+            learn.add_row_vector(Yp, self.mean)
+            out["projection"] = self.solve_stream(b_all, Yhat=Yp, eps=eps, max_iter=max_iter, chunk=chunk)
+            self.log(f"stream projection: median {int(np.median(out['projection']['iters']))}")
+        out["predict_seconds"] = t_pred
+        return out
+
     def _solve_group(self, F, b, stats, g0, fallback_b=None):
         """Iterate the family solver to its stop; record iterations and
         convergence into stats[...][g0:g0+nb]; a member left unconverged is

@@ -112,3 +112,123 @@ def test_mixed_family_reaches_optimum(small_family):
         ro = oracle.Oracle.from_instance(insts[l]).solve(1e-5, check_every=50, max_iter=400_000)
         assert res[l]["kkt"] <= 1e-4
         assert abs(res[l]["pobj"] - ro["pobj"]) <= 2e-3 * (1 + abs(ro["pobj"]))
+
+
+def _fam(fam, B=64, **kw):
+    return Family(fam.m, fam.n, fam.row_ptr, fam.col_idx, fam.val, fam.c, B=B, **kw)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_refilled_member_equals_a_fresh_run(small_family, precision):
+    """A member that enters a stopped slot mid-run (family_refill) follows
+    bitwise the trajectory it has alone in a fresh family: same stopping
+    iteration, residuals and iterates, whatever its slot and start time."""
+    fam = small_family
+    first = [fam.instance(fam.theta(3000 + i, p=8)) for i in range(6)]
+    late = [fam.instance(fam.theta(3100 + i, p=8)) for i in range(4)]
+    kw = dict(precision=precision, eps=1e-4, check_every=10, max_iter=20_000)
+    with _fam(fam, **kw) as F:
+        F.set_rhs(np.stack([i["b"] for i in first]))
+        owner = list(range(6))          # member index per slot (late members are 100 + q)
+        queue = list(range(4))
+        res_late = {}
+        sol_late = {}
+        while True:
+            active = F.iterate(50)
+            res = F.residuals()
+            stopped = [sl for sl in range(6) if res[sl]["status"] != "running" and owner[sl] is not None]
+            for sl in stopped:
+                if owner[sl] >= 100:
+                    res_late[owner[sl] - 100] = res[sl]
+                    sol_late[owner[sl] - 100] = {k: v[sl].copy() for k, v in F.solution().items()}
+                owner[sl] = None
+            take = [sl for sl in stopped][: len(queue)]
+            if take:
+                qs = [queue.pop(0) for _ in take]
+                say(f"{precision}: refill slots {take} with late members {qs}")
+                F.refill(take, np.stack([late[q]["b"] for q in qs]))
+                for sl, q in zip(take, qs):
+                    owner[sl] = 100 + q
+                continue
+            if active == 0 and not queue:
+                break
+    assert len(res_late) == 4
+    for q in range(4):
+        with _fam(fam, **kw) as G:
+            G.set_rhs(late[q]["b"][None, :])
+            while G.iterate(2000):
+                pass
+            r = G.residuals()[0]
+            s = G.solution()
+        say(f"late member {q}: refilled iter {res_late[q]['iter']} fresh iter {r['iter']}")
+        assert res_late[q]["status"] == r["status"] == "converged"
+        for k in ("iter", "kkt", "r_prim", "r_dual", "r_gap", "pobj", "dobj", "res_ax_b"):
+            assert res_late[q][k] == r[k], k
+        for k in KEYS:
+            assert np.array_equal(sol_late[q][k], s[k][0]), k
+
+
+def test_refill_with_predicted_start_matches_set_start_predicted(small_family):
+    """The predicted start a refill gives a slot is the start
+    family_set_start_predicted gives a fresh family: bitwise the same member
+    after its 30 iterations (max_iter counts the member's own iterations)."""
+    import torch
+    fam = small_family
+    a, b = fam.instance(fam.theta(3200, p=8)), fam.instance(fam.theta(3201, p=8))
+    rng = np.random.default_rng(8)
+    D = fam.n + fam.m
+    xl = torch.from_numpy(rng.standard_normal((1, D)).astype(np.float32)).cuda()
+    kw = dict(precision="fp64", eps=0.0, check_every=10, max_iter=30)
+    with _fam(fam, **kw) as F:
+        F.set_rhs(np.stack([a["b"], a["b"]]))
+        assert F.iterate(100) == 0                   # both stop at max_iter 30
+        F.refill([1], b["b"][None, :], dev_ptr=xl.data_ptr(), ld=D)
+        assert F.iterate(100) == 0
+        rr = F.residuals()[1]
+        sr = {k: v[1] for k, v in F.solution().items()}
+    with _fam(fam, **kw) as G:
+        G.set_rhs(b["b"][None, :])
+        G.set_start_predicted(xl.data_ptr(), D, "both")
+        assert G.iterate(100) == 0
+        rg = G.residuals()[0]
+        sg = {k: v[0] for k, v in G.solution().items()}
+    assert rr["status"] == rg["status"] == "max_iter" and rr["iter"] == rg["iter"] == 30
+    for k in ("kkt", "pobj", "dobj", "res_ax_b"):
+        assert rr[k] == rg[k], k
+    for k in KEYS:
+        assert np.array_equal(sr[k], sg[k]), k
+
+
+def test_refilled_fp64_member_matches_oracle(small_family):
+    fam = small_family
+    a, b = fam.instance(fam.theta(3300, p=8)), fam.instance(fam.theta(3301, p=8))
+    with _fam(fam, precision="fp64", eps=0.0, check_every=10, max_iter=200) as F:
+        F.set_rhs(np.stack([a["b"], a["b"], a["b"]]))
+        assert F.iterate(1000) == 0
+        F.refill([2], b["b"][None, :])
+        assert F.iterate(1000) == 0
+        res = F.residuals()
+        s = {k: v[2] for k, v in F.solution().items()}
+    o = oracle.Oracle.from_instance(b)
+    o.iterate(200)
+    st = o.state()
+    errs = {k: rel(s[k], st[k]) for k in KEYS}
+    say(f"refilled member vs oracle after 200: {errs}")
+    assert max(errs.values()) <= 1e-9
+    assert res[2]["iter"] == 200 and res[0]["iter"] == 200
+
+
+def test_refill_rejects_running_and_repeated_slots(small_family):
+    fam = small_family
+    a = fam.instance(fam.theta(3400, p=8))
+    with _fam(fam, precision="fp64", eps=0.0, check_every=10, max_iter=20) as F:
+        F.set_rhs(np.stack([a["b"]] * 3))
+        with pytest.raises(Exception):
+            F.refill([0], a["b"][None, :])                 # slot 0 still running
+        F.iterate(100)
+        with pytest.raises(Exception):
+            F.refill([1, 1], np.stack([a["b"]] * 2))       # the same slot twice
+        with pytest.raises(Exception):
+            F.refill([3], a["b"][None, :])                 # beyond the current members
+        F.refill([0, 2], np.stack([a["b"]] * 2))
+        assert F.iterate(5) == 2
