@@ -124,6 +124,16 @@ typedef struct {
     double eps_gap;       /* bound on |c'x + b'lambda| of UV_CRIT_POGS, and
                              an extra condition of UV_CRIT_INF when > 0
                              (0 = none); >= 0 */
+    int32_t resident;     /* 0 = automatic: a problem whose cones all have
+                             size 1, with m, n < 65536 and small enough for
+                             one CU's LDS (about 150 KiB: x, z, u, delta,
+                             lambda and both copies of A with 16-bit row and
+                             column numbers) runs on the resident path, one
+                             workgroup iterating in LDS with the checks in
+                             the same launch, unless lanes_*, unroll_*,
+                             slabs_* or slab_kernel force a shape of the
+                             sweep kernels; 1 = never; 2 = required
+                             (UV_EINVAL at create when it does not apply) */
 } uv_opts;
 
 /* Stopping tests (Section V): UV_CRIT_KKT stops when kkt <= eps_kkt (the
@@ -225,6 +235,17 @@ void solver_destroy(uv_solver *s);
 /* Static string for a UV_E* code. */
 const char *solver_strerror(int code);
 
+/* One call: solver_create, iterations from the zero start until the
+ * stopping test holds at a check or `iters` iterations (or max_iter) are
+ * done, solver_solution (any output may be NULL) and solver_residuals of the
+ * final iterate into *r (may be NULL), then solver_destroy.  Returns what
+ * solver_create or solver_iterate returned (UV_ENUMERIC with the outputs
+ * filled on a numeric stop), else the first failing call's code. */
+int solver_solve(const uv_csr *A, const double *b, const double *c,
+                 const uv_cones *K, const uv_opts *opts, int64_t iters,
+                 double *x, double *z, double *lambda, double *delta,
+                 uv_residuals *r);
+
 /* Measurement: runs `iters` iterations (no residual checks), timing every
  * kernel launch with HIP events on the solver's stream, and returns the
  * average duration in milliseconds of the column pass (A'u, x-step,
@@ -235,7 +256,10 @@ int solver_time_kernels(uv_solver *s, int32_t iters, double *ms_col,
 /* The resolved launch shape: shape[0] lanes per row and shape[1] gathers in
  * flight per lane in the row pass, shape[2], shape[3] the same for the
  * column pass, shape[4], shape[5] the XCD slab counts of the row and column
- * passes (shape holds 6 entries). */
+ * passes, shape[6] 1 on the resident path (shape holds 7 entries).  On the
+ * resident path solver_iterate runs the resident kernel; the other calls
+ * (residual queries between checks, resume, solver_time_kernels) use the
+ * sweep kernels on the same state. */
 int solver_launch_shape(const uv_solver *s, int32_t *shape);
 
 /* ------------------------------------------------------------------------

@@ -551,6 +551,61 @@ k_res_col_slab(int n, const double *__restrict__ P, const double *__restrict__ c
     uv::block_sum_max<3, 2>(acc, mx, part + blockIdx.x, pstride);
 }
 
+// The stopping test of a check from its sums and maxima: s[0] ||Az-b||^2,
+// s[1] b'lambda, s[2] ||Ax-b||^2, s[3] ||A'lambda+c-delta||^2, s[4] c'z,
+// s[5] c'x, s[6] ||Az-b||_inf, s[7] ||Az||_inf, s[8]
+// ||A'lambda+c-delta||_inf, s[9] ||A'lambda||_inf; nrm: ||b||^2, ||c||^2,
+// ||b||_inf, ||c||_inf; it: the iteration count they belong to.  Records
+// the residuals in st and, with decide, the status and the stop flag;
+// returns whether the run stops here.  One thread.
+__device__ bool finish_check(const double (&s)[10], const double (&nrm)[4], long long it, double eps,
+                             double eps_abs, double eps_gap, int crit, int decide, DevStatus *st)
+{
+    const double rp = sqrt(s[0]) / (1.0 + sqrt(nrm[0]));
+    const double rd = sqrt(s[3]) / (1.0 + sqrt(nrm[1]));
+    const double cz = s[4], bl = s[1], cx = s[5];
+    const double rg = fabs(cz + bl) / (1.0 + fabs(cz) + fabs(bl));
+    const double kkt = uv::kkt_of(rp, rd, rg);
+    const double res_ax_b = sqrt(s[2]), gap_x = fabs(cx + bl);
+    st->r_prim = rp;
+    st->r_dual = rd;
+    st->r_gap = rg;
+    st->kkt = kkt;
+    st->pobj = cz;
+    st->dobj = -bl;
+    st->res_ax_b = res_ax_b;
+    st->prim_inf = s[6];
+    st->dual_inf = s[8];
+    const double scale_p = fmax(s[7], nrm[2]), scale_d = fmax(s[9], nrm[3]);
+    st->scale_p = scale_p;
+    st->scale_d = scale_d;
+    st->pobj_x = cx;
+    st->gap_x = gap_x;
+    st->check_iter = it;
+    if (!decide) return false;
+    // crit 1 adds the gap condition when eps_gap > 0; crit 2 is the POGS
+    // form (strict inequalities as printed)
+    bool conv;
+    if (crit == 1)
+        conv = s[6] <= eps_abs + eps * scale_p && s[8] <= eps_abs + eps * scale_d &&
+               (eps_gap <= 0.0 || gap_x < eps_gap);
+    else if (crit == 2)
+        conv = res_ax_b < eps_abs && gap_x < eps_gap;
+    else
+        conv = kkt <= eps;
+    if (!isfinite(kkt)) {
+        st->status = UV_STATUS_NUMERIC;
+        st->done = 1;
+        return true;
+    }
+    if (conv) {
+        st->status = UV_STATUS_CONVERGED;
+        st->done = 1;
+        return true;
+    }
+    return false;
+}
+
 // Adds the partials in a fixed order (eight independent loads in flight
 // per thread), forms the residuals and decides whether to stop.  Partials
 // are stored component-major: prow[k * nrow + block], rows: sums of
@@ -605,44 +660,272 @@ k_finalize(int nrow, const double *__restrict__ prow, int ncol, const double *__
     double s[10];
     uv::block_sum_max<6, 4>(v, w, s, 1);
     if (threadIdx.x != 0) return;
-    const double rp = sqrt(s[0]) / (1.0 + sqrt(st->bnorm2));
-    const double rd = sqrt(s[3]) / (1.0 + sqrt(st->cnorm2));
-    const double cz = s[4], bl = s[1], cx = s[5];
-    const double rg = fabs(cz + bl) / (1.0 + fabs(cz) + fabs(bl));
-    const double kkt = uv::kkt_of(rp, rd, rg);
-    const double res_ax_b = sqrt(s[2]), gap_x = fabs(cx + bl);
-    st->r_prim = rp;
-    st->r_dual = rd;
-    st->r_gap = rg;
-    st->kkt = kkt;
-    st->pobj = cz;
-    st->dobj = -bl;
-    st->res_ax_b = res_ax_b;
-    st->prim_inf = s[6];
-    st->dual_inf = s[8];
-    st->scale_p = fmax(s[7], st->binf);
-    st->scale_d = fmax(s[9], st->cinf);
-    st->pobj_x = cx;
-    st->gap_x = gap_x;
-    st->check_iter = st->iter;
-    if (!decide) return;
-    // crit 1 adds the gap condition when eps_gap > 0; crit 2 is the POGS
-    // form (strict inequalities as printed)
-    bool conv;
-    if (crit == 1)
-        conv = s[6] <= eps_abs + eps * st->scale_p && s[8] <= eps_abs + eps * st->scale_d &&
-               (eps_gap <= 0.0 || gap_x < eps_gap);
-    else if (crit == 2)
-        conv = res_ax_b < eps_abs && gap_x < eps_gap;
-    else
-        conv = kkt <= eps;
-    if (!isfinite(kkt)) {
-        st->status = UV_STATUS_NUMERIC;
-        st->done = 1;
-    } else if (conv) {
-        st->status = UV_STATUS_CONVERGED;
-        st->done = 1;
+    const double nrm[4] = {st->bnorm2, st->cnorm2, st->binf, st->cinf};
+    finish_check(s, nrm, st->iter, eps, eps_abs, eps_gap, crit, decide, st);
+}
+
+// ---------------------------------------------------------------------------
+// Resident path: a small orthant problem held whole in one workgroup's LDS
+// ---------------------------------------------------------------------------
+
+// Byte offsets in the dynamic LDS of k_resident: FP64 delta and lambda, the
+// sweep-type iterates x, z, u, the CSC and CSR values, the offsets and the
+// 16-bit row and column numbers (m, n < 65536).
+struct ResLayout {
+    int d, l, x, z, u, vc, va, cp, rp, ri, ci;
+    int bytes;
+};
+
+constexpr int kResThreads = 1024;
+constexpr int kResLdsMax = 160 * 1024 - 2048;  // a CU's LDS less the kernel's static slots
+
+template <typename T>
+ResLayout resident_layout(int m, int n, int nnz)
+{
+    ResLayout L{};
+    size_t o = 0;
+    auto put = [&](int &field, size_t bytes) {
+        field = (int)o;
+        o = (o + bytes + 15) / 16 * 16;
+    };
+    put(L.d, 8 * (size_t)n);
+    put(L.l, 8 * (size_t)m);
+    put(L.x, sizeof(T) * (size_t)n);
+    put(L.z, sizeof(T) * (size_t)n);
+    put(L.u, sizeof(T) * (size_t)m);
+    put(L.vc, sizeof(T) * (size_t)nnz);
+    put(L.va, sizeof(T) * (size_t)nnz);
+    put(L.cp, 4 * ((size_t)n + 1));
+    put(L.rp, 4 * ((size_t)m + 1));
+    put(L.ri, 2 * (size_t)nnz);
+    put(L.ci, 2 * (size_t)nnz);
+    L.bytes = o > (size_t)INT32_MAX ? INT32_MAX : (int)o;
+    return L;
+}
+
+// Sum over the entries k0..k1-1 of a row or column held in LDS, split over
+// the L lanes of a group (this lane: `lane`), four entries in flight per
+// lane, then across the group (the total in every lane).  A fixed order.
+template <typename T, typename TV, typename G>
+__device__ __forceinline__ T lds_dot(int k0, int k1, int lane, int L, const unsigned short *idx, const TV *val,
+                                     const G *vec)
+{
+    T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    int k = k0 + lane;
+    for (; k + 3 * L < k1; k += 4 * L) {
+        const int j0 = idx[k], j1 = idx[k + L], j2 = idx[k + 2 * L], j3 = idx[k + 3 * L];
+        a0 += (T)val[k] * (T)vec[j0];
+        a1 += (T)val[k + L] * (T)vec[j1];
+        a2 += (T)val[k + 2 * L] * (T)vec[j2];
+        a3 += (T)val[k + 3 * L] * (T)vec[j3];
     }
+    for (; k < k1; k += L) a0 += (T)val[k] * (T)vec[idx[k]];
+    T a = (a0 + a1) + (a2 + a3);
+    for (int off = L >> 1; off > 0; off >>= 1) a += __shfl_xor(a, off, L);
+    return a;
+}
+
+// Two sums of lds_dot over the same entries (A z and A x of a check row):
+// the indices and values are read once.
+template <typename TV, typename G>
+__device__ __forceinline__ void lds_dot2(int k0, int k1, int lane, int L, const unsigned short *idx, const TV *val,
+                                         const G *v1, const G *v2, double &s1, double &s2)
+{
+    double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
+    int k = k0 + lane;
+    for (; k + L < k1; k += 2 * L) {
+        const int j0 = idx[k], j1 = idx[k + L];
+        const double w0 = (double)val[k], w1 = (double)val[k + L];
+        a0 += w0 * (double)v1[j0];
+        b0 += w0 * (double)v2[j0];
+        a1 += w1 * (double)v1[j1];
+        b1 += w1 * (double)v2[j1];
+    }
+    for (; k < k1; k += L) {
+        const int j = idx[k];
+        const double w = (double)val[k];
+        a0 += w * (double)v1[j];
+        b0 += w * (double)v2[j];
+    }
+    s1 = a0 + a1;
+    s2 = b0 + b1;
+    for (int off = L >> 1; off > 0; off >>= 1) {
+        s1 += __shfl_xor(s1, off, L);
+        s2 += __shfl_xor(s2, off, L);
+    }
+}
+
+// The FP64 residual check of the resident kernel (every thread calls it):
+// per-thread sums over its rows and columns, then a fixed-order workgroup
+// reduction; thread 0 gets the sums and maxima of finish_check in sv.
+template <typename T>
+__device__ __forceinline__ void res_check(int m, int n, int Lr, int Lc, const int *rps, const unsigned short *cis,
+                                          const int *cps, const unsigned short *ris, const double *cva,
+                                          const double *cvc, const T *xs, const T *zs, const double *ds,
+                                          const double *ls, const double *__restrict__ b64,
+                                          const double *__restrict__ c64, double (*red)[kResThreads / 64],
+                                          double (&sv)[10])
+{
+    constexpr int NT = kResThreads;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int gc = tid / Lc, lc = tid % Lc, gr = tid / Lr, lr = tid % Lr;
+    double v[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = gr; i < m; i += NT / Lr) {
+        double qz, qx;
+        lds_dot2(rps[i], rps[i + 1], lr, Lr, cis, cva, zs, xs, qz, qx);
+        if (lr == 0) {
+            const double bi = b64[i], rz = qz - bi, rx = qx - bi;
+            v[0] += rz * rz;
+            v[1] += bi * ls[i];
+            v[2] += rx * rx;
+            v[6] = fmax(v[6], fabs(rz));
+            v[7] = fmax(v[7], fabs(qz));
+        }
+    }
+    for (int j = gc; j < n; j += NT / Lc) {
+        const double a = lds_dot<double>(cps[j], cps[j + 1], lc, Lc, ris, cvc, ls);
+        if (lc == 0) {
+            const double cj = c64[j], r = a + cj - ds[j];
+            v[3] += r * r;
+            v[4] += cj * (double)zs[j];
+            v[5] += cj * (double)xs[j];
+            v[8] = fmax(v[8], fabs(r));
+            v[9] = fmax(v[9], fabs(a));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = uv::group_sum<64>(v[k]);
+#pragma unroll
+    for (int k = 6; k < 10; ++k)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] = fmax(v[k], __shfl_xor(v[k], off, 64));
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 10; ++k) red[k][w] = v[k];
+    __syncthreads();
+    if (tid == 0) {
+        for (int k = 0; k < 10; ++k) {
+            double a = red[k][0];
+            for (int q = 1; q < NT / 64; ++q) a = k < 6 ? a + red[k][q] : fmax(a, red[k][q]);
+            sv[k] = a;
+        }
+    }
+}
+
+// Up to `iters` iterations of a small orthant problem in one workgroup: the
+// state and both copies of A are staged in LDS once, then every iteration
+// runs the column pass (Lc lanes per column: A'u from LDS, then the x-step,
+// projection and delta update), a barrier, the row pass (Lr lanes per row:
+// A x, the lambda and u updates) and a barrier, with the FP64 residual
+// check of the other paths every check_every iterations (FP64 values of A:
+// the staged ones in FP64, from global memory in the mixed form; then a
+// fixed-order workgroup reduction) and its stop decision; the state goes
+// back to global memory at the end.  Same per-entry arithmetic as the sweep
+// kernels.  eval_only: no iteration, the residuals of the current state are
+// recorded without a stop decision (a residual query).
+template <typename T>
+__global__ void __launch_bounds__(kResThreads)
+k_resident(int m, int n, ResLayout L, int Lr, int Lc, const int *__restrict__ rp, const int *__restrict__ ci,
+           const T *__restrict__ va, const int *__restrict__ cp, const int *__restrict__ ri,
+           const T *__restrict__ vc, const double *__restrict__ va64, const double *__restrict__ vc64,
+           const T *__restrict__ b, const double *__restrict__ b64, const T *__restrict__ c,
+           const double *__restrict__ c64, const T *__restrict__ fu, T *__restrict__ x, T *__restrict__ z,
+           T *__restrict__ u, double *__restrict__ lam, double *__restrict__ delta, double mu, long long iters,
+           int eval_only, int check_every, double eps, double eps_abs, double eps_gap, int crit, DevStatus *st)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ double red[10][kResThreads / 64];
+    __shared__ int stop;
+    if (!eval_only && st->done) return;
+    constexpr int NT = kResThreads;
+    const int tid = threadIdx.x;
+    double *ds = (double *)(lds_raw + L.d), *ls = (double *)(lds_raw + L.l);
+    T *xs = (T *)(lds_raw + L.x), *zs = (T *)(lds_raw + L.z), *us = (T *)(lds_raw + L.u);
+    T *vcs = (T *)(lds_raw + L.vc), *vas = (T *)(lds_raw + L.va);
+    int *cps = (int *)(lds_raw + L.cp), *rps = (int *)(lds_raw + L.rp);
+    unsigned short *ris = (unsigned short *)(lds_raw + L.ri), *cis = (unsigned short *)(lds_raw + L.ci);
+    const int nnz = rp[m];
+    for (int j = tid; j < n; j += NT) {
+        xs[j] = x[j];
+        zs[j] = z[j];
+        ds[j] = delta[j];
+    }
+    for (int i = tid; i < m; i += NT) {
+        us[i] = u[i];
+        ls[i] = lam[i];
+    }
+    for (int j = tid; j <= n; j += NT) cps[j] = cp[j];
+    for (int i = tid; i <= m; i += NT) rps[i] = rp[i];
+    for (int k = tid; k < nnz; k += NT) {
+        ris[k] = (unsigned short)ri[k];
+        vcs[k] = vc[k];
+        cis[k] = (unsigned short)ci[k];
+        vas[k] = va[k];
+    }
+    if (tid == 0) stop = 0;
+    __syncthreads();
+    const long long it0 = st->iter;
+    const double nrm[4] = {st->bnorm2, st->cnorm2, st->binf, st->cinf};
+    // FP64 values of A for the checks: the staged ones in FP64, global ones in the mixed form
+    const double *cva = sizeof(T) == sizeof(double) ? (const double *)vas : va64;
+    const double *cvc = sizeof(T) == sizeof(double) ? (const double *)vcs : vc64;
+    if (eval_only) {
+        double sv[10];
+        res_check<T>(m, n, Lr, Lc, rps, cis, cps, ris, cva, cvc, xs, zs, ds, ls, b64, c64, red, sv);
+        if (tid == 0) finish_check(sv, nrm, it0, eps, eps_abs, eps_gap, crit, 0, st);
+        return;
+    }
+    const double inv_mu = 1.0 / mu;
+    const int gc = tid / Lc, lc = tid % Lc, gr = tid / Lr, lr = tid % Lr;
+    long long done = 0;
+    for (long long t = 0; t < iters; ++t) {
+        for (int j = gc; j < n; j += NT / Lc) {
+            const int k0 = cps[j], k1 = cps[j + 1];
+            const T a = lds_dot<T>(k0, k1, lc, Lc, ris, vcs, us);
+            if (lc == 0) {
+                const double d = ds[j];
+                const T dm = (T)(d * inv_mu);
+                const T xn = x_step<T>(k1 - k0, xs[j], zs[j], a, dm, c[j], inv_mu);
+                const T v = xn - dm;
+                const T zn = v > (T)0 ? v : (T)0;
+                xs[j] = xn;
+                zs[j] = zn;
+                ds[j] = d + mu * ((double)zn - (double)xn);
+            }
+        }
+        __syncthreads();
+        for (int i = gr; i < m; i += NT / Lr) {
+            const T q = lds_dot<T>(rps[i], rps[i + 1], lr, Lr, cis, vas, xs);
+            if (lr == 0) {
+                const T e = fu[i] * (b[i] - q);
+                const double li = ls[i] - mu * (double)e;
+                ls[i] = li;
+                us[i] = (T)((double)e - li * inv_mu);
+            }
+        }
+        __syncthreads();
+        done = t + 1;
+        const long long itn = it0 + done;
+        if (itn % check_every != 0) continue;
+        double sv[10];
+        res_check<T>(m, n, Lr, Lc, rps, cis, cps, ris, cva, cvc, xs, zs, ds, ls, b64, c64, red, sv);
+        if (tid == 0) {
+            st->iter = itn;
+            stop = finish_check(sv, nrm, itn, eps, eps_abs, eps_gap, crit, 1, st) ? 1 : 0;
+        }
+        __syncthreads();
+        if (stop) break;
+    }
+    for (int j = tid; j < n; j += NT) {
+        x[j] = xs[j];
+        z[j] = zs[j];
+        delta[j] = ds[j];
+    }
+    for (int i = tid; i < m; i += NT) {
+        u[i] = us[i];
+        lam[i] = ls[i];
+    }
+    if (tid == 0) st->iter = it0 + done;
 }
 
 }  // namespace
@@ -688,6 +971,9 @@ struct uv_solver {
     double *sva64 = nullptr, *svc64 = nullptr;  // FP64 values of the slab copies
     double *P_res = nullptr;    // FP64 slab partials of the mixed form's checks
     int nblk_row_fused = 0;     // row-residual partial blocks written by the check row pass
+    bool resident = false;      // iterate with k_resident (the whole problem in one workgroup's LDS)
+    ResLayout rlay{};
+    int res_lr = 1, res_lc = 1;  // lanes per row and per column of k_resident
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int64_t host_iter = 0;
@@ -1012,6 +1298,79 @@ int build_graph(uv_solver *s)
     return UV_OK;
 }
 
+// Device operands of k_resident.
+struct ResArgs {
+    int m, n;
+    ResLayout L;
+    int Lr, Lc;
+    const int *rp, *ci, *cp, *ri;
+    const void *va, *vc, *b, *c, *fu;  // sweep type
+    const double *va64, *vc64, *b64, *c64;
+    void *x, *z, *u;                   // sweep type
+    double *lam, *delta;
+    DevStatus *st;
+    bool mixed;
+    double mu, eps, eps_abs, eps_gap;
+    int check_every, crit;
+};
+
+// Up to `iters` iterations on the resident path in launches of at most 2^16
+// iterations (a launch returns at once once a check has stopped the run),
+// or with eval_only one launch that records the residuals of the state.
+void resident_launch(const ResArgs &a, hipStream_t st, int64_t iters, bool eval_only)
+{
+    constexpr int64_t kChunk = (int64_t)1 << 16;
+    int64_t left = eval_only ? 1 : iters;
+    while (left > 0) {
+        const long long q = eval_only ? 0 : (long long)std::min(left, kChunk);
+#define UV_RES_ARGS(T)                                                                                         \
+    a.m, a.n, a.L, a.Lr, a.Lc, a.rp, a.ci, (const T *)a.va, a.cp, a.ri, (const T *)a.vc, a.va64, a.vc64,         \
+        (const T *)a.b, a.b64, (const T *)a.c, a.c64, (const T *)a.fu, (T *)a.x, (T *)a.z, (T *)a.u, a.lam,        \
+        a.delta, a.mu, q, eval_only ? 1 : 0, a.check_every, a.eps, a.eps_abs, a.eps_gap, a.crit, a.st
+        if (a.mixed) k_resident<float><<<1, kResThreads, a.L.bytes, st>>>(UV_RES_ARGS(float));
+        else k_resident<double><<<1, kResThreads, a.L.bytes, st>>>(UV_RES_ARGS(double));
+#undef UV_RES_ARGS
+        left -= eval_only ? 1 : kChunk;
+    }
+}
+
+ResArgs res_args(const uv_solver *s)
+{
+    ResArgs a{};
+    a.m = s->m;
+    a.n = s->n;
+    a.L = s->rlay;
+    a.Lr = s->res_lr;
+    a.Lc = s->res_lc;
+    a.rp = s->rp;
+    a.ci = s->ci;
+    a.cp = s->cp;
+    a.ri = s->ri;
+    a.va = s->va;
+    a.vc = s->vc;
+    a.b = s->b;
+    a.c = s->c;
+    a.fu = s->fu;
+    a.va64 = s->va64;
+    a.vc64 = s->vc64;
+    a.b64 = s->b64;
+    a.c64 = s->c64;
+    a.x = s->x;
+    a.z = s->z;
+    a.u = s->u;
+    a.lam = s->lam;
+    a.delta = s->delta;
+    a.st = s->st;
+    a.mixed = s->o.precision == UV_MIXED;
+    a.mu = s->o.mu;
+    a.eps = s->o.eps_kkt;
+    a.eps_abs = s->o.eps_abs;
+    a.eps_gap = s->o.eps_gap;
+    a.check_every = s->o.check_every;
+    a.crit = s->o.criterion;
+    return a;
+}
+
 int sync_status(uv_solver *s)
 {
     UV_TRY(hipMemcpyAsync(s->st_host, s->st, sizeof(DevStatus), hipMemcpyDeviceToHost, s->stream));
@@ -1032,6 +1391,7 @@ int validate(const uv_csr *A, const double *b, const double *c, const uv_cones *
     if (!unroll_ok(o->unroll_row) || !unroll_ok(o->unroll_col)) return UV_EINVAL;
     if (!slabs_ok(o->slabs_row) || !slabs_ok(o->slabs_col)) return UV_EINVAL;
     if (o->slab_kernel < 0 || o->slab_kernel > 3) return UV_EINVAL;
+    if (o->resident < 0 || o->resident > 2) return UV_EINVAL;
     if (A->nnz > 0 && (!A->col_idx || !A->val)) return UV_EINVAL;
     if (!A->row_ptr) return UV_EINVAL;
     if (A->nnz >= ((int64_t)1 << 31)) return UV_ETOOBIG;
@@ -1257,6 +1617,7 @@ void uv_default_opts(uv_opts *o)
     o->eps_abs = 0.0;
     o->slab_kernel = 0;
     o->eps_gap = 0.0;
+    o->resident = 0;
 }
 
 const char *solver_strerror(int code)
@@ -1320,9 +1681,44 @@ int solver_create(const uv_csr *A, const double *b, const double *c, const uv_co
     s->E_col = o.unroll_col ? o.unroll_col : 2;
     s->chunked = o.slab_kernel != 2;
     s->batch8 = o.slab_kernel != 3;
+    {
+        // the resident path when every cone has size 1, the row and column
+        // numbers fit 16 bits and the whole problem fits one CU's LDS
+        const bool mixed = o.precision == UV_MIXED;
+        s->rlay = mixed ? resident_layout<float>(A->m, A->n, (int)A->nnz)
+                        : resident_layout<double>(A->m, A->n, (int)A->nnz);
+        const bool fits = K->n_soc == 0 && A->m < 65536 && A->n < 65536 && s->rlay.bytes <= kResLdsMax;
+        if (o.resident == 2 && !fits) {
+            solver_destroy(s);
+            return UV_EINVAL;
+        }
+        // automatic only when no launch shape of the sweep kernels is forced
+        const bool forced = o.lanes_row || o.lanes_col || o.unroll_row || o.unroll_col || o.slabs_row ||
+                            o.slabs_col || o.slab_kernel;
+        s->resident = fits && (o.resident == 2 || (o.resident == 0 && !forced));
+        // lanes per segment: the most (a power of two, at most 64) that
+        // keeps every segment of the pass on a lane group at once
+        auto lanes = [](int segs) {
+            int L = 1;
+            while (L < 64 && (int64_t)segs * L * 2 <= kResThreads) L <<= 1;
+            return L;
+        };
+        s->res_lr = lanes(A->m);
+        s->res_lc = lanes(A->n);
+        if (s->resident) {
+            const hipError_t e = mixed ? hipFuncSetAttribute((const void *)k_resident<float>,
+                                                             hipFuncAttributeMaxDynamicSharedMemorySize, kResLdsMax)
+                                       : hipFuncSetAttribute((const void *)k_resident<double>,
+                                                             hipFuncAttributeMaxDynamicSharedMemorySize, kResLdsMax);
+            if (e != hipSuccess) {
+                solver_destroy(s);
+                return UV_EHIP;
+            }
+        }
+    }
     rc = setup(s, A, b, c, K);
     if (rc == UV_OK) rc = solver_set_start(s, nullptr, nullptr, nullptr, nullptr);
-    if (rc == UV_OK && s->o.use_graph) rc = build_graph(s);
+    if (rc == UV_OK && s->o.use_graph && !s->resident) rc = build_graph(s);
     if (rc != UV_OK) {
         solver_destroy(s);
         return rc;
@@ -1400,6 +1796,10 @@ int solver_iterate(uv_solver *s, int64_t k, int32_t *done)
         int64_t it = s->host_iter, since = 0;
         const int ce = s->o.check_every;
         const int64_t look = 50 * (int64_t)ce;  // read the stop flag every 50 checks
+        if (s->resident && left > 0) {
+            resident_launch(res_args(s), s->stream, left, false);
+            left = 0;
+        }
         while (left > 0) {
             if (s->exec && it % ce == 0 && left >= ce) {
                 UV_TRY(hipGraphLaunch(s->exec, s->stream));
@@ -1439,7 +1839,8 @@ int solver_residuals(uv_solver *s, uv_residuals *r)
 {
     if (!s || !r) return UV_EINVAL;
     if (s->st_host->check_iter != s->st_host->iter) {
-        launch_residuals(s, s->stream, false, false);
+        if (s->resident) resident_launch(res_args(s), s->stream, 0, true);
+        else launch_residuals(s, s->stream, false, false);
         UV_TRY(hipGetLastError());
         int rc = sync_status(s);
         if (rc != UV_OK) return rc;
@@ -1484,6 +1885,24 @@ int solver_solution(uv_solver *s, double *x, double *z, double *lambda, double *
     if (delta) UV_TRY(hipMemcpyAsync(delta, s->delta, 8 * (size_t)s->n, hipMemcpyDeviceToHost, st));
     UV_TRY(hipStreamSynchronize(st));
     return UV_OK;
+}
+
+int solver_solve(const uv_csr *A, const double *b, const double *c, const uv_cones *K, const uv_opts *opts,
+                 int64_t iters, double *x, double *z, double *lambda, double *delta, uv_residuals *r)
+{
+    if (iters < 0) return UV_EINVAL;
+    uv_solver *s = nullptr;
+    int rc = solver_create(A, b, c, K, opts, &s);
+    if (rc != UV_OK) return rc;
+    int32_t done = 0;
+    rc = solver_iterate(s, iters, &done);
+    if (rc == UV_OK || rc == UV_ENUMERIC) {
+        int rc2 = solver_solution(s, x, z, lambda, delta);
+        if (rc2 == UV_OK && r) rc2 = solver_residuals(s, r);
+        if (rc2 != UV_OK) rc = rc2;
+    }
+    solver_destroy(s);
+    return rc;
 }
 
 int solver_time_kernels(uv_solver *s, int32_t iters, double *ms_col, double *ms_row)
@@ -1531,6 +1950,7 @@ int solver_launch_shape(const uv_solver *s, int32_t *shape)
     shape[3] = s->E_col;
     shape[4] = s->S_row;
     shape[5] = s->S_col;
+    shape[6] = s->resident ? 1 : 0;
     return UV_OK;
 }
 

@@ -39,7 +39,7 @@ class UvOpts(ctypes.Structure):
                 ("unroll_col", ctypes.c_int32), ("slabs_row", ctypes.c_int32),
                 ("slabs_col", ctypes.c_int32), ("criterion", ctypes.c_int32),
                 ("eps_abs", ctypes.c_double), ("slab_kernel", ctypes.c_int32),
-                ("eps_gap", ctypes.c_double)]
+                ("eps_gap", ctypes.c_double), ("resident", ctypes.c_int32)]
 
 
 class UvResiduals(ctypes.Structure):
@@ -90,6 +90,9 @@ def lib():
     L.solver_resume.restype = ctypes.c_int
     L.solver_iterate.argtypes = [P, i64, ctypes.POINTER(i32)]
     L.solver_iterate.restype = ctypes.c_int
+    L.solver_solve.argtypes = [ctypes.POINTER(UvCsr), P, P, ctypes.POINTER(UvCones), ctypes.POINTER(UvOpts),
+                               i64, P, P, P, P, ctypes.POINTER(UvResiduals)]
+    L.solver_solve.restype = ctypes.c_int
     L.solver_residuals.argtypes = [P, ctypes.POINTER(UvResiduals)]
     L.solver_residuals.restype = ctypes.c_int
     L.solver_solution.argtypes = [P, P, P, P, P]
@@ -147,6 +150,56 @@ def default_opts() -> UvOpts:
     return o
 
 
+def _problem(m, n, row_ptr, col_idx, val, b, c, n_orth, soc_sizes):
+    """ctypes views of a problem (the arrays are returned too, to keep them
+    alive while the library reads them)."""
+    rp, ci, va, nnz = _csr(m, row_ptr, col_idx, val)
+    sizes = np.ascontiguousarray(soc_sizes, dtype=np.int32)
+    csr = UvCsr(m, n, nnz, _ptr(rp), _ptr(ci), _ptr(va))
+    cones = UvCones(int(n_orth), int(sizes.size), _ptr(sizes) if sizes.size else None)
+    bb = _f64(b, m)
+    cc = _f64(c, n)
+    return (rp, ci, va, sizes), csr, cones, bb, cc
+
+
+def _opts(*, mu=1.0, precision="fp64", check_every=10, eps=1e-4, max_iter=0, lanes_row=0, lanes_col=0,
+          unroll_row=0, unroll_col=0, slabs_row=0, slabs_col=0, criterion="kkt", eps_abs=0.0, eps_gap=0.0,
+          slab_kernel="auto", resident="auto", use_graph=True, stream=None):
+    o = default_opts()
+    o.mu = float(mu)
+    o.precision = {"fp64": UV_FP64, "mixed": UV_MIXED}[precision]
+    o.check_every = int(check_every)
+    o.eps_kkt = float(eps)
+    o.max_iter = int(max_iter)
+    o.hip_stream = stream
+    o.lanes_row, o.lanes_col = int(lanes_row), int(lanes_col)
+    o.unroll_row, o.unroll_col = int(unroll_row), int(unroll_col)
+    o.slabs_row, o.slabs_col = int(slabs_row), int(slabs_col)
+    o.criterion = {"kkt": 0, "inf": 1, "pogs": 2}[criterion]
+    o.eps_gap = float(eps_gap)
+    o.resident = {"auto": 0, "never": 1, "required": 2}[resident]
+    o.slab_kernel = {"auto": 0, "chunked": 1, "lanes": 2, "chunked4": 3}[slab_kernel]
+    o.eps_abs = float(eps_abs)
+    o.use_graph = 1 if use_graph else 0
+    return o
+
+
+def solve(inst, iters, **kw):
+    """solver_solve on an instance dict: (return code, solution dict,
+    residuals dict).  Options as for Solver."""
+    m, n = int(inst["m"]), int(inst["n"])
+    keep, csr, cones, bb, cc = _problem(m, n, inst["row_ptr"], inst["col_idx"], inst["val"], inst["b"],
+                                        inst["c"], inst["n_orth"], inst["soc_sizes"])
+    o = _opts(**kw)
+    x, z, d, lam = np.empty(n), np.empty(n), np.empty(n), np.empty(m)
+    r = UvResiduals()
+    rc = lib().solver_solve(ctypes.byref(csr), _ptr(bb), _ptr(cc), ctypes.byref(cones), ctypes.byref(o),
+                            ctypes.c_int64(int(iters)), _ptr(x), _ptr(z), _ptr(lam), _ptr(d), ctypes.byref(r))
+    res = {k: getattr(r, k) for k, _ in UvResiduals._fields_}
+    res["status"] = STATUS.get(res["status"], res["status"])
+    return rc, {"x": x, "z": z, "delta": d, "lambda": lam}, res
+
+
 class Solver:
     """One problem on the GPU: ``min c'x s.t. A x = b, x in K``.
 
@@ -158,32 +211,18 @@ class Solver:
     def __init__(self, m, n, row_ptr, col_idx, val, b, c, n_orth, soc_sizes=(), *,
                  mu=1.0, precision="fp64", check_every=10, eps=1e-4, max_iter=0,
                  lanes_row=0, lanes_col=0, unroll_row=0, unroll_col=0, slabs_row=0, slabs_col=0,
-                 criterion="kkt", eps_abs=0.0, eps_gap=0.0, slab_kernel="auto", use_graph=True, stream=None):
+                 criterion="kkt", eps_abs=0.0, eps_gap=0.0, slab_kernel="auto", resident="auto", use_graph=True,
+                 stream=None):
         L = lib()
         self.m, self.n = int(m), int(n)
-        rp, ci, va, nnz = _csr(self.m, row_ptr, col_idx, val)
-        sizes = np.ascontiguousarray(soc_sizes, dtype=np.int32)
-        csr = UvCsr(self.m, self.n, nnz, _ptr(rp), _ptr(ci), _ptr(va))
-        cones = UvCones(int(n_orth), int(sizes.size), _ptr(sizes) if sizes.size else None)
-        o = default_opts()
-        o.mu = float(mu)
-        o.precision = {"fp64": UV_FP64, "mixed": UV_MIXED}[precision]
-        o.check_every = int(check_every)
-        o.eps_kkt = float(eps)
-        o.max_iter = int(max_iter)
-        o.hip_stream = stream
-        o.lanes_row, o.lanes_col = int(lanes_row), int(lanes_col)
-        o.unroll_row, o.unroll_col = int(unroll_row), int(unroll_col)
-        o.slabs_row, o.slabs_col = int(slabs_row), int(slabs_col)
-        o.criterion = {"kkt": 0, "inf": 1, "pogs": 2}[criterion]
-        o.eps_gap = float(eps_gap)
-        o.slab_kernel = {"auto": 0, "chunked": 1, "lanes": 2, "chunked4": 3}[slab_kernel]
-        o.eps_abs = float(eps_abs)
-        o.use_graph = 1 if use_graph else 0
+        keep, csr, cones, bb, cc = _problem(self.m, self.n, row_ptr, col_idx, val, b, c, n_orth, soc_sizes)
+        o = _opts(mu=mu, precision=precision, check_every=check_every, eps=eps, max_iter=max_iter,
+                  lanes_row=lanes_row, lanes_col=lanes_col, unroll_row=unroll_row, unroll_col=unroll_col,
+                  slabs_row=slabs_row, slabs_col=slabs_col, criterion=criterion, eps_abs=eps_abs,
+                  eps_gap=eps_gap, slab_kernel=slab_kernel, resident=resident, use_graph=use_graph,
+                  stream=stream)
         self.precision = precision
         self.nnz = csr.nnz
-        bb = _f64(b, self.m)
-        cc = _f64(c, self.n)
         h = ctypes.c_void_p()
         _check(L.solver_create(ctypes.byref(csr), _ptr(bb), _ptr(cc), ctypes.byref(cones),
                                ctypes.byref(o), ctypes.byref(h)), "solver_create")
@@ -251,10 +290,10 @@ class Solver:
 
     def launch_shape(self) -> dict:
         """Lanes and gathers in flight per lane of the row and column passes."""
-        a = (ctypes.c_int32 * 6)()
+        a = (ctypes.c_int32 * 7)()
         _check(lib().solver_launch_shape(self._h, a), "solver_launch_shape")
         return {"lanes_row": a[0], "unroll_row": a[1], "lanes_col": a[2], "unroll_col": a[3],
-                "slabs_row": a[4], "slabs_col": a[5]}
+                "slabs_row": a[4], "slabs_col": a[5], "resident": bool(a[6])}
 
 
 def _bind_batch(L):
