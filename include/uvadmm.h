@@ -53,6 +53,7 @@ extern "C" {
                            b or c are accepted at create and end the run
                            at its first check with this code) */
 #define UV_ETOOBIG  -7  /* nnz >= 2^31 (device indices are 32-bit) */
+#define UV_ENOSCRATCH -8  /* the problem does not fit solver_solve_noalloc */
 
 /* Largest second-order cone handled (one workgroup projects a cone). */
 #define UV_MAX_CONE 1024
@@ -245,6 +246,25 @@ int solver_solve(const uv_csr *A, const double *b, const double *c,
                  const uv_cones *K, const uv_opts *opts, int64_t iters,
                  double *x, double *z, double *lambda, double *delta,
                  uv_residuals *r);
+
+/* solver_solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments and results (bitwise the same outputs as solver_solve),
+ * and no device, pinned-host or host heap allocation -- every device buffer
+ * is carved from one fixed 2 MiB array per GPU, which each GPU keeps until
+ * the process ends.  It serves the problems of the resident path: every
+ * cone of size 1, m, n < 65536, small enough for one CU's LDS (about
+ * 158 KiB) and for the fixed array; others return UV_ENOSCRATCH before any
+ * device work (UV_EINVAL with opts.resident = 1).  Inputs and outputs are
+ * host buffers as for solver_solve; the work is ordered on opts.hip_stream
+ * (NULL: the null stream) and the call returns when it is done.  Every call
+ * on one GPU uses that GPU's array: calls that overlap on one GPU (two host
+ * threads, or two streams) race and must not be made; a call overwrites all
+ * it reads of the array before reading it. */
+int solver_solve_noalloc(const uv_csr *A, const double *b, const double *c,
+                         const uv_cones *K, const uv_opts *opts,
+                         int64_t iters, double *x, double *z,
+                         double *lambda, double *delta, uv_residuals *r);
 
 /* Measurement: runs `iters` iterations (no residual checks), timing every
  * kernel launch with HIP events on the solver's stream, and returns the

@@ -26,6 +26,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1298,6 +1299,15 @@ int build_graph(uv_solver *s)
     return UV_OK;
 }
 
+// Lanes per segment of k_resident: the most (a power of two, at most 64)
+// that keeps every segment of the pass on a lane group at once.
+int resident_lanes(int segs)
+{
+    int L = 1;
+    while (L < 64 && (int64_t)segs * L * 2 <= kResThreads) L <<= 1;
+    return L;
+}
+
 // Device operands of k_resident.
 struct ResArgs {
     int m, n;
@@ -1631,6 +1641,9 @@ const char *solver_strerror(int code)
     case UV_EHIP: return "HIP runtime error";
     case UV_ENUMERIC: return "NaN or Inf in a residual check";
     case UV_ETOOBIG: return "nnz must be below 2^31";
+    case UV_ENOSCRATCH:
+        return "the problem does not fit the no-allocation entry point (orthant cones only, m, n < 65536, "
+               "small enough for one CU's LDS and the fixed device scratch)";
     default: return "unknown error code";
     }
 }
@@ -1696,15 +1709,8 @@ int solver_create(const uv_csr *A, const double *b, const double *c, const uv_co
         const bool forced = o.lanes_row || o.lanes_col || o.unroll_row || o.unroll_col || o.slabs_row ||
                             o.slabs_col || o.slab_kernel;
         s->resident = fits && (o.resident == 2 || (o.resident == 0 && !forced));
-        // lanes per segment: the most (a power of two, at most 64) that
-        // keeps every segment of the pass on a lane group at once
-        auto lanes = [](int segs) {
-            int L = 1;
-            while (L < 64 && (int64_t)segs * L * 2 <= kResThreads) L <<= 1;
-            return L;
-        };
-        s->res_lr = lanes(A->m);
-        s->res_lc = lanes(A->n);
+        s->res_lr = resident_lanes(A->m);
+        s->res_lc = resident_lanes(A->n);
         if (s->resident) {
             const hipError_t e = mixed ? hipFuncSetAttribute((const void *)k_resident<float>,
                                                              hipFuncAttributeMaxDynamicSharedMemorySize, kResLdsMax)
@@ -1762,6 +1768,104 @@ int upload_state(uv_solver *s, const double *x, const double *z, const double *d
     else k_start<double><<<blocks_for(m, kWG), kWG, 0, st>>>(m, s->lam, (double *)s->u, im, s->st);
     UV_TRY(hipGetLastError());
     return UV_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch of the no-allocation entry point
+// ---------------------------------------------------------------------------
+namespace {
+
+// Every device buffer of solver_solve_noalloc is carved from this array, so
+// the call allocates nothing.  Each GPU holds its own copy until the process
+// ends; host code reaches it only through the address hipGetSymbolAddress
+// returns on that device (the array's name is not a device address there).
+constexpr size_t kScratchBytes = (size_t)2 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kScratchDevices] = {};
+
+// The scratch array's address on the current device (looked up once per
+// device, with that device current).
+int scratch_address(unsigned char **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return UV_EHIP;
+    if (dev < 0 || dev >= kScratchDevices) return UV_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return UV_EHIP;
+        g_scratch_ptr[dev] = (unsigned char *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return UV_OK;
+}
+
+// Buffers carved in order from a region of `cap` bytes, 256-byte aligned;
+// run once without a base to size the request.
+struct Carve {
+    unsigned char *base;
+    size_t off, cap;
+    bool ok;
+    template <typename T>
+    T *take(size_t count)
+    {
+        off = (off + 255) / 256 * 256;
+        const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+        if (off + bytes > cap) ok = false;
+        T *p = ok && base ? (T *)(base + off) : nullptr;
+        off += bytes;
+        return p;
+    }
+};
+
+// int64 row offsets (m + 1, validated below 2^31) to the 32-bit device form.
+__global__ void __launch_bounds__(kWG) k_narrow_offsets(int len, const int64_t *__restrict__ src, int *__restrict__ dst)
+{
+    const int i = blockIdx.x * kWG + threadIdx.x;
+    if (i < len) dst[i] = (int)src[i];
+}
+
+// Device buffers of one no-allocation solve.
+struct NoAlloc {
+    DevStatus *st;
+    int64_t *rp64;
+    int *rp, *ci, *cp, *ri, *cnt, *bsum;
+    double *va64, *vc64, *b64, *c64, *lam, *delta, *wide;
+    void *va, *vc, *b, *c, *fu, *x, *z, *u;
+};
+
+bool carve_noalloc(Carve &cv, int m, int n, int nnz, bool mixed, NoAlloc &d)
+{
+    const size_t ts = mixed ? 4 : 8;
+    d.st = cv.take<DevStatus>(1);
+    d.rp64 = cv.take<int64_t>((size_t)m + 1);
+    d.rp = cv.take<int>((size_t)m + 1);
+    d.ci = cv.take<int>(nnz);
+    d.cp = cv.take<int>((size_t)n + 1);
+    d.ri = cv.take<int>(nnz);
+    d.cnt = cv.take<int>(n);
+    d.bsum = cv.take<int>(blocks_for(n, 4 * kWG));
+    d.va64 = cv.take<double>(nnz);
+    d.vc64 = cv.take<double>(nnz);
+    d.b64 = cv.take<double>(m);
+    d.c64 = cv.take<double>(n);
+    d.lam = cv.take<double>(m);
+    d.delta = cv.take<double>(n);
+    d.wide = cv.take<double>(n);
+    d.va = mixed ? (void *)cv.take<float>(nnz) : (void *)d.va64;
+    d.vc = mixed ? (void *)cv.take<float>(nnz) : (void *)d.vc64;
+    d.b = mixed ? (void *)cv.take<float>(m) : (void *)d.b64;
+    d.c = mixed ? (void *)cv.take<float>(n) : (void *)d.c64;
+    d.fu = cv.take<char>(ts * m);
+    d.x = cv.take<char>(ts * n);
+    d.z = cv.take<char>(ts * n);
+    d.u = cv.take<char>(ts * m);
+    return cv.ok;
 }
 
 }  // namespace
@@ -1903,6 +2007,152 @@ int solver_solve(const uv_csr *A, const double *b, const double *c, const uv_con
     }
     solver_destroy(s);
     return rc;
+}
+
+int solver_solve_noalloc(const uv_csr *A, const double *b, const double *c, const uv_cones *K, const uv_opts *opts,
+                         int64_t iters, double *x, double *z, double *lambda, double *delta, uv_residuals *r)
+{
+    if (iters < 0) return UV_EINVAL;
+    uv_opts o;
+    uv_default_opts(&o);
+    if (opts) o = *opts;
+    int rc = validate(A, b, c, K, &o);
+    if (rc != UV_OK) return rc;
+    if (o.resident == 1) return UV_EINVAL;  // this entry point is the resident path
+    const bool mixed = o.precision == UV_MIXED;
+    const int m = A->m, n = A->n, nnz = (int)A->nnz;
+    const ResLayout L = mixed ? resident_layout<float>(m, n, nnz) : resident_layout<double>(m, n, nnz);
+    if (K->n_soc != 0 || m >= 65536 || n >= 65536 || L.bytes > kResLdsMax) return UV_ENOSCRATCH;
+    NoAlloc d{};
+    Carve size{nullptr, 0, kScratchBytes, true};
+    if (!carve_noalloc(size, m, n, nnz, mixed, d)) return UV_ENOSCRATCH;
+    unsigned char *base = nullptr;
+    if ((rc = scratch_address(&base)) != UV_OK) return rc;
+    Carve cv{base, 0, kScratchBytes, true};
+    carve_noalloc(cv, m, n, nnz, mixed, d);
+    const hipError_t fe = mixed ? hipFuncSetAttribute((const void *)k_resident<float>,
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize, kResLdsMax)
+                                : hipFuncSetAttribute((const void *)k_resident<double>,
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize, kResLdsMax);
+    if (fe != hipSuccess) return UV_EHIP;
+    hipStream_t st = (hipStream_t)o.hip_stream;
+    const size_t ts = mixed ? 4 : 8;
+    // inputs and the setup of solver_create
+    UV_TRY(hipMemcpyAsync(d.rp64, A->row_ptr, 8 * ((size_t)m + 1), hipMemcpyHostToDevice, st));
+    k_narrow_offsets<<<blocks_for(m + 1, kWG), kWG, 0, st>>>(m + 1, d.rp64, d.rp);
+    if (nnz > 0) {
+        UV_TRY(hipMemcpyAsync(d.ci, A->col_idx, 4 * (size_t)nnz, hipMemcpyHostToDevice, st));
+        UV_TRY(hipMemcpyAsync(d.va64, A->val, 8 * (size_t)nnz, hipMemcpyHostToDevice, st));
+    }
+    UV_TRY(hipMemcpyAsync(d.b64, b, 8 * (size_t)m, hipMemcpyHostToDevice, st));
+    UV_TRY(hipMemcpyAsync(d.c64, c, 8 * (size_t)n, hipMemcpyHostToDevice, st));
+    if (!build_csc(m, n, nnz, d.rp, d.ci, d.va64, d.cp, d.ri, d.vc64, d.cnt, d.bsum, st)) return UV_EHIP;
+    if (mixed) {
+        k_row_factor<float><<<blocks_for(m, kWG), kWG, 0, st>>>(m, d.rp, d.va64, (float *)d.fu);
+        if (nnz > 0) {
+            k_narrow<float><<<blocks_for(nnz, kWG), kWG, 0, st>>>(nnz, d.va64, (float *)d.va);
+            k_narrow<float><<<blocks_for(nnz, kWG), kWG, 0, st>>>(nnz, d.vc64, (float *)d.vc);
+        }
+        k_narrow<float><<<blocks_for(m, kWG), kWG, 0, st>>>(m, d.b64, (float *)d.b);
+        k_narrow<float><<<blocks_for(n, kWG), kWG, 0, st>>>(n, d.c64, (float *)d.c);
+    } else {
+        k_row_factor<double><<<blocks_for(m, kWG), kWG, 0, st>>>(m, d.rp, d.va64, (double *)d.fu);
+    }
+    k_norms<<<1, kWG, 0, st>>>(m, d.b64, n, d.c64, d.st);
+    // the zero start (everything the last call left in the scratch is overwritten)
+    UV_TRY(hipMemsetAsync(d.x, 0, ts * n, st));
+    UV_TRY(hipMemsetAsync(d.z, 0, ts * n, st));
+    UV_TRY(hipMemsetAsync(d.delta, 0, 8 * (size_t)n, st));
+    UV_TRY(hipMemsetAsync(d.lam, 0, 8 * (size_t)m, st));
+    const double im = 1.0 / o.mu;
+    if (mixed) k_start<float><<<blocks_for(m, kWG), kWG, 0, st>>>(m, d.lam, (float *)d.u, im, d.st);
+    else k_start<double><<<blocks_for(m, kWG), kWG, 0, st>>>(m, d.lam, (double *)d.u, im, d.st);
+    UV_TRY(hipGetLastError());
+    ResArgs a{};
+    a.m = m;
+    a.n = n;
+    a.L = L;
+    a.Lr = resident_lanes(m);
+    a.Lc = resident_lanes(n);
+    a.rp = d.rp;
+    a.ci = d.ci;
+    a.cp = d.cp;
+    a.ri = d.ri;
+    a.va = d.va;
+    a.vc = d.vc;
+    a.b = d.b;
+    a.c = d.c;
+    a.fu = d.fu;
+    a.va64 = d.va64;
+    a.vc64 = d.vc64;
+    a.b64 = d.b64;
+    a.c64 = d.c64;
+    a.x = d.x;
+    a.z = d.z;
+    a.u = d.u;
+    a.lam = d.lam;
+    a.delta = d.delta;
+    a.st = d.st;
+    a.mixed = mixed;
+    a.mu = o.mu;
+    a.eps = o.eps_kkt;
+    a.eps_abs = o.eps_abs;
+    a.eps_gap = o.eps_gap;
+    a.check_every = o.check_every;
+    a.crit = o.criterion;
+    int64_t left = iters;
+    if (o.max_iter > 0) left = std::min<int64_t>(left, o.max_iter);
+    resident_launch(a, st, left, false);
+    UV_TRY(hipGetLastError());
+    DevStatus h{};
+    UV_TRY(hipMemcpyAsync(&h, d.st, sizeof(DevStatus), hipMemcpyDeviceToHost, st));
+    UV_TRY(hipStreamSynchronize(st));
+    if (r && h.check_iter != h.iter) {  // residuals of the final iterate (no decision)
+        resident_launch(a, st, 0, true);
+        UV_TRY(hipGetLastError());
+        const int status = h.status, stopped = h.done;
+        UV_TRY(hipMemcpyAsync(&h, d.st, sizeof(DevStatus), hipMemcpyDeviceToHost, st));
+        UV_TRY(hipStreamSynchronize(st));
+        h.status = status;
+        h.done = stopped;
+    }
+    if (!h.done && o.max_iter > 0 && h.iter >= o.max_iter) {
+        h.status = UV_STATUS_MAX_ITER;
+        h.done = 1;
+    }
+    // outputs
+    auto get_t = [&](double *dst, const void *src) -> int {
+        if (!dst) return UV_OK;
+        if (mixed) {
+            k_widen<float><<<blocks_for(n, kWG), kWG, 0, st>>>(n, (const float *)src, d.wide);
+            src = d.wide;
+        }
+        if (hipMemcpyAsync(dst, src, 8 * (size_t)n, hipMemcpyDeviceToHost, st) != hipSuccess) return UV_EHIP;
+        return hipStreamSynchronize(st) == hipSuccess ? UV_OK : UV_EHIP;
+    };
+    if ((rc = get_t(x, d.x)) != UV_OK) return rc;
+    if ((rc = get_t(z, d.z)) != UV_OK) return rc;
+    if (lambda) UV_TRY(hipMemcpyAsync(lambda, d.lam, 8 * (size_t)m, hipMemcpyDeviceToHost, st));
+    if (delta) UV_TRY(hipMemcpyAsync(delta, d.delta, 8 * (size_t)n, hipMemcpyDeviceToHost, st));
+    UV_TRY(hipStreamSynchronize(st));
+    if (r) {
+        r->r_prim = h.r_prim;
+        r->r_dual = h.r_dual;
+        r->r_gap = h.r_gap;
+        r->kkt = h.kkt;
+        r->pobj = h.pobj;
+        r->dobj = h.dobj;
+        r->res_ax_b = h.res_ax_b;
+        r->prim_inf = h.prim_inf;
+        r->dual_inf = h.dual_inf;
+        r->scale_p = h.scale_p;
+        r->scale_d = h.scale_d;
+        r->iter = h.iter;
+        r->status = h.status;
+        r->pobj_x = h.pobj_x;
+        r->gap_x = h.gap_x;
+    }
+    return h.status == UV_STATUS_NUMERIC ? UV_ENUMERIC : UV_OK;
 }
 
 int solver_time_kernels(uv_solver *s, int32_t iters, double *ms_col, double *ms_row)

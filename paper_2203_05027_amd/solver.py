@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libuvadmm.so")
 
 UV_OK, UV_EINVAL, UV_EBADCSR, UV_ECONE, UV_ENOMEM, UV_EHIP, UV_ENUMERIC, UV_ETOOBIG = 0, -1, -2, -3, -4, -5, -6, -7
+UV_ENOSCRATCH = -8
 UV_FP64, UV_MIXED = 0, 1
 UV_MAX_CONE = 1024
 STATUS = {0: "running", 1: "converged", 2: "max_iter", 3: "numeric"}
@@ -93,6 +94,8 @@ def lib():
     L.solver_solve.argtypes = [ctypes.POINTER(UvCsr), P, P, ctypes.POINTER(UvCones), ctypes.POINTER(UvOpts),
                                i64, P, P, P, P, ctypes.POINTER(UvResiduals)]
     L.solver_solve.restype = ctypes.c_int
+    L.solver_solve_noalloc.argtypes = L.solver_solve.argtypes
+    L.solver_solve_noalloc.restype = ctypes.c_int
     L.solver_residuals.argtypes = [P, ctypes.POINTER(UvResiduals)]
     L.solver_residuals.restype = ctypes.c_int
     L.solver_solution.argtypes = [P, P, P, P, P]
@@ -184,17 +187,19 @@ def _opts(*, mu=1.0, precision="fp64", check_every=10, eps=1e-4, max_iter=0, lan
     return o
 
 
-def solve(inst, iters, **kw):
-    """solver_solve on an instance dict: (return code, solution dict,
-    residuals dict).  Options as for Solver."""
+def solve(inst, iters, noalloc=False, **kw):
+    """solver_solve (or, with noalloc, solver_solve_noalloc) on an instance
+    dict: (return code, solution dict, residuals dict).  Options as for
+    Solver."""
     m, n = int(inst["m"]), int(inst["n"])
     keep, csr, cones, bb, cc = _problem(m, n, inst["row_ptr"], inst["col_idx"], inst["val"], inst["b"],
                                         inst["c"], inst["n_orth"], inst["soc_sizes"])
     o = _opts(**kw)
     x, z, d, lam = np.empty(n), np.empty(n), np.empty(n), np.empty(m)
     r = UvResiduals()
-    rc = lib().solver_solve(ctypes.byref(csr), _ptr(bb), _ptr(cc), ctypes.byref(cones), ctypes.byref(o),
-                            ctypes.c_int64(int(iters)), _ptr(x), _ptr(z), _ptr(lam), _ptr(d), ctypes.byref(r))
+    fn = lib().solver_solve_noalloc if noalloc else lib().solver_solve
+    rc = fn(ctypes.byref(csr), _ptr(bb), _ptr(cc), ctypes.byref(cones), ctypes.byref(o),
+            ctypes.c_int64(int(iters)), _ptr(x), _ptr(z), _ptr(lam), _ptr(d), ctypes.byref(r))
     res = {k: getattr(r, k) for k, _ in UvResiduals._fields_}
     res["status"] = STATUS.get(res["status"], res["status"])
     return rc, {"x": x, "z": z, "delta": d, "lambda": lam}, res
