@@ -372,6 +372,52 @@ def bench_family_sweep(args, B=256, iters=300):
           flush=True)
 
 
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix-core peak
+
+
+def mlp_gemm_block(sizes=(8192, 4096), hidden=(512, 512), k=256, p=64, batch=256):
+    """The network's matrix-core GEMM (mlp_gemm_bf16) on square problems,
+    with B stored k-contiguous and n-contiguous, and the network's own train
+    step (BF16 MFMA forward and backward, Adam) at the warm start's shape;
+    TFLOP/s against the dense BF16 peak."""
+    import torch
+    from paper_2203_05027_amd import learn
+    out = {"peak_tflops": BF16_PEAK_TFLOPS, "square": []}
+    for n in sizes:
+        A = torch.randint(-16000, 16000, (n, n), dtype=torch.int16, device="cuda")
+        B = torch.randint(-16000, 16000, (n, n), dtype=torch.int16, device="cuda")
+        for layout, tb in (("B k-contiguous", True), ("B n-contiguous", False)):
+            learn.gemm_bf16(A, B, transB=tb)
+            reps = 10
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                learn.gemm_bf16(A, B, transB=tb)
+            dt = (time.perf_counter() - t0) / reps
+            tf = 2.0 * n ** 3 / dt / 1e12
+            out["square"].append({"M=N=K": n, "layout": layout, "ms": dt * 1e3, "tflops": tf,
+                                  "frac": tf / BF16_PEAK_TFLOPS})
+        del A, B
+    dims = [p, *hidden, k]
+    net = learn.MLP(dims, max_batch=batch, seed=1)
+    x = torch.randn(batch, p, device="cuda")
+    t = torch.randn(batch, k, device="cuda")
+    for _ in range(5):
+        net.train_step(x, t, lr=1e-4)
+    torch.cuda.synchronize()
+    reps = 200
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.train_step(x, t, lr=1e-4)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    fwd = sum(2 * batch * a * b for a, b in zip(dims[:-1], dims[1:]))
+    flops = fwd + fwd + (fwd - 2 * batch * dims[0] * dims[1])   # forward, weight gradients, input gradients
+    out["train_step"] = {"dims": dims, "batch": batch, "ms": dt * 1e3, "gemm_flops": flops,
+                         "tflops": flops / dt / 1e12, "frac": flops / dt / 1e12 / BF16_PEAK_TFLOPS}
+    return out
+
+
 def parametric_block(n_train, n_eval, epochs, train_eps=1e-3, train_cap=20_000, ttk_cap=200_000,
                      parts=("both", "primal", "dual"), projection=True, plain=8, cpu=True):
     """The learned warm start on the parametric family (A 5e4 x 1e5, theta in
@@ -444,6 +490,7 @@ def parametric_block(n_train, n_eval, epochs, train_eps=1e-3, train_cap=20_000, 
         "warm": dict(summary("both"), predict_s=cmp["predict_seconds"]),
         "plain_gpu_cold": {"members": plain, "seconds": tp, "per_member_s": tp / max(plain, 1), "iters": ip},
         "cpu_baseline": cpu_member,
+        "mlp_gemm": mlp_gemm_block(),
     }
     for v, key in (("primal", "warm_primal_only"), ("dual", "warm_dual_only"),
                    ("projection", "basis_projection_of_solution")):

@@ -1,8 +1,9 @@
 // mlp.hip -- the learned warm start's network: a multilayer perceptron
-// (ReLU hidden layers, linear output) whose GEMMs run on the BF16 matrix
-// cores (v_mfma_f32_16x16x16_bf16, FP32 accumulation), trained on a mean
-// squared error with Adam.  Master weights, biases, gradients and the Adam
-// moments are FP32; each GEMM reads BF16 copies of its operands.
+// (ReLU hidden layers, linear output) whose GEMMs run on gfx950's BF16
+// matrix cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation) from
+// LDS-staged tiles, trained on a mean squared error with Adam.  Master
+// weights, biases, gradients and the Adam moments are FP32; each GEMM reads
+// BF16 copies of its operands.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -17,7 +18,7 @@
 
 namespace {
 
-typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 // FP32 -> BF16, round to nearest even (NaN stays NaN).
@@ -38,54 +39,172 @@ enum Epi {
     EPI_MASK = 3,       // C * [act > 0] -> FP32 and BF16 (gradient through a ReLU)
 };
 
+// How a GEMM operand tile is read from global memory: 16-byte loads of
+// eight elements consecutive along k (KC) or along the tile's other
+// dimension (MC: m for A, n for B), or one element at a time (EL) when
+// neither stride is 1 or the addresses are not 16-byte aligned.
+enum LoadMode { LD_KC = 0, LD_MC = 1, LD_EL = 2 };
+
+constexpr int kBK = 64;           // k per staged step (two 16x16x32 MFMAs)
+constexpr int kLK = kBK + 8;      // LDS row pitch in elements (144 bytes: 16-byte aligned rows)
+
+// The loads of one operand tile (ROWS rows of the tile's m or n dimension,
+// k0..k0+63) of a thread: ROWS * 8 / 256 chunks of eight elements, held in
+// registers between the global loads and the LDS stores so that the next
+// tile's loads are in flight while the current tile is multiplied.
+// Element (r, k) of the operand is P[r * rs + k * ks]; rows >= R and k >= K
+// are zero.  KC: chunks along k (row c / 8, k (c % 8) * 8); MC: chunks along
+// the rows (k c % 64, rows (c / 64) * 8), so that the 64 lanes of a
+// wavefront store their transposed elements to 64 consecutive k of one row
+// (no LDS bank conflicts; lanes eight rows apart would all meet in one or
+// two banks, whatever the 16-byte-aligned pitch).
+template <int MODE, int ROWS>
+struct TileLoad {
+    static constexpr int kChunks = ROWS * kBK / 8 / 256;
+    static_assert(kChunks >= 1 && ROWS * kBK / 8 % 256 == 0, "whole chunks per thread");
+    uint4 v[kChunks];
+
+    __device__ __forceinline__ void load(const uint16_t *__restrict__ P, int64_t rs, int64_t ks, int r0, int R,
+                                         int k0, int K)
+    {
+#pragma unroll
+        for (int q = 0; q < kChunks; ++q) {
+            const int c = threadIdx.x + q * 256;
+            v[q] = uint4{0u, 0u, 0u, 0u};
+            if (MODE == LD_KC) {
+                const int gr = r0 + (c >> 3), gk = k0 + (c & 7) * 8;
+                if (gr < R && gk < K) v[q] = *(const uint4 *)(P + (int64_t)gr * rs + gk);
+            } else {
+                const int gk = k0 + c % kBK, gr = r0 + (c / kBK) * 8;
+                if (gr < R && gk < K) v[q] = *(const uint4 *)(P + (int64_t)gk * ks + gr);
+            }
+        }
+    }
+
+    // into LDS as T[row][k] (k contiguous, pitch kLK)
+    __device__ __forceinline__ void store(uint16_t *__restrict__ T) const
+    {
+#pragma unroll
+        for (int q = 0; q < kChunks; ++q) {
+            const int c = threadIdx.x + q * 256;
+            if (MODE == LD_KC) {
+                *(uint4 *)(T + (c >> 3) * kLK + (c & 7) * 8) = v[q];
+            } else {
+                const int kk = c % kBK, r8 = (c / kBK) * 8;
+                const uint16_t *e = (const uint16_t *)&v[q];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) T[(r8 + t) * kLK + kk] = e[t];
+            }
+        }
+    }
+};
+
+// The element-wise form (no unit stride or unaligned operands): straight
+// into LDS.
+template <int ROWS>
+__device__ __forceinline__ void stage_el(const uint16_t *__restrict__ P, int64_t rs, int64_t ks, int r0, int R,
+                                         int k0, int K, uint16_t *__restrict__ T)
+{
+    for (int c = threadIdx.x; c < ROWS * kBK; c += 256) {
+        const int r = c / kBK, kk = c % kBK, gr = r0 + r, gk = k0 + kk;
+        T[r * kLK + kk] = (gr < R && gk < K) ? P[(int64_t)gr * rs + (int64_t)gk * ks] : (uint16_t)0;
+    }
+}
+
 // C (M x N) = A (M x K) B (K x N) on BF16 operands with FP32 accumulation;
 // A(i,k) = A[i*a_rs + k*a_cs], B(k,j) = B[k*b_rs + j*b_cs]; M, N, K
-// multiples of 16.  Each wavefront owns one 16 x 16 tile of C: lane l feeds
-// A[l%16][4(l/16)..+3] and B[4(l/16)..+3][l%16] and receives
-// C[4(l/16)..+3][l%16] (the 16x16x16 BF16 MFMA operand layout).
-template <int EPI>
+// multiples of 16.  A workgroup (four wavefronts, 2 x 2) owns a block of
+// (32 TM) x (32 TN) entries of C, a wavefront (16 TM) x (16 TN): TM x TN
+// accumulators of the 16x16x32 MFMA.  Each 64-deep k step stages the
+// block's A rows and B columns in LDS, k contiguous, from coalesced 16-byte
+// loads issued during the previous step's products; lane l reads its
+// operands as one 16-byte LDS load each: A[l % 16][8 (l / 16) .. +7] and
+// B[8 (l / 16) .. +7][l % 16] of a 32-wide half step, and holds
+// C[4 (l / 16) .. +3][l % 16] of each tile.
+template <int EPI, int TM, int TN, int AM, int BMODE>
 __global__ void __launch_bounds__(256)
 k_mfma_gemm(int M, int N, int K, const uint16_t *__restrict__ A, int64_t a_rs, int64_t a_cs,
             const uint16_t *__restrict__ B, int64_t b_rs, int64_t b_cs, float *__restrict__ Cf,
             uint16_t *__restrict__ Cb, int64_t ldc, const float *__restrict__ bias,
             const uint16_t *__restrict__ act)
 {
-    const int wave = blockIdx.x * 4 + threadIdx.x / 64, lane = threadIdx.x % 64;
-    const int tiles_n = N / 16;
-    const int ti = wave / tiles_n, tj = wave % tiles_n;
-    if (ti * 16 >= M) return;
-    const int r = lane % 16, kq = lane / 16;
-    const int64_t arow = (int64_t)(ti * 16 + r) * a_rs, bcol = (int64_t)(tj * 16 + r) * b_cs;
-    v4f acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        v4s a, b;
+    constexpr int BM = 32 * TM, BN = 32 * TN;
+    constexpr bool PREFETCH = AM != LD_EL && BMODE != LD_EL;
+    __shared__ __align__(16) uint16_t As[BM * kLK];
+    __shared__ __align__(16) uint16_t Bs[BN * kLK];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int tiles_n = (N + BN - 1) / BN;
+    const int m0 = (blockIdx.x / tiles_n) * BM, n0 = (blockIdx.x % tiles_n) * BN;
+    const int r = lane & 15, kq = lane >> 4;
+    v4f acc[TM][TN];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int64_t k = k0 + kq * 4 + e;
-            a[e] = (short)A[arow + k * a_cs];
-            b[e] = (short)B[k * b_rs + bcol];
-        }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    // A tile: rows m (A(m, k) = A[m a_rs + k a_cs]); B tile: rows n (B(k, n) = B[n b_cs + k b_rs])
+    TileLoad<AM == LD_EL ? LD_KC : AM, BM> la;
+    TileLoad<BMODE == LD_EL ? LD_KC : BMODE, BN> lb;
+    if (PREFETCH) {
+        la.load(A, a_rs, a_cs, m0, M, 0, K);
+        lb.load(B, b_cs, b_rs, n0, N, 0, K);
     }
-    const int col = tj * 16 + r;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int row = ti * 16 + kq * 4 + e;
-        const int64_t o = (int64_t)row * ldc + col;
-        float v = acc[e];
-        if (EPI == EPI_F32) {
-            Cf[o] = v;
-        } else if (EPI == EPI_BIAS_RELU) {
-            v += bias[col];
-            Cb[o] = f2bf(v > 0.f ? v : 0.f);
-        } else if (EPI == EPI_BIAS_F32) {
-            Cf[o] = v + bias[col];
+    for (int k0 = 0; k0 < K; k0 += kBK) {
+        if (PREFETCH) {
+            la.store(As);
+            lb.store(Bs);
         } else {
-            v = bf2f(act[o]) > 0.f ? v : 0.f;
-            Cf[o] = v;
-            Cb[o] = f2bf(v);
+            stage_el<BM>(A, a_rs, a_cs, m0, M, k0, K, As);
+            stage_el<BN>(B, b_cs, b_rs, n0, N, k0, K, Bs);
         }
+        __syncthreads();
+        if (PREFETCH && k0 + kBK < K) {
+            la.load(A, a_rs, a_cs, m0, M, k0 + kBK, K);
+            lb.load(B, b_cs, b_rs, n0, N, k0 + kBK, K);
+        }
+#pragma unroll
+        for (int h = 0; h < kBK / 32; ++h) {
+            v8bf af[TM], bf[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+                af[i] = *(const v8bf *)(As + (wm * 16 * TM + i * 16 + r) * kLK + h * 32 + kq * 8);
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+                bf[j] = *(const v8bf *)(Bs + (wn * 16 * TN + j * 16 + r) * kLK + h * 32 + kq * 8);
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
     }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int col = n0 + wn * 16 * TN + j * 16 + r;
+            if (col >= N) continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = m0 + wm * 16 * TM + i * 16 + kq * 4 + e;
+                if (row >= M) continue;
+                const int64_t o = (int64_t)row * ldc + col;
+                float v = acc[i][j][e];
+                if (EPI == EPI_F32) {
+                    Cf[o] = v;
+                } else if (EPI == EPI_BIAS_RELU) {
+                    v += bias[col];
+                    Cb[o] = f2bf(v > 0.f ? v : 0.f);
+                } else if (EPI == EPI_BIAS_F32) {
+                    Cf[o] = v + bias[col];
+                } else {
+                    v = bf2f(act[o]) > 0.f ? v : 0.f;
+                    Cf[o] = v;
+                    Cb[o] = f2bf(v);
+                }
+            }
+        }
 }
 
 __global__ void __launch_bounds__(256) k_to_bf16(int64_t len, const float *__restrict__ x, uint16_t *__restrict__ y)
@@ -200,14 +319,58 @@ T *malloc_d(uv_mlp *h, size_t count)
     return (T *)p;
 }
 
+// Load mode of an operand whose element (r, k) is P[r * rs + k * ks]:
+// 16-byte loads need a unit stride along them, the other stride a multiple
+// of eight elements and a 16-byte-aligned base.
+int load_mode(const uint16_t *P, int64_t rs, int64_t ks)
+{
+    const bool aligned = ((uintptr_t)P & 15) == 0;
+    if (aligned && ks == 1 && rs % 8 == 0) return LD_KC;
+    if (aligned && rs == 1 && ks % 8 == 0) return LD_MC;
+    return LD_EL;
+}
+
+template <int EPI, int TM, int TN, int AM>
+void gemm_launch_b(int bmode, unsigned grid, hipStream_t st, int M, int N, int K, const uint16_t *A, int64_t a_rs,
+                   int64_t a_cs, const uint16_t *B, int64_t b_rs, int64_t b_cs, float *Cf, uint16_t *Cb, int64_t ldc,
+                   const float *bias, const uint16_t *act)
+{
+#define UV_GEMM_ARGS M, N, K, A, a_rs, a_cs, B, b_rs, b_cs, Cf, Cb, ldc, bias, act
+    if (bmode == LD_KC) k_mfma_gemm<EPI, TM, TN, AM, LD_KC><<<grid, 256, 0, st>>>(UV_GEMM_ARGS);
+    else if (bmode == LD_MC) k_mfma_gemm<EPI, TM, TN, AM, LD_MC><<<grid, 256, 0, st>>>(UV_GEMM_ARGS);
+    else k_mfma_gemm<EPI, TM, TN, AM, LD_EL><<<grid, 256, 0, st>>>(UV_GEMM_ARGS);
+}
+
+template <int EPI, int TM, int TN>
+void gemm_launch(hipStream_t st, int M, int N, int K, const uint16_t *A, int64_t a_rs, int64_t a_cs,
+                 const uint16_t *B, int64_t b_rs, int64_t b_cs, float *Cf, uint16_t *Cb, int64_t ldc,
+                 const float *bias, const uint16_t *act)
+{
+    const unsigned grid = (unsigned)(((M + 32 * TM - 1) / (32 * TM)) * ((N + 32 * TN - 1) / (32 * TN)));
+    const int am = load_mode(A, a_rs, a_cs), bm = load_mode(B, b_cs, b_rs);
+    if (am == LD_KC) gemm_launch_b<EPI, TM, TN, LD_KC>(bm, grid, st, UV_GEMM_ARGS);
+    else if (am == LD_MC) gemm_launch_b<EPI, TM, TN, LD_MC>(bm, grid, st, UV_GEMM_ARGS);
+    else gemm_launch_b<EPI, TM, TN, LD_EL>(bm, grid, st, UV_GEMM_ARGS);
+#undef UV_GEMM_ARGS
+}
+
+// 128 x 128 blocks when they still give every CU a block, else 64 x 64.
+template <int EPI>
+int gemm_any(hipStream_t st, int M, int N, int K, const uint16_t *A, int64_t a_rs, int64_t a_cs,
+             const uint16_t *B, int64_t b_rs, int64_t b_cs, float *Cf, uint16_t *Cb, int64_t ldc,
+             const float *bias, const uint16_t *act)
+{
+    const int64_t big = (int64_t)((M + 127) / 128) * ((N + 127) / 128);
+    if (big >= 256) gemm_launch<EPI, 4, 4>(st, M, N, K, A, a_rs, a_cs, B, b_rs, b_cs, Cf, Cb, ldc, bias, act);
+    else gemm_launch<EPI, 2, 2>(st, M, N, K, A, a_rs, a_cs, B, b_rs, b_cs, Cf, Cb, ldc, bias, act);
+    return hipGetLastError() == hipSuccess ? UV_OK : UV_EHIP;
+}
+
 template <int EPI>
 int mm(uv_mlp *h, int M, int N, int K, const uint16_t *A, int64_t a_rs, int64_t a_cs, const uint16_t *B,
        int64_t b_rs, int64_t b_cs, float *Cf, uint16_t *Cb, int64_t ldc, const float *bias, const uint16_t *act)
 {
-    const int64_t tiles = (int64_t)(M / 16) * (N / 16);
-    k_mfma_gemm<EPI><<<(unsigned)((tiles + 3) / 4), 256, 0, h->stream>>>(M, N, K, A, a_rs, a_cs, B, b_rs, b_cs, Cf,
-                                                                        Cb, ldc, bias, act);
-    return hipGetLastError() == hipSuccess ? UV_OK : UV_EHIP;
+    return gemm_any<EPI>(h->stream, M, N, K, A, a_rs, a_cs, B, b_rs, b_cs, Cf, Cb, ldc, bias, act);
 }
 
 int forward(uv_mlp *h, int batch, const float *x)
@@ -404,10 +567,9 @@ int mlp_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t *A, int64_t a_
                   int64_t b_rs, int64_t b_cs, float *C, int64_t ldc, void *stream)
 {
     if (M < 16 || N < 16 || K < 16 || M % 16 || N % 16 || K % 16 || !A || !B || !C) return UV_EINVAL;
-    const int64_t tiles = (int64_t)(M / 16) * (N / 16);
-    k_mfma_gemm<EPI_F32><<<(unsigned)((tiles + 3) / 4), 256, 0, (hipStream_t)stream>>>(
-        M, N, K, A, a_rs, a_cs, B, b_rs, b_cs, C, nullptr, ldc, nullptr, nullptr);
-    if (hipGetLastError() != hipSuccess) return UV_EHIP;
+    if (gemm_any<EPI_F32>((hipStream_t)stream, M, N, K, A, a_rs, a_cs, B, b_rs, b_cs, C, nullptr, ldc, nullptr,
+                          nullptr) != UV_OK)
+        return UV_EHIP;
     return hipStreamSynchronize((hipStream_t)stream) == hipSuccess ? UV_OK : UV_EHIP;
 }
 

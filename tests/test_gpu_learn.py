@@ -159,3 +159,38 @@ def test_pca_fit_recovers_subspace(torch_cuda):
     cos = np.linalg.svd(Vt[:8] @ Bm.T, compute_uv=False)
     say(f"principal-angle cosines min {cos.min():.6f}")
     assert cos.min() > 0.999
+
+
+@pytest.mark.parametrize("Mm,Nn,Kk", [(16, 16, 16), (48, 80, 48), (256, 512, 64), (2048, 2048, 96)])
+@pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True)])
+def test_gemm_bf16_tiles_and_ragged_k(torch_cuda, Mm, Nn, Kk, ta, tb):
+    """Block tiles of both sizes (64 and 128: the 2048 x 2048 case), a k that
+    leaves part of the last 32-wide step empty, and both load modes of each
+    operand, against an FP64 product of the same BF16 values."""
+    from paper_2203_05027_amd import learn
+    torch = torch_cuda
+    rng = np.random.default_rng(Mm + Nn + Kk)
+    A = M.bf16_round(rng.standard_normal((Kk, Mm) if ta else (Mm, Kk))).astype(np.float32)
+    B = M.bf16_round(rng.standard_normal((Nn, Kk) if tb else (Kk, Nn))).astype(np.float32)
+    Ab = torch.from_numpy((_bits(A)).astype(np.int16)).cuda()
+    Bb = torch.from_numpy((_bits(B)).astype(np.int16)).cuda()
+    C = learn.gemm_bf16(Ab, Bb, transA=ta, transB=tb).cpu().numpy()
+    ref = (A.T if ta else A).astype(np.float64) @ (B.T if tb else B).astype(np.float64)
+    np.testing.assert_allclose(C, ref, rtol=1e-5, atol=1e-4)
+
+
+def test_gemm_bf16_unaligned_operands(torch_cuda):
+    """Operands that start 2 bytes off a 16-byte boundary take the
+    element-wise load path and give the same product."""
+    from paper_2203_05027_amd import learn
+    torch = torch_cuda
+    rng = np.random.default_rng(3)
+    Mm, Nn, Kk = 64, 96, 80
+    A = M.bf16_round(rng.standard_normal((Mm, Kk))).astype(np.float32)
+    B = M.bf16_round(rng.standard_normal((Kk, Nn))).astype(np.float32)
+    Ab = torch.zeros(Mm * Kk + 1, dtype=torch.int16, device="cuda")
+    Bb = torch.zeros(Kk * Nn + 1, dtype=torch.int16, device="cuda")
+    Ab[1:] = torch.from_numpy(_bits(A).astype(np.int16).reshape(-1)).cuda()
+    Bb[1:] = torch.from_numpy(_bits(B).astype(np.int16).reshape(-1)).cuda()
+    C = learn.gemm_bf16(Ab[1:].view(Mm, Kk), Bb[1:].view(Kk, Nn)).cpu().numpy()
+    np.testing.assert_allclose(C, A.astype(np.float64) @ B.astype(np.float64), rtol=1e-5, atol=1e-4)
