@@ -97,7 +97,7 @@ def alg_bytes(m, n, nnz, precision, index_bytes=4):
     return row, col
 
 
-def measure(inst, precision, steps, warmup, check_every, ttk_cap, mu, ttk=True):
+def measure(inst, precision, steps, warmup, check_every, ttk_cap, mu, ttk=True, history_path=None):
     import torch
     from paper_2203_05027_amd.solver import Solver
 
@@ -124,8 +124,9 @@ def measure(inst, precision, steps, warmup, check_every, ttk_cap, mu, ttk=True):
         return out
 
     # time to 1e-4 relative KKT from the zero start
+    cap_checks = ttk_cap // check_every + 1 if history_path else 0
     s = Solver.from_instance(inst, mu=mu, precision=precision, eps=1e-4,
-                             check_every=check_every, max_iter=ttk_cap)
+                             check_every=check_every, max_iter=ttk_cap, history=cap_checks)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     chunk = 2000
@@ -138,6 +139,12 @@ def measure(inst, precision, steps, warmup, check_every, ttk_cap, mu, ttk=True):
     out["ttk_status"] = r["status"]
     out["ttk_kkt"] = r["kkt"]
     out["ttk_pobj"] = r["pobj"]
+    if history_path:  # every check of the run, one JSON object a line
+        recs = s.history()
+        with open(history_path, "a") as f:
+            for rec in recs:
+                f.write(json.dumps({"workload": inst.get("name", ""), "precision": precision, **rec}) + "\n")
+        out["history_records"] = len(recs)
     s.close()
     return out
 
@@ -258,11 +265,14 @@ def standard_block(inst, mu, cg_iters, cg_tol, check_every, cap_s, uv_ttk_s=None
     return out
 
 
-def batched_block(steps_sweep=100, ttk_cap=60_000, plain_sample=8, count=4096, log_fn=log, cpu_threads=0,
+def batched_block(steps_sweep=100, ttk_cap=300_000, plain_per_bucket=4, count=4096, log_fn=log, cpu_threads=0,
                   cpu_iters=1000, ttk=True):
     """The batched workload: all instances in one persistent launch (mixed
-    precision), sweep throughput, time to 1e-4 for the batch, and the plain
-    single-problem solver on a sample of the same instances (ttk=False: the
+    precision), sweep throughput, time to 1e-4 for the batch (the time when
+    every instance has converged or reached the cap; the instances still
+    unconverged at the cap are listed), and the plain single-problem solver
+    on a sample stratified by size bucket (plain_per_bucket instances drawn
+    from each), scaled bucket by bucket to all instances (ttk=False: the
     sweep alone, its timed launch the last of the block)."""
     from paper_2203_05027_amd import autotune
     from paper_2203_05027_amd import instances as I
@@ -295,24 +305,43 @@ def batched_block(steps_sweep=100, ttk_cap=60_000, plain_sample=8, count=4096, l
         res = [b.residuals(i) for i in range(count)]
     its = np.array([r["iter"] for r in res])
     conv = np.array([r["status"] == "converged" for r in res])
+    ms_ = np.array([i["m"] for i in insts])
     out.update(time_to_1e4_s=dt, converged=int(conv.sum()), cap=ttk_cap,
-               iters_median=float(np.median(its[conv])), iters_max_converged=int(its[conv].max()))
-    # plain solver, one instance at a time (graph replay), on a sample
+               converged_within_60k=int((conv & (its <= 60_000)).sum()),
+               iters_median=float(np.median(its[conv])), iters_max_converged=int(its[conv].max()),
+               unconverged=[{"instance": int(i), "m": int(ms_[i]), "iter": int(its[i]), "kkt": res[i]["kkt"],
+                             "status": res[i]["status"]} for i in np.nonzero(~conv)[0]])
+    # plain solver, one instance at a time, on a sample stratified by size bucket
     rng = np.random.default_rng(1)
-    sample = rng.choice(count, plain_sample, replace=False)
-    tp, ip = 0.0, 0
-    for i in sample:
-        with Solver.from_instance(insts[i], precision="mixed", eps=1e-4, max_iter=ttk_cap) as s:
-            t0 = time.perf_counter()
-            while not s.iterate(5000):
-                pass
-            tp += time.perf_counter() - t0
-            ip += s.residuals()["iter"]
-    batch_sample_iters = int(its[sample].sum())
-    out["plain_sample"] = {"instances": plain_sample, "seconds": tp, "iters": ip,
-                           "us_per_iter": tp / ip * 1e6,
-                           "est_all_instances_s": tp / ip * 1e6 * its.sum() * 1e-6,
-                           "batched_iters_same_sample": batch_sample_iters}
+    edges = [50, 128, 512, 2048, 5001]
+    buckets, tp_all, ip_all = [], 0.0, 0
+    est = 0.0
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        members = np.nonzero((ms_ >= lo) & (ms_ < hi))[0]
+        if members.size == 0:
+            continue
+        pick = rng.choice(members, min(plain_per_bucket, members.size), replace=False)
+        tp, ip = 0.0, 0
+        for i in pick:
+            with Solver.from_instance(insts[i], precision="mixed", eps=1e-4, max_iter=ttk_cap) as s:
+                t0 = time.perf_counter()
+                while not s.iterate(5000):
+                    pass
+                tp += time.perf_counter() - t0
+                ip += s.residuals()["iter"]
+        # the bucket's batched iteration count at the plain solver's time per iteration
+        b_est = tp / ip * float(its[members].sum())
+        est += b_est
+        tp_all += tp
+        ip_all += ip
+        buckets.append({"m_range": [lo, hi - 1], "instances": int(members.size), "sampled": int(pick.size),
+                        "seconds": tp, "iters": ip, "us_per_iter": tp / ip * 1e6,
+                        "batched_iters_same_sample": int(its[pick].sum()), "est_bucket_s": b_est})
+    out["plain_sample"] = {"per_bucket": buckets, "seconds": tp_all, "iters": ip_all,
+                           "est_all_instances_s": est,
+                           "what": f"{plain_per_bucket} instances drawn per size bucket of m, each solved alone to "
+                                   "1e-4; a bucket's estimate is its batched iteration total at the sample's "
+                                   "time per iteration"}
     if cpu_threads:
         out["cpu_oracle"] = batched_cpu(insts, sample_size=16 * cpu_threads, iters=cpu_iters, threads=cpu_threads)
     return out
@@ -524,6 +553,8 @@ def main():
     ap.add_argument("--ttk-cap", type=int, default=200_000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--history", default=None,
+                    help="write every residual check of the time-to-1e-4 runs to this JSONL file")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-ttk", action="store_true",
                     help="skip the time-to-1e-4 runs (with --workload lp_batched: the sweep alone)")
@@ -586,11 +617,13 @@ def main():
     log(f"workload {args.workload} m={m} n={n} nnz={nnz} generated in {time.time() - t0:.1f} s")
 
     res = {}
+    if args.history:
+        open(args.history, "w").close()
     ttk = not args.no_ttk and inst.get("bounded", True)   # no time to a tolerance on unbounded problems
     for prec in (["fp64"] if args.no_mixed else ["fp64", "mixed"]):
         log(f"measuring {prec}")
         res[prec] = measure(inst, prec, args.steps, args.warmup, args.check_every,
-                            args.ttk_cap, args.mu, ttk=ttk)
+                            args.ttk_cap, args.mu, ttk=ttk, history_path=args.history)
         log(f"{prec}: {json.dumps(res[prec])}")
 
     main_r = res["fp64"]

@@ -135,6 +135,9 @@ typedef struct {
                              slabs_* or slab_kernel force a shape of the
                              sweep kernels; 1 = never; 2 = required
                              (UV_EINVAL at create when it does not apply) */
+    int32_t history;      /* residual history: the last `history` checks of
+                             the iteration are recorded on the device (0 =
+                             none; at most 2^24); see solver_history */
 } uv_opts;
 
 /* Stopping tests (Section V): UV_CRIT_KKT stops when kkt <= eps_kkt (the
@@ -235,6 +238,21 @@ void solver_destroy(uv_solver *s);
 
 /* Static string for a UV_E* code. */
 const char *solver_strerror(int code);
+
+/* One record of the residual history: a check of the iteration (Section
+ * V-B's residuals, as in uv_residuals), with the GPU time since the start
+ * (solver_set_start or solver_resume) at which it was taken. */
+typedef struct {
+    int64_t iter;
+    double seconds;
+    double r_prim, r_dual, r_gap, kkt, pobj, dobj, res_ax_b, gap_x;
+} uv_history;
+
+/* The latest min(max, recorded, opts.history) checks of the residual
+ * history into out[0..*count-1], oldest first (host buffer of max records);
+ * *count = 0 when opts.history was 0.  Residual queries between checks are
+ * not recorded. */
+int solver_history(uv_solver *s, int32_t max, uv_history *out, int32_t *count);
 
 /* One call: solver_create, iterations from the zero start until the
  * stopping test holds at a check or `iters` iterations (or max_iter) are

@@ -48,8 +48,24 @@ struct DevStatus {
     double pobj_x, gap_x;  // c'x and |c'x + b'lambda| (the POGS-form test)
     long long iter;        // iterations done
     long long check_iter;  // iteration count at the last residual evaluation
+    long long hist_n;      // checks recorded in the residual history since the start
+    unsigned long long clock0;  // GPU wall clock at the start
     int done;              // 1 = stop: every sweep kernel returns at once
     int status;            // UV_STATUS_*
+};
+
+// One record of the residual history (a check of the iteration), as kept on
+// the device: the iteration, the GPU wall clock and the residuals.
+struct HistRec {
+    long long iter;
+    unsigned long long clock;
+    double r_prim, r_dual, r_gap, kkt, pobj, dobj, res_ax_b, gap_x;
+};
+
+// Ring of the last `cap` records (rec null: no history kept).
+struct HistRing {
+    HistRec *rec;
+    int cap;
 };
 
 constexpr int kSocTile = 256;  // columns per SOC tile when cones are small
@@ -87,6 +103,8 @@ k_start(int m, const double *__restrict__ lam, T *__restrict__ u, double inv_mu,
     if (i == 0) {
         st->iter = 0;
         st->check_iter = -1;
+        st->hist_n = 0;
+        st->clock0 = wall_clock64();
         st->done = 0;
         st->status = UV_STATUS_RUNNING;
     }
@@ -557,11 +575,16 @@ k_res_col_slab(int n, const double *__restrict__ P, const double *__restrict__ c
 // s[5] c'x, s[6] ||Az-b||_inf, s[7] ||Az||_inf, s[8]
 // ||A'lambda+c-delta||_inf, s[9] ||A'lambda||_inf; nrm: ||b||^2, ||c||^2,
 // ||b||_inf, ||c||_inf; it: the iteration count they belong to.  Records
-// the residuals in st and, with decide, the status and the stop flag;
-// returns whether the run stops here.  One thread.
+// the residuals in st and, with decide, the status and the stop flag (and a
+// record in the residual history); returns whether the run stops here.  One
+// thread.
 __device__ bool finish_check(const double (&s)[10], const double (&nrm)[4], long long it, double eps,
-                             double eps_abs, double eps_gap, int crit, int decide, DevStatus *st)
+                             double eps_abs, double eps_gap, int crit, int decide, DevStatus *st, HistRing hist)
 {
+    // a check replayed after the run stopped (the rest of a graph launch)
+    // repeats the stopping check: it leaves the status, the values and the
+    // history as they are
+    if (decide && st->done) return true;
     const double rp = sqrt(s[0]) / (1.0 + sqrt(nrm[0]));
     const double rd = sqrt(s[3]) / (1.0 + sqrt(nrm[1]));
     const double cz = s[4], bl = s[1], cx = s[5];
@@ -584,6 +607,20 @@ __device__ bool finish_check(const double (&s)[10], const double (&nrm)[4], long
     st->gap_x = gap_x;
     st->check_iter = it;
     if (!decide) return false;
+    if (hist.rec) {  // the checks of the iteration go into the residual history
+        HistRec &h = hist.rec[st->hist_n % hist.cap];
+        h.iter = it;
+        h.clock = wall_clock64();
+        h.r_prim = rp;
+        h.r_dual = rd;
+        h.r_gap = rg;
+        h.kkt = kkt;
+        h.pobj = cz;
+        h.dobj = -bl;
+        h.res_ax_b = res_ax_b;
+        h.gap_x = gap_x;
+        st->hist_n += 1;
+    }
     // crit 1 adds the gap condition when eps_gap > 0; crit 2 is the POGS
     // form (strict inequalities as printed)
     bool conv;
@@ -621,7 +658,7 @@ __device__ bool finish_check(const double (&s)[10], const double (&nrm)[4], long
 // status and the stop flag change at the checks of the iteration alone.
 __global__ void __launch_bounds__(kWG)
 k_finalize(int nrow, const double *__restrict__ prow, int ncol, const double *__restrict__ pcol,
-           double eps, double eps_abs, double eps_gap, int crit, int decide, DevStatus *st)
+           double eps, double eps_abs, double eps_gap, int crit, int decide, DevStatus *st, HistRing hist)
 {
     double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, w[4] = {0.0, 0.0, 0.0, 0.0};
     for (int base = threadIdx.x; base < nrow; base += 8 * kWG) {
@@ -662,7 +699,7 @@ k_finalize(int nrow, const double *__restrict__ prow, int ncol, const double *__
     uv::block_sum_max<6, 4>(v, w, s, 1);
     if (threadIdx.x != 0) return;
     const double nrm[4] = {st->bnorm2, st->cnorm2, st->binf, st->cinf};
-    finish_check(s, nrm, st->iter, eps, eps_abs, eps_gap, crit, decide, st);
+    finish_check(s, nrm, st->iter, eps, eps_abs, eps_gap, crit, decide, st, hist);
 }
 
 // ---------------------------------------------------------------------------
@@ -832,7 +869,8 @@ k_resident(int m, int n, ResLayout L, int Lr, int Lc, const int *__restrict__ rp
            const T *__restrict__ b, const double *__restrict__ b64, const T *__restrict__ c,
            const double *__restrict__ c64, const T *__restrict__ fu, T *__restrict__ x, T *__restrict__ z,
            T *__restrict__ u, double *__restrict__ lam, double *__restrict__ delta, double mu, long long iters,
-           int eval_only, int check_every, double eps, double eps_abs, double eps_gap, int crit, DevStatus *st)
+           int eval_only, int check_every, double eps, double eps_abs, double eps_gap, int crit, DevStatus *st,
+           HistRing hist)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ double red[10][kResThreads / 64];
@@ -873,7 +911,7 @@ k_resident(int m, int n, ResLayout L, int Lr, int Lc, const int *__restrict__ rp
     if (eval_only) {
         double sv[10];
         res_check<T>(m, n, Lr, Lc, rps, cis, cps, ris, cva, cvc, xs, zs, ds, ls, b64, c64, red, sv);
-        if (tid == 0) finish_check(sv, nrm, it0, eps, eps_abs, eps_gap, crit, 0, st);
+        if (tid == 0) finish_check(sv, nrm, it0, eps, eps_abs, eps_gap, crit, 0, st, hist);
         return;
     }
     const double inv_mu = 1.0 / mu;
@@ -912,7 +950,7 @@ k_resident(int m, int n, ResLayout L, int Lr, int Lc, const int *__restrict__ rp
         res_check<T>(m, n, Lr, Lc, rps, cis, cps, ris, cva, cvc, xs, zs, ds, ls, b64, c64, red, sv);
         if (tid == 0) {
             st->iter = itn;
-            stop = finish_check(sv, nrm, itn, eps, eps_abs, eps_gap, crit, 1, st) ? 1 : 0;
+            stop = finish_check(sv, nrm, itn, eps, eps_abs, eps_gap, crit, 1, st, hist) ? 1 : 0;
         }
         __syncthreads();
         if (stop) break;
@@ -975,6 +1013,8 @@ struct uv_solver {
     bool resident = false;      // iterate with k_resident (the whole problem in one workgroup's LDS)
     ResLayout rlay{};
     int res_lr = 1, res_lc = 1;  // lanes per row and per column of k_resident
+    HistRec *hist = nullptr;     // residual history ring (opts.history records)
+    double clock_khz = 0.0;      // rate of the GPU wall clock
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int64_t host_iter = 0;
@@ -1278,7 +1318,8 @@ void launch_residuals(uv_solver *s, hipStream_t st, bool row_done, bool decide)
     const int nrow = row_done ? s->nblk_row_fused : s->nblk_row;
     const int ncol = slab ? (int)blocks_for(s->n, kWG) : s->nblk_rescol;
     k_finalize<<<1, kWG, 0, st>>>(nrow, s->part_row, ncol, s->part_col, s->o.eps_kkt, s->o.eps_abs,
-                                  s->o.eps_gap, s->o.criterion, decide ? 1 : 0, s->st);
+                                  s->o.eps_gap, s->o.criterion, decide ? 1 : 0, s->st,
+                                  HistRing{s->hist, s->o.history});
 }
 
 // One iteration; with check, the residuals of the new iterate follow it.
@@ -1319,6 +1360,7 @@ struct ResArgs {
     void *x, *z, *u;                   // sweep type
     double *lam, *delta;
     DevStatus *st;
+    HistRing hist;
     bool mixed;
     double mu, eps, eps_abs, eps_gap;
     int check_every, crit;
@@ -1336,7 +1378,7 @@ void resident_launch(const ResArgs &a, hipStream_t st, int64_t iters, bool eval_
 #define UV_RES_ARGS(T)                                                                                         \
     a.m, a.n, a.L, a.Lr, a.Lc, a.rp, a.ci, (const T *)a.va, a.cp, a.ri, (const T *)a.vc, a.va64, a.vc64,         \
         (const T *)a.b, a.b64, (const T *)a.c, a.c64, (const T *)a.fu, (T *)a.x, (T *)a.z, (T *)a.u, a.lam,        \
-        a.delta, a.mu, q, eval_only ? 1 : 0, a.check_every, a.eps, a.eps_abs, a.eps_gap, a.crit, a.st
+        a.delta, a.mu, q, eval_only ? 1 : 0, a.check_every, a.eps, a.eps_abs, a.eps_gap, a.crit, a.st, a.hist
         if (a.mixed) k_resident<float><<<1, kResThreads, a.L.bytes, st>>>(UV_RES_ARGS(float));
         else k_resident<double><<<1, kResThreads, a.L.bytes, st>>>(UV_RES_ARGS(double));
 #undef UV_RES_ARGS
@@ -1371,6 +1413,7 @@ ResArgs res_args(const uv_solver *s)
     a.lam = s->lam;
     a.delta = s->delta;
     a.st = s->st;
+    a.hist = HistRing{s->hist, s->o.history};
     a.mixed = s->o.precision == UV_MIXED;
     a.mu = s->o.mu;
     a.eps = s->o.eps_kkt;
@@ -1402,6 +1445,7 @@ int validate(const uv_csr *A, const double *b, const double *c, const uv_cones *
     if (!slabs_ok(o->slabs_row) || !slabs_ok(o->slabs_col)) return UV_EINVAL;
     if (o->slab_kernel < 0 || o->slab_kernel > 3) return UV_EINVAL;
     if (o->resident < 0 || o->resident > 2) return UV_EINVAL;
+    if (o->history < 0 || o->history > (1 << 24)) return UV_EINVAL;
     if (A->nnz > 0 && (!A->col_idx || !A->val)) return UV_EINVAL;
     if (!A->row_ptr) return UV_EINVAL;
     if (A->nnz >= ((int64_t)1 << 31)) return UV_ETOOBIG;
@@ -1473,6 +1517,14 @@ int setup(uv_solver *s, const uv_csr *A, const double *b, const double *c, const
     s->part_row = dalloc<double>(s, 5 * (size_t)std::max(s->nblk_row, s->nblk_row_fused));
     s->part_col = dalloc<double>(s, 5 * std::max((size_t)s->nblk_rescol, (size_t)blocks_for(n, kWG)));
     s->st = dalloc<DevStatus>(s, 1);
+    if (s->o.history > 0) {
+        s->hist = dalloc<HistRec>(s, (size_t)s->o.history);
+        if (!s->hist) return UV_ENOMEM;
+        int dev = 0, khz = 0;
+        UV_TRY(hipGetDevice(&dev));
+        UV_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        s->clock_khz = khz;
+    }
     const size_t ncnt = std::max({(size_t)n, (size_t)s->S_row * m, (size_t)s->S_col * n});
     int *cnt = dalloc<int>(s, ncnt);
     int *bsum = dalloc<int>(s, blocks_for(ncnt, 4 * kWG));
@@ -1628,6 +1680,7 @@ void uv_default_opts(uv_opts *o)
     o->slab_kernel = 0;
     o->eps_gap = 0.0;
     o->resident = 0;
+    o->history = 0;
 }
 
 const char *solver_strerror(int code)
@@ -1991,6 +2044,42 @@ int solver_solution(uv_solver *s, double *x, double *z, double *lambda, double *
     return UV_OK;
 }
 
+int solver_history(uv_solver *s, int32_t max, uv_history *out, int32_t *count)
+{
+    if (!s || max < 0 || (max > 0 && !out) || !count) return UV_EINVAL;
+    *count = 0;
+    if (!s->hist || max == 0) return UV_OK;
+    UV_TRY(hipMemcpyAsync(s->st_host, s->st, sizeof(DevStatus), hipMemcpyDeviceToHost, s->stream));
+    UV_TRY(hipStreamSynchronize(s->stream));
+    const long long written = s->st_host->hist_n, cap = s->o.history;
+    const long long kept = std::min(written, cap), take = std::min<long long>(kept, max);
+    const double per_s = s->clock_khz > 0 ? 1.0 / (s->clock_khz * 1e3) : 0.0;
+    // the latest `take` records, oldest first: at most two runs of the ring
+    std::vector<HistRec> h((size_t)take);
+    const long long first = (written - take) % cap, run1 = std::min(take, cap - first);
+    if (run1 > 0)
+        UV_TRY(hipMemcpy(h.data(), s->hist + first, sizeof(HistRec) * (size_t)run1, hipMemcpyDeviceToHost));
+    if (take > run1)
+        UV_TRY(hipMemcpy(h.data() + run1, s->hist, sizeof(HistRec) * (size_t)(take - run1),
+                         hipMemcpyDeviceToHost));
+    for (long long q = 0; q < take; ++q) {
+        const HistRec &r = h[(size_t)q];
+        uv_history &o = out[q];
+        o.iter = r.iter;
+        o.seconds = (double)(r.clock - s->st_host->clock0) * per_s;
+        o.r_prim = r.r_prim;
+        o.r_dual = r.r_dual;
+        o.r_gap = r.r_gap;
+        o.kkt = r.kkt;
+        o.pobj = r.pobj;
+        o.dobj = r.dobj;
+        o.res_ax_b = r.res_ax_b;
+        o.gap_x = r.gap_x;
+    }
+    *count = (int32_t)take;
+    return UV_OK;
+}
+
 int solver_solve(const uv_csr *A, const double *b, const double *c, const uv_cones *K, const uv_opts *opts,
                  int64_t iters, double *x, double *z, double *lambda, double *delta, uv_residuals *r)
 {
@@ -2093,6 +2182,7 @@ int solver_solve_noalloc(const uv_csr *A, const double *b, const double *c, cons
     a.lam = d.lam;
     a.delta = d.delta;
     a.st = d.st;
+    a.hist = HistRing{nullptr, 0};
     a.mixed = mixed;
     a.mu = o.mu;
     a.eps = o.eps_kkt;

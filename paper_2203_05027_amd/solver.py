@@ -40,7 +40,8 @@ class UvOpts(ctypes.Structure):
                 ("unroll_col", ctypes.c_int32), ("slabs_row", ctypes.c_int32),
                 ("slabs_col", ctypes.c_int32), ("criterion", ctypes.c_int32),
                 ("eps_abs", ctypes.c_double), ("slab_kernel", ctypes.c_int32),
-                ("eps_gap", ctypes.c_double), ("resident", ctypes.c_int32)]
+                ("eps_gap", ctypes.c_double), ("resident", ctypes.c_int32),
+                ("history", ctypes.c_int32)]
 
 
 class UvResiduals(ctypes.Structure):
@@ -52,6 +53,14 @@ class UvResiduals(ctypes.Structure):
                 ("scale_d", ctypes.c_double), ("iter", ctypes.c_int64),
                 ("status", ctypes.c_int32), ("pobj_x", ctypes.c_double),
                 ("gap_x", ctypes.c_double)]
+
+
+class UvHistory(ctypes.Structure):
+    _fields_ = [("iter", ctypes.c_int64), ("seconds", ctypes.c_double),
+                ("r_prim", ctypes.c_double), ("r_dual", ctypes.c_double),
+                ("r_gap", ctypes.c_double), ("kkt", ctypes.c_double),
+                ("pobj", ctypes.c_double), ("dobj", ctypes.c_double),
+                ("res_ax_b", ctypes.c_double), ("gap_x", ctypes.c_double)]
 
 
 class UvError(RuntimeError):
@@ -109,6 +118,8 @@ def lib():
     L.solver_time_kernels.restype = ctypes.c_int
     L.solver_launch_shape.argtypes = [P, ctypes.POINTER(i32)]
     L.solver_launch_shape.restype = ctypes.c_int
+    L.solver_history.argtypes = [P, i32, ctypes.POINTER(UvHistory), ctypes.POINTER(i32)]
+    L.solver_history.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -167,7 +178,7 @@ def _problem(m, n, row_ptr, col_idx, val, b, c, n_orth, soc_sizes):
 
 def _opts(*, mu=1.0, precision="fp64", check_every=10, eps=1e-4, max_iter=0, lanes_row=0, lanes_col=0,
           unroll_row=0, unroll_col=0, slabs_row=0, slabs_col=0, criterion="kkt", eps_abs=0.0, eps_gap=0.0,
-          slab_kernel="auto", resident="auto", use_graph=True, stream=None):
+          slab_kernel="auto", resident="auto", history=0, use_graph=True, stream=None):
     o = default_opts()
     o.mu = float(mu)
     o.precision = {"fp64": UV_FP64, "mixed": UV_MIXED}[precision]
@@ -183,6 +194,7 @@ def _opts(*, mu=1.0, precision="fp64", check_every=10, eps=1e-4, max_iter=0, lan
     o.resident = {"auto": 0, "never": 1, "required": 2}[resident]
     o.slab_kernel = {"auto": 0, "chunked": 1, "lanes": 2, "chunked4": 3}[slab_kernel]
     o.eps_abs = float(eps_abs)
+    o.history = int(history)
     o.use_graph = 1 if use_graph else 0
     return o
 
@@ -216,17 +228,18 @@ class Solver:
     def __init__(self, m, n, row_ptr, col_idx, val, b, c, n_orth, soc_sizes=(), *,
                  mu=1.0, precision="fp64", check_every=10, eps=1e-4, max_iter=0,
                  lanes_row=0, lanes_col=0, unroll_row=0, unroll_col=0, slabs_row=0, slabs_col=0,
-                 criterion="kkt", eps_abs=0.0, eps_gap=0.0, slab_kernel="auto", resident="auto", use_graph=True,
-                 stream=None):
+                 criterion="kkt", eps_abs=0.0, eps_gap=0.0, slab_kernel="auto", resident="auto", history=0,
+                 use_graph=True, stream=None):
         L = lib()
         self.m, self.n = int(m), int(n)
         keep, csr, cones, bb, cc = _problem(self.m, self.n, row_ptr, col_idx, val, b, c, n_orth, soc_sizes)
         o = _opts(mu=mu, precision=precision, check_every=check_every, eps=eps, max_iter=max_iter,
                   lanes_row=lanes_row, lanes_col=lanes_col, unroll_row=unroll_row, unroll_col=unroll_col,
                   slabs_row=slabs_row, slabs_col=slabs_col, criterion=criterion, eps_abs=eps_abs,
-                  eps_gap=eps_gap, slab_kernel=slab_kernel, resident=resident, use_graph=use_graph,
-                  stream=stream)
+                  eps_gap=eps_gap, slab_kernel=slab_kernel, resident=resident, history=history,
+                  use_graph=use_graph, stream=stream)
         self.precision = precision
+        self._history_cap = int(history)
         self.nnz = csr.nnz
         h = ctypes.c_void_p()
         _check(L.solver_create(ctypes.byref(csr), _ptr(bb), _ptr(cc), ctypes.byref(cones),
@@ -292,6 +305,18 @@ class Solver:
         _check(lib().solver_time_kernels(self._h, int(iters), ctypes.byref(a), ctypes.byref(b)),
                "solver_time_kernels")
         return a.value, b.value
+
+    def history(self, max_records: int | None = None) -> list:
+        """The residual history (kept when created with history=N > 0): the
+        latest checks of the iteration, oldest first, as dicts with iter,
+        seconds (GPU time since the start) and the residuals."""
+        cap = self._history_cap if max_records is None else int(max_records)
+        if cap <= 0:
+            return []
+        buf = (UvHistory * cap)()
+        cnt = ctypes.c_int32()
+        _check(lib().solver_history(self._h, cap, buf, ctypes.byref(cnt)), "solver_history")
+        return [{k: getattr(buf[i], k) for k, _ in UvHistory._fields_} for i in range(cnt.value)]
 
     def launch_shape(self) -> dict:
         """Lanes and gathers in flight per lane of the row and column passes."""

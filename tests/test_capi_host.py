@@ -37,7 +37,7 @@ def test_library_exports_every_declared_function():
 
 def test_strerror_names_every_code():
     L = S.lib()
-    for code in range(0, -8, -1):
+    for code in range(0, -9, -1):
         assert L.solver_strerror(code).decode() != "unknown error code"
     assert L.solver_strerror(-99).decode() == "unknown error code"
 
@@ -313,3 +313,36 @@ def test_cone_validation_agrees_with_a_plain_check(data):
         assert code not in (S.UV_ECONE, S.UV_EBADCSR, S.UV_EINVAL), (n_orth, sizes, code)
     else:
         assert code == S.UV_ECONE, (n_orth, sizes, code)
+
+
+# ctypes mirrors of the header's structs: every field at the C compiler's
+# offset and the same total size (a field added on one side only would shift
+# every later one and corrupt options silently).
+_MIRRORS = {"uv_csr": S.UvCsr, "uv_cones": S.UvCones, "uv_opts": S.UvOpts,
+            "uv_residuals": S.UvResiduals, "uv_history": S.UvHistory}
+
+
+def test_ctypes_structs_match_the_header(tmp_path):
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc") or shutil.which("cc")
+    if gcc is None:
+        pytest.skip("no host C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "uvadmm.h"', "int main(void) {"]
+    for cname, py in _MIRRORS.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, field, val = ln.split()
+        got[(cname, field)] = int(val)
+    for cname, py in _MIRRORS.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

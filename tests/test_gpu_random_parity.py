@@ -88,6 +88,46 @@ def test_random_problems_match_oracle(inst, mu, opts, warm, data):
 
 
 @SETTINGS
+@given(data=st.data(), mu=st.sampled_from([0.3, 1.0, 2.5]), warm=st.booleans(),
+       precision=st.sampled_from(["fp64", "mixed"]))
+def test_random_resident_problems_match_oracle(data, mu, warm, precision):
+    """The resident path on drawn orthant problems (ragged shapes, emptied
+    rows, any check interval), warm or cold: FP64 at the 1e-9 bar, the mixed
+    form against its own sweep kernels (resident off) at FP32 rounding."""
+    m = data.draw(st.integers(1, 450), "m")
+    n = data.draw(st.integers(1, 900), "n")
+    k = data.draw(st.integers(1, min(4, m)), "k")
+    inst = I.lp_instance(m, n, k, seed=data.draw(st.integers(0, 10_000), "seed"))
+    if m > 2 and data.draw(st.booleans(), "holes"):
+        inst = empty_rows(inst, data.draw(st.lists(st.integers(0, m - 1), max_size=3), "rows"))
+    iters = data.draw(st.integers(1, 60), "iters")
+    ce = data.draw(st.integers(1, 12), "check_every")
+    say(f"resident m={m} n={n} nnz={inst['nnz']} mu={mu} warm={warm} {precision} iters={iters} ce={ce}")
+    start = None
+    if warm:
+        rng = np.random.default_rng(inst["seed"])
+        start = (rng.standard_normal(n), rng.standard_normal(n), rng.standard_normal(n), rng.standard_normal(m))
+    outs = {}
+    for path in ("required", "never") if precision == "mixed" else ("required",):
+        with Solver.from_instance(inst, mu=mu, eps=0.0, check_every=ce, precision=precision, resident=path) as s:
+            assert s.launch_shape()["resident"] == (path == "required")
+            if start is not None:
+                s.set_start(*start)
+            s.iterate(iters)
+            outs[path] = s.solution()
+    if precision == "fp64":
+        orc = oracle.Oracle.from_instance(inst, mu=mu)
+        if start is not None:
+            orc.set_start(*start)
+        orc.iterate(iters)
+        errs = errors(outs["required"], orc.state())
+        assert max(errs.values()) <= 1e-9, errs
+    else:
+        errs = errors(outs["required"], outs["never"])
+        assert max(errs.values()) <= 1e-4, errs
+
+
+@SETTINGS
 @given(data=st.data())
 def test_random_batches_match_oracle(data):
     count = data.draw(st.integers(1, 6), "count")
