@@ -505,7 +505,11 @@ def parametric_block(n_train, n_eval, epochs, train_eps=1e-3, train_cap=20_000, 
         d = cmp[v]
         return {"seconds": d["seconds"], "per_member_s": d["seconds"] / ne,
                 "iters_median": float(np.median(d["iters"])), "iters_mean": float(np.mean(d["iters"])),
-                "iters_total": int(d["iters"].sum()), "converged": int(d["converged"].sum())}
+                "iters_total": int(d["iters"].sum()), "converged": int(d["converged"].sum()),
+                "iters_p90": float(np.percentile(d["iters"], 90)), "iters_max": int(d["iters"].max()),
+                "group_iters": d["group_iters"], "tail_iters": d["tail_iters"], "busy": d["busy"],
+                "handed_over": d["handed_over"], "handover_iters": d["handover_iters"],
+                "ms_per_group_iter": d["seconds"] * 1e3 / max(d["group_iters"], 1)}
 
     out = {
         "workload": f"lp_parametric: m={fam.m} n={fam.n} nnz={fam.row_ptr[-1]}, theta in R^64, "

@@ -216,6 +216,16 @@ int solver_set_start(uv_solver *s, const double *x, const double *z,
 int solver_resume(uv_solver *s, const double *x, const double *z,
                   const double *delta, const double *lambda);
 
+/* Replaces the right-hand side b (m doubles, host; every entry finite, else
+ * UV_EINVAL) of problem eq. prob_primal, keeping A, c, the cones, the
+ * factors F_U, F_V and the device set-up: one handle serves a family of
+ * problems that differ in b.  The iterate belongs to the old b, so the next
+ * iteration needs a new start: solver_iterate returns UV_EINVAL until
+ * solver_set_start or solver_resume is called (with the state of a run on
+ * this b, solver_resume continues that run).  Residual queries evaluate
+ * against the new b. */
+int solver_set_rhs(uv_solver *s, const double *b);
+
 /* Runs up to k iterations (fewer if kkt <= eps_kkt at a check, or max_iter
  * is reached) and waits for them.  Checks happen when the total iteration
  * count is a multiple of check_every.  *done (may be NULL) is set to 1 when
@@ -426,6 +436,15 @@ int family_residuals(uv_family *h, uv_residuals *r);
  * be NULL): x, z, delta (nb x n), lambda (nb x m). */
 int family_solution(uv_family *h, double *x, double *z, double *lambda,
                     double *delta);
+
+/* Iterate of the member in one slot (< nb) into host buffers (any may be
+ * NULL): x, z, delta (n doubles), lambda (m doubles) -- the state that
+ * solver_resume takes, so a member can continue its run on a solver_create
+ * handle of the same A and c (its b set by solver_set_rhs), for instance
+ * once few members are left running and the group's iteration costs more
+ * than the single problem's. */
+int family_member_state(uv_family *h, int32_t slot, double *x, double *z,
+                        double *lambda, double *delta);
 
 /* FP32 rows [z (n) ; lambda (m)] of the nb instances into a DEVICE matrix
  * with row stride ld >= n + m (training data for a learned start). */

@@ -307,6 +307,15 @@ k_fam_from_dev(int len, int B, int nb, const S *__restrict__ src, T *__restrict_
     dst[(size_t)l * ld + off + j] = (T)src[(size_t)j * B + l];
 }
 
+// One instance's column: src[j * B + slot] -> dst[j] (FP64).
+template <typename S>
+__global__ void __launch_bounds__(256)
+k_fam_slot_from_dev(int len, int B, int slot, const S *__restrict__ src, double *__restrict__ dst)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j < len) dst[j] = (double)src[(size_t)j * B + slot];
+}
+
 // u = -lambda/mu for all instances, and per-instance reset.
 template <typename T>
 __global__ void __launch_bounds__(256)
@@ -961,6 +970,29 @@ int family_solution(uv_family *h, double *x, double *z, double *lambda, double *
         else
             k_fam_from_dev<float, double><<<g, 256, 0, st>>>(len, B, nb, (const float *)src, h->stage, (size_t)len, 0);
         if (hipMemcpyAsync(dst, h->stage, 8 * (size_t)len * nb, hipMemcpyDeviceToHost, st) != hipSuccess) return UV_EHIP;
+        return hipStreamSynchronize(st) == hipSuccess ? UV_OK : UV_EHIP;
+    };
+    int rc;
+    if ((rc = get(x, h->X, h->n, false)) != UV_OK) return rc;
+    if ((rc = get(z, h->Z, h->n, false)) != UV_OK) return rc;
+    if ((rc = get(lambda, h->LAM, h->m, true)) != UV_OK) return rc;
+    if ((rc = get(delta, h->D, h->n, true)) != UV_OK) return rc;
+    return UV_OK;
+}
+
+int family_member_state(uv_family *h, int32_t slot, double *x, double *z, double *lambda, double *delta)
+{
+    if (!h || slot < 0 || slot >= h->nb) return UV_EINVAL;
+    hipStream_t st = h->stream;
+    const bool mixed = h->o.precision == UV_MIXED;
+    auto get = [&](double *dst, const void *src, int len, bool f64) -> int {
+        if (!dst) return UV_OK;
+        const unsigned g = blocks_for(len, 256);
+        if (f64 || !mixed)
+            k_fam_slot_from_dev<double><<<g, 256, 0, st>>>(len, h->B, slot, (const double *)src, h->stage);
+        else
+            k_fam_slot_from_dev<float><<<g, 256, 0, st>>>(len, h->B, slot, (const float *)src, h->stage);
+        if (hipMemcpyAsync(dst, h->stage, 8 * (size_t)len, hipMemcpyDeviceToHost, st) != hipSuccess) return UV_EHIP;
         return hipStreamSynchronize(st) == hipSuccess ? UV_OK : UV_EHIP;
     };
     int rc;

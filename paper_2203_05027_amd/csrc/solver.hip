@@ -1011,6 +1011,7 @@ struct uv_solver {
     double *P_res = nullptr;    // FP64 slab partials of the mixed form's checks
     int nblk_row_fused = 0;     // row-residual partial blocks written by the check row pass
     bool resident = false;      // iterate with k_resident (the whole problem in one workgroup's LDS)
+    bool need_start = false;    // b changed (solver_set_rhs): no iteration before a new start
     ResLayout rlay{};
     int res_lr = 1, res_lc = 1;  // lanes per row and per column of k_resident
     HistRec *hist = nullptr;     // residual history ring (opts.history records)
@@ -1930,7 +1931,29 @@ int solver_set_start(uv_solver *s, const double *x, const double *z, const doubl
     if (!s) return UV_EINVAL;
     int rc = upload_state(s, x, z, delta, lambda);
     if (rc != UV_OK) return rc;
+    s->need_start = false;
     return sync_status(s);
+}
+
+int solver_set_rhs(uv_solver *s, const double *b)
+{
+    if (!s || !b) return UV_EINVAL;
+    for (int i = 0; i < s->m; ++i)
+        if (!std::isfinite(b[i])) return UV_EINVAL;
+    hipStream_t st = s->stream;
+    UV_TRY(hipMemcpyAsync(s->b64, b, 8 * (size_t)s->m, hipMemcpyHostToDevice, st));
+    if (s->o.precision == UV_MIXED)
+        k_narrow<float><<<blocks_for(s->m, kWG), kWG, 0, st>>>(s->m, s->b64, (float *)s->b);
+    k_norms<<<1, kWG, 0, st>>>(s->m, s->b64, s->n, s->c64, s->st);
+    UV_TRY(hipGetLastError());
+    int rc = sync_status(s);
+    if (rc != UV_OK) return rc;
+    // the residuals of the last check belong to the old b
+    s->st_host->check_iter = -1;
+    UV_TRY(hipMemcpyAsync(s->st, s->st_host, sizeof(DevStatus), hipMemcpyHostToDevice, st));
+    UV_TRY(hipStreamSynchronize(st));
+    s->need_start = true;
+    return UV_OK;
 }
 
 int solver_resume(uv_solver *s, const double *x, const double *z, const double *delta, const double *lambda)
@@ -1938,6 +1961,7 @@ int solver_resume(uv_solver *s, const double *x, const double *z, const double *
     if (!s) return UV_EINVAL;
     int rc = upload_state(s, x, z, delta, lambda);
     if (rc != UV_OK) return rc;
+    s->need_start = false;
     launch_row(s, s->stream, 2);
     UV_TRY(hipGetLastError());
     return sync_status(s);
@@ -1945,7 +1969,7 @@ int solver_resume(uv_solver *s, const double *x, const double *z, const double *
 
 int solver_iterate(uv_solver *s, int64_t k, int32_t *done)
 {
-    if (!s || k < 0) return UV_EINVAL;
+    if (!s || k < 0 || s->need_start) return UV_EINVAL;
     if (done) *done = 0;
     if (!s->st_host->done) {
         int64_t left = k;
@@ -2248,7 +2272,7 @@ int solver_solve_noalloc(const uv_csr *A, const double *b, const double *c, cons
 int solver_time_kernels(uv_solver *s, int32_t iters, double *ms_col, double *ms_row)
 {
     if (!s || iters < 1 || !ms_col || !ms_row) return UV_EINVAL;
-    if (s->st_host->done) return UV_EINVAL;   // a stopped solver launches nothing to time
+    if (s->st_host->done || s->need_start) return UV_EINVAL;   // a stopped solver launches nothing to time
     std::vector<hipEvent_t> ev(3 * (size_t)iters, nullptr);
     int rc = UV_OK;
     for (auto &e : ev)

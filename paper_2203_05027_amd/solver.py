@@ -118,6 +118,8 @@ def lib():
     L.solver_time_kernels.restype = ctypes.c_int
     L.solver_launch_shape.argtypes = [P, ctypes.POINTER(i32)]
     L.solver_launch_shape.restype = ctypes.c_int
+    L.solver_set_rhs.argtypes = [P, P]
+    L.solver_set_rhs.restype = ctypes.c_int
     L.solver_history.argtypes = [P, i32, ctypes.POINTER(UvHistory), ctypes.POINTER(i32)]
     L.solver_history.restype = ctypes.c_int
     _lib = L
@@ -272,6 +274,11 @@ class Solver:
         n, m = self.n, self.m
         args = (_f64(x, n), _f64(z, n), _f64(delta, n), _f64(lam, m))
         _check(lib().solver_set_start(self._h, *[_ptr(a) for a in args]), "solver_set_start")
+
+    def set_rhs(self, b):
+        """New right-hand side (same A, c, cones); call set_start or resume
+        before iterating again."""
+        _check(lib().solver_set_rhs(self._h, _ptr(_f64(b, self.m))), "solver_set_rhs")
 
     def resume(self, x=None, z=None, delta=None, lam=None):
         """Continue a run from a state returned by solution() (checkpoint)."""
@@ -482,6 +489,8 @@ def _bind_family(L):
     L.family_residuals.restype = ctypes.c_int
     L.family_solution.argtypes = [P, P, P, P, P]
     L.family_solution.restype = ctypes.c_int
+    L.family_member_state.argtypes = [P, i32, P, P, P, P]
+    L.family_member_state.restype = ctypes.c_int
     L.family_solution_device.argtypes = [P, P, i64]
     L.family_solution_device.restype = ctypes.c_int
     L.family_destroy.argtypes = [P]
@@ -595,6 +604,15 @@ class Family:
         nb, n, m = self.nb, self.n, self.m
         x, z, d, lam = np.empty((nb, n)), np.empty((nb, n)), np.empty((nb, n)), np.empty((nb, m))
         _check(lib().family_solution(self._h, _ptr(x), _ptr(z), _ptr(lam), _ptr(d)), "family_solution")
+        return {"x": x, "z": z, "delta": d, "lambda": lam}
+
+    def member_state(self, slot: int) -> dict:
+        """The iterate of the member in one slot (the state Solver.resume
+        takes to continue its run)."""
+        n, m = self.n, self.m
+        x, z, d, lam = np.empty(n), np.empty(n), np.empty(n), np.empty(m)
+        _check(lib().family_member_state(self._h, int(slot), _ptr(x), _ptr(z), _ptr(lam), _ptr(d)),
+               "family_member_state")
         return {"x": x, "z": z, "delta": d, "lambda": lam}
 
     def solution_device(self, dev_ptr: int, ld: int):

@@ -15,7 +15,12 @@ Pipeline, every numeric step in the library's kernels:
 Members stream through the family solver's B slots: a slot whose member
 stops takes the next pending member at once (family_refill), so the time to
 solve a set of members follows their total iteration count rather than the
-slowest member of each group of B.
+slowest member of each group of B.  Once no member is pending and only a few
+still run, one group iteration (all B slots' traffic) costs more than those
+few members' iterations on the single-problem solver: the remaining members
+then continue their runs there, one after another, from their exact state
+(family_member_state -> solver_set_rhs + solver_resume), so a slow member
+does not hold the whole group.
 """
 from __future__ import annotations
 
@@ -24,7 +29,7 @@ import time
 import numpy as np
 
 from . import learn
-from .solver import Family
+from .solver import Family, Solver
 
 
 class _Rhs:
@@ -141,7 +146,7 @@ class WarmStart:
 
     # 4. warm vs cold ---------------------------------------------------
     def solve_stream(self, b_all, Yhat=None, parts="both", eps=1e-4, max_iter=100_000, chunk=50,
-                     keep=None):
+                     keep=None, tail_slots=16):
         """Solves every member (row of the host array b_all) through the B
         slots, refilling a slot as soon as its member stops.  With Yhat
         (device FP32 rows [x ; lambda], one per member) a member starts from
@@ -150,12 +155,25 @@ class WarmStart:
         keep: a device FP32 tensor (len(b_all) x (n + m)) that receives each
         member's [z ; lambda] when it stops.  Returns {"iters", "converged",
         "seconds"}; the time runs from the first right-hand side to the last
-        stop (predictions are made beforehand and timed by the caller)."""
+        stop (predictions are made beforehand and timed by the caller).
+        tail_slots: once no member is pending and at most this many still
+        run, they continue on the single-problem solver (0: never).  One
+        group iteration of the 256-slot family on the 5e4 x 1e5 LP takes
+        0.46 ms against 17 us for an iteration of one member alone, so a
+        member moved there costs 1/27 of a group iteration per iteration;
+        16 leaves room for the per-member hand-over (a state copy each way).
+        Also returned: "group_iters" (iterations of the B-slot group),
+        "busy" (the fraction of slot-iterations that served a member),
+        "tail_iters" (group iterations after the last member got a slot),
+        "handed_over" (members finished on the single-problem solver) and
+        "handover_iters" (their iterations there)."""
         torch = self.torch
         N = len(b_all)
         D = self.D
         iters = np.zeros(N, np.int64)
         conv = np.zeros(N, bool)
+        tail = self._tail_solver(b_all[0:1][0], eps) if tail_slots > 0 else None
+        handed, handed_iters = 0, 0
         with self._family(eps, max_iter) as F:
             buf = (torch.empty((self.B, D), dtype=torch.float32, device="cuda") if keep is not None else None)
             torch.cuda.synchronize()
@@ -167,9 +185,13 @@ class WarmStart:
             owner = list(range(nb))                  # member in each slot (None: idle)
             warm = [Yhat is not None] * nb           # whether the slot's member started warm
             nxt, retry = nb, []
+            group_iters, tail_iters, busy_slot_iters = 0, 0, 0
             while True:
                 F.iterate(chunk)
                 res = F.residuals()
+                group_iters += chunk
+                if nxt >= N and not retry:
+                    tail_iters += chunk
                 free, stopped = [], []
                 for sl in range(nb):
                     mem = owner[sl]
@@ -181,6 +203,7 @@ class WarmStart:
                         continue
                     stopped.append(sl)
                     iters[mem] += r["iter"]
+                    busy_slot_iters += r["iter"]
                     ok = r["status"] == "converged"
                     if not ok and warm[sl]:
                         retry.append(mem)            # the cold fallback
@@ -195,6 +218,7 @@ class WarmStart:
                     owner[sl] = None
                 # pending members in order (contiguous prediction rows), then cold retries
                 take = min(len(free), N - nxt)
+                entered = bool(take) or bool(retry and free)
                 if take:
                     sl_new = free[:take]
                     ptr = Yhat[nxt].data_ptr() if Yhat is not None else None
@@ -211,12 +235,64 @@ class WarmStart:
                         owner[sl], warm[sl] = mem, False
                 if all(o is None for o in owner) and nxt >= N and not retry:
                     break
+                running = [sl for sl in range(nb) if owner[sl] is not None]
+                # (not in a pass that just refilled slots: their residuals
+                # above belong to the members that left)
+                if tail is not None and not entered and nxt >= N and not retry and len(running) <= tail_slots:
+                    for sl in running:  # the last few continue alone
+                        mem = owner[sl]
+                        done_here = res[sl]["iter"]
+                        busy_slot_iters += done_here
+                        ok, more = self._finish_alone(tail, F, sl, b_all[mem:mem + 1][0], eps,
+                                                      max_iter - done_here, warm[sl], max_iter)
+                        iters[mem] += done_here + more
+                        conv[mem] = ok
+                        handed += 1
+                        handed_iters += more
+                        if keep is not None:
+                            st = tail.solution()
+                            row = np.concatenate([st["z"], st["lambda"]]).astype(np.float32)
+                            keep[mem].copy_(torch.from_numpy(row))
+                        owner[sl] = None
+                    break
             torch.cuda.synchronize()
             seconds = time.perf_counter() - t0
-        return {"iters": iters, "converged": conv, "seconds": seconds}
+        if tail is not None:
+            tail.close()
+        return {"iters": iters, "converged": conv, "seconds": seconds, "group_iters": group_iters,
+                "busy": busy_slot_iters / max(group_iters * self.B, 1), "tail_iters": tail_iters,
+                "handed_over": handed, "handover_iters": handed_iters}
+
+    def _tail_solver(self, b0, eps):
+        """The single-problem solver that takes over the last running
+        members (same A, c, options; its b is set per member)."""
+        f = self.fam
+        return Solver(f.m, f.n, f.row_ptr, f.col_idx, f.val, b0, f.c, f.n, (), eps=eps, **self.opts)
+
+    @staticmethod
+    def _finish_alone(tail, F, slot, b, eps, left, warm, max_iter):
+        """Continues the member in `slot` on the single-problem solver from
+        its current state for at most `left` more iterations; a warm-started
+        member left unconverged is re-solved cold (its iterations add up).
+        Returns (converged, iterations run here)."""
+        st = F.member_state(slot)
+        tail.set_rhs(b)
+        tail.resume(st["x"], st["z"], st["delta"], st["lambda"])
+        more = 0
+        if left > 0:
+            tail.iterate(left)
+            more = tail.residuals()["iter"]
+        ok = tail.residuals()["status"] == "converged"
+        if not ok and warm:  # the cold fallback
+            tail.set_start()
+            tail.iterate(max_iter)
+            r = tail.residuals()
+            more += r["iter"]
+            ok = r["status"] == "converged"
+        return ok, more
 
     def compare_stream(self, thetas, eps=1e-4, max_iter=100_000, parts=("both",), projection=False,
-                       chunk=50):
+                       chunk=50, tail_slots=16):
         """Cold and learned starts of the same members through the same
         streaming driver and slots (see solve_stream).  Variants: "cold", one
         per entry of parts ("both", "primal" or "dual" halves of the
@@ -228,7 +304,8 @@ class WarmStart:
         N = len(thetas)
         b_all = np.ascontiguousarray(self.fam.b_many(thetas))
         keep = torch.empty((N, self.D), dtype=torch.float32, device="cuda") if projection else None
-        out = {"cold": self.solve_stream(b_all, eps=eps, max_iter=max_iter, chunk=chunk, keep=keep)}
+        out = {"cold": self.solve_stream(b_all, eps=eps, max_iter=max_iter, chunk=chunk, keep=keep,
+                                         tail_slots=tail_slots)}
         self.log(f"stream cold: {out['cold']['seconds']:.2f} s, median {int(np.median(out['cold']['iters']))}")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -236,7 +313,8 @@ class WarmStart:
         torch.cuda.synchronize()
         t_pred = time.perf_counter() - t0
         for p in parts:
-            r = self.solve_stream(b_all, Yhat=Yhat, parts=p, eps=eps, max_iter=max_iter, chunk=chunk)
+            r = self.solve_stream(b_all, Yhat=Yhat, parts=p, eps=eps, max_iter=max_iter, chunk=chunk,
+                                  tail_slots=tail_slots)
             r["seconds"] += t_pred
             out[p] = r
             self.log(f"stream {p}: {r['seconds']:.2f} s, median {int(np.median(r['iters']))}")
@@ -248,7 +326,8 @@ class WarmStart:
             learn.add_row_vector(coef, neg_mb)
             Yp = learn.gemm(coef, self.basis)
             learn.add_row_vector(Yp, self.mean)
-            out["projection"] = self.solve_stream(b_all, Yhat=Yp, eps=eps, max_iter=max_iter, chunk=chunk)
+            out["projection"] = self.solve_stream(b_all, Yhat=Yp, eps=eps, max_iter=max_iter, chunk=chunk,
+                                                  tail_slots=tail_slots)
             self.log(f"stream projection: median {int(np.median(out['projection']['iters']))}")
         out["predict_seconds"] = t_pred
         return out

@@ -232,3 +232,72 @@ def test_refill_rejects_running_and_repeated_slots(small_family):
             F.refill([3], a["b"][None, :])                 # beyond the current members
         F.refill([0, 2], np.stack([a["b"]] * 2))
         assert F.iterate(5) == 2
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_member_state_is_the_members_row_of_the_solution(small_family, precision):
+    fam = small_family
+    insts = family_members(fam, [fam.theta(4000 + i, p=8) for i in range(7)])
+    with _fam(fam, precision=precision, eps=0.0, check_every=10) as F:
+        F.set_rhs(np.stack([i["b"] for i in insts]))
+        F.iterate(130)
+        sol = F.solution()
+        for sl in (0, 3, 6):
+            st = F.member_state(sl)
+            for k in KEYS:
+                assert np.array_equal(st[k], sol[k][sl]), (sl, k)
+        with pytest.raises(Exception):
+            F.member_state(7)
+
+
+def test_member_continues_on_the_single_problem_solver(small_family):
+    """Hand-over of a running member: its state (family_member_state) taken
+    into a solver_create handle of the same A and c whose b is the member's
+    (solver_set_rhs + solver_resume) continues the run: after 150 more
+    iterations it agrees with the member kept in the family, and with the
+    oracle run on the member alone for all 270 iterations (FP64, 1e-9)."""
+    from paper_2203_05027_amd.solver import Solver
+    fam = small_family
+    insts = family_members(fam, [fam.theta(4100 + i, p=8) for i in range(5)])
+    with _fam(fam, precision="fp64", eps=0.0, check_every=10) as F:
+        F.set_rhs(np.stack([i["b"] for i in insts]))
+        F.iterate(120)
+        st = F.member_state(2)
+        F.iterate(150)
+        kept = {k: v[2].copy() for k, v in F.solution().items()}
+    other = insts[0]
+    with Solver(fam.m, fam.n, fam.row_ptr, fam.col_idx, fam.val, other["b"], fam.c, fam.n, (),
+                eps=0.0, check_every=10) as s:
+        s.set_rhs(insts[2]["b"])
+        s.resume(st["x"], st["z"], st["delta"], st["lambda"])
+        s.iterate(150)
+        moved = s.solution()
+    o = oracle.Oracle.from_instance(insts[2])
+    o.iterate(270)
+    ref = o.state()
+    for k in KEYS:
+        assert rel(moved[k], kept[k]) <= 1e-9, (k, rel(moved[k], kept[k]))
+        assert rel(moved[k], ref[k]) <= 1e-9, (k, rel(moved[k], ref[k]))
+
+
+def test_stream_hand_over_keeps_every_member_and_its_count(small_family):
+    """The streaming driver with the last running members handed to the
+    single-problem solver against the driver without it: every member
+    converges in both, and each member's iteration count agrees to within
+    two checks (the hand-over continues the same iteration; only the order
+    of FP32 additions differs)."""
+    import torch  # noqa: F401
+    from paper_2203_05027_amd.warmstart import WarmStart
+    fam = small_family
+    ws = WarmStart(fam, k=8, hidden=(32, 32), B=64, log=say)
+    thetas = np.stack([fam.theta(5000 + i, p=8) for i in range(150)])
+    b_all = np.ascontiguousarray(fam.b_many(thetas))
+    with_h = ws.solve_stream(b_all, eps=1e-4, max_iter=100_000, tail_slots=16)
+    without = ws.solve_stream(b_all, eps=1e-4, max_iter=100_000, tail_slots=0)
+    say(f"hand-over: {with_h['handed_over']} members, {with_h['handover_iters']} iterations alone; "
+        f"group iterations {with_h['group_iters']} vs {without['group_iters']}; "
+        f"{with_h['seconds']:.2f} s vs {without['seconds']:.2f} s")
+    assert with_h["converged"].all() and without["converged"].all()
+    assert without["handed_over"] == 0 and with_h["handed_over"] >= 1
+    assert np.abs(with_h["iters"] - without["iters"]).max() <= 20
+    assert with_h["group_iters"] <= without["group_iters"]
