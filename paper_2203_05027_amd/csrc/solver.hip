@@ -581,10 +581,6 @@ k_res_col_slab(int n, const double *__restrict__ P, const double *__restrict__ c
 __device__ bool finish_check(const double (&s)[10], const double (&nrm)[4], long long it, double eps,
                              double eps_abs, double eps_gap, int crit, int decide, DevStatus *st, HistRing hist)
 {
-    // a check replayed after the run stopped (the rest of a graph launch)
-    // repeats the stopping check: it leaves the status, the values and the
-    // history as they are
-    if (decide && st->done) return true;
     const double rp = sqrt(s[0]) / (1.0 + sqrt(nrm[0]));
     const double rd = sqrt(s[3]) / (1.0 + sqrt(nrm[1]));
     const double cz = s[4], bl = s[1], cx = s[5];
@@ -698,6 +694,10 @@ k_finalize(int nrow, const double *__restrict__ prow, int ncol, const double *__
     double s[10];
     uv::block_sum_max<6, 4>(v, w, s, 1);
     if (threadIdx.x != 0) return;
+    // a check replayed after the run stopped (the rest of a graph launch)
+    // repeats the stopping check: it leaves the status, the values and the
+    // history as they are
+    if (decide && st->done) return;
     const double nrm[4] = {st->bnorm2, st->cnorm2, st->binf, st->cinf};
     finish_check(s, nrm, st->iter, eps, eps_abs, eps_gap, crit, decide, st, hist);
 }
@@ -841,12 +841,14 @@ __device__ __forceinline__ void res_check(int m, int n, int Lr, int Lc, const in
 #pragma unroll
         for (int k = 0; k < 10; ++k) red[k][w] = v[k];
     __syncthreads();
-    if (tid == 0) {
-        for (int k = 0; k < 10; ++k) {
-            double a = red[k][0];
-            for (int q = 1; q < NT / 64; ++q) a = k < 6 ? a + red[k][q] : fmax(a, red[k][q]);
-            sv[k] = a;
+    if (w == 0) {  // lane k < 10 of the first wavefront folds value k over the wavefronts, in order
+        double a = 0.0;
+        if (lane < 10) {
+            a = red[lane][0];
+            for (int q = 1; q < NT / 64; ++q) a = lane < 6 ? a + red[lane][q] : fmax(a, red[lane][q]);
         }
+#pragma unroll
+        for (int k = 0; k < 10; ++k) sv[k] = __shfl(a, k, 64);
     }
 }
 
@@ -917,6 +919,7 @@ k_resident(int m, int n, ResLayout L, int Lr, int Lc, const int *__restrict__ rp
     const double inv_mu = 1.0 / mu;
     const int gc = tid / Lc, lc = tid % Lc, gr = tid / Lr, lr = tid % Lr;
     long long done = 0;
+    int to_check = check_every - (int)(it0 % check_every);  // iterations left to the next check
     for (long long t = 0; t < iters; ++t) {
         for (int j = gc; j < n; j += NT / Lc) {
             const int k0 = cps[j], k1 = cps[j + 1];
@@ -945,7 +948,8 @@ k_resident(int m, int n, ResLayout L, int Lr, int Lc, const int *__restrict__ rp
         __syncthreads();
         done = t + 1;
         const long long itn = it0 + done;
-        if (itn % check_every != 0) continue;
+        if (--to_check != 0) continue;
+        to_check = check_every;
         double sv[10];
         res_check<T>(m, n, Lr, Lc, rps, cis, cps, ris, cva, cvc, xs, zs, ds, ls, b64, c64, red, sv);
         if (tid == 0) {
