@@ -31,7 +31,7 @@ def small_family():
     return I.ParametricFamily(m=300, n=600, k=5, p=8, seed=7)
 
 
-@pytest.mark.parametrize("B,nb", [(64, 5), (128, 70)])
+@pytest.mark.parametrize("B,nb", [(64, 5), (128, 70), (192, 150), (512, 300)])
 def test_fp64_family_matches_oracle(small_family, B, nb):
     fam = small_family
     thetas = [fam.theta(1000 + i, p=8) for i in range(nb)]
