@@ -301,3 +301,32 @@ def test_stream_hand_over_keeps_every_member_and_its_count(small_family):
     assert without["handed_over"] == 0 and with_h["handed_over"] >= 1
     assert np.abs(with_h["iters"] - without["iters"]).max() <= 20
     assert with_h["group_iters"] <= without["group_iters"]
+
+
+def test_hand_over_falls_back_to_a_cold_solve(small_family):
+    """A warm-started member handed to the single-problem solver that does
+    not converge within the iterations it has left is solved again from the
+    zero start, as in the group: its iterations add up, and the cold part
+    is exactly a fresh handle's count."""
+    import torch  # noqa: F401
+    from paper_2203_05027_amd.solver import Solver
+    from paper_2203_05027_amd.warmstart import WarmStart
+    fam = small_family
+    ws = WarmStart(fam, k=8, hidden=(32, 32), B=64, log=say)
+    insts = family_members(fam, [fam.theta(6000 + i, p=8) for i in range(3)])
+    b = np.stack([i["b"] for i in insts])
+    tail = ws._tail_solver(b[0], 1e-4)
+    try:
+        with _fam(fam, precision="mixed", eps=1e-4, check_every=10) as F:
+            F.set_rhs(b)
+            F.iterate(20)
+            ok, more = ws._finish_alone(tail, F, 1, b[1], 1e-4, 10, True, 100_000)
+    finally:
+        tail.close()
+    with Solver(fam.m, fam.n, fam.row_ptr, fam.col_idx, fam.val, b[1], fam.c, fam.n, (), eps=1e-4,
+                precision="mixed", check_every=10) as s:
+        while not s.iterate(5000):
+            pass
+        cold = s.residuals()["iter"]
+    say(f"hand-over fallback: {more} iterations alone, a fresh cold solve {cold}")
+    assert ok and more == 10 + cold
