@@ -66,6 +66,39 @@ __device__ __forceinline__ T group_sum(T v)
     return v;
 }
 
+// A wavefront's sum (MAX = false) or maximum of a double, in lane 0: pairs
+// within quads, then the other quad of each half row and the other half of
+// each row of 16 lanes (DPP moves, no LDS traffic), then the four row totals
+// read across the wavefront and combined as (r0 + r1) + (r2 + r3).  A fixed
+// order, so results are bitwise reproducible (not the same order as
+// group_sum<64>).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane), hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <bool MAX>
+__device__ __forceinline__ double wave_fold0(double v)
+{
+    auto op = [](double a, double b) { return MAX ? fmax(a, b) : a + b; };
+    v = op(v, dpp_move<0xB1>(v));   // quad_perm 1,0,3,2: lane ^ 1
+    v = op(v, dpp_move<0x4E>(v));   // quad_perm 2,3,0,1: lane ^ 2
+    v = op(v, dpp_move<0x141>(v));  // row_half_mirror: the other quad of the half row
+    v = op(v, dpp_move<0x140>(v));  // row_mirror: the other half of the row
+    return op(op(read_lane(v, 0), read_lane(v, 16)), op(read_lane(v, 32), read_lane(v, 48)));
+}
+
 // Workgroup sum of K doubles, deterministic (wave butterfly, then thread 0
 // adds the per-wave totals in wave order).  Thread 0 writes component k to
 // out[k * stride].

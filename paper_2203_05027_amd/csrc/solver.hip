@@ -832,11 +832,9 @@ __device__ __forceinline__ void res_check(int m, int n, int Lr, int Lc, const in
         }
     }
 #pragma unroll
-    for (int k = 0; k < 6; ++k) v[k] = uv::group_sum<64>(v[k]);
+    for (int k = 0; k < 6; ++k) v[k] = uv::wave_fold0<false>(v[k]);
 #pragma unroll
-    for (int k = 6; k < 10; ++k)
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v[k] = fmax(v[k], __shfl_xor(v[k], off, 64));
+    for (int k = 6; k < 10; ++k) v[k] = uv::wave_fold0<true>(v[k]);
     if (lane == 0)
 #pragma unroll
         for (int k = 0; k < 10; ++k) red[k][w] = v[k];
