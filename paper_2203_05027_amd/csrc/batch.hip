@@ -44,8 +44,7 @@ struct BInst {
 template <typename T>
 __device__ __forceinline__ T group_sum_rt(T v, int L)
 {
-    for (int off = L >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, L);
-    return v;
+    return uv::lane_sum<T>(v, L);
 }
 
 // Sum over the workgroup (blockDim.x a multiple of 64), deterministic;

@@ -55,15 +55,42 @@ __device__ __forceinline__ double kkt_of(double rp, double rd, double rg)
 constexpr int kWG = 256;      // threads per workgroup for every sweep kernel
 constexpr int kWave = 64;     // CDNA wavefront width
 
-// Sum over the L consecutive lanes of a group (L a power of two <= 64); the
-// butterfly leaves the total in every lane of the group.  A fixed pattern,
-// so results are bitwise reproducible.
+// v of lane ^ 1 (CTRL 0xB1) or lane ^ 2 (CTRL 0x4E): a DPP quad permutation,
+// a register move with no LDS traffic.
+template <int CTRL>
+__device__ __forceinline__ float dpp_quad(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF,
+                                                                   false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_quad(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the L consecutive lanes of a group (L a power of two <= 64, a
+// run-time value; every lane of a group active or none); the butterfly,
+// widest offset first, leaves the total in every lane of the group.  The
+// offsets 2 and 1 are DPP quad moves, the wider ones cross-lane permutes:
+// the same pairs and order either way, so results are bitwise reproducible.
+template <typename T>
+__device__ __forceinline__ T lane_sum(T v, int L)
+{
+    for (int off = L >> 1; off >= 4; off >>= 1) v += __shfl_xor(v, off, L);
+    if (L >= 4) v += dpp_quad<0x4E>(v);
+    if (L >= 2) v += dpp_quad<0xB1>(v);
+    return v;
+}
+
 template <int L, typename T>
 __device__ __forceinline__ T group_sum(T v)
 {
-#pragma unroll
-    for (int off = L / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, L);
-    return v;
+    return lane_sum<T>(v, L);
 }
 
 // A wavefront's sum (MAX = false) or maximum of a double, in lane 0: pairs

@@ -758,9 +758,7 @@ __device__ __forceinline__ T lds_dot(int k0, int k1, int lane, int L, const unsi
         a3 += (T)val[k + 3 * L] * (T)vec[j3];
     }
     for (; k < k1; k += L) a0 += (T)val[k] * (T)vec[idx[k]];
-    T a = (a0 + a1) + (a2 + a3);
-    for (int off = L >> 1; off > 0; off >>= 1) a += __shfl_xor(a, off, L);
-    return a;
+    return uv::lane_sum<T>((a0 + a1) + (a2 + a3), L);
 }
 
 // Two sums of lds_dot over the same entries (A z and A x of a check row):
@@ -785,12 +783,8 @@ __device__ __forceinline__ void lds_dot2(int k0, int k1, int lane, int L, const 
         a0 += w * (double)v1[j];
         b0 += w * (double)v2[j];
     }
-    s1 = a0 + a1;
-    s2 = b0 + b1;
-    for (int off = L >> 1; off > 0; off >>= 1) {
-        s1 += __shfl_xor(s1, off, L);
-        s2 += __shfl_xor(s2, off, L);
-    }
+    s1 = uv::lane_sum<double>(a0 + a1, L);
+    s2 = uv::lane_sum<double>(b0 + b1, L);
 }
 
 // The FP64 residual check of the resident kernel (every thread calls it):
