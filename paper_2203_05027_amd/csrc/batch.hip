@@ -320,11 +320,16 @@ k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__
                 if (j < n && lc == 0) col_update(j, end - beg, atu, d, zj, cj);
             }
             __syncthreads();
-            // row pass: q = A x, lambda update, u
+            // row pass: q = A x, lambda update, u.  At a check iteration the
+            // row pass forms A x and A z in FP64 with the FP64 values of A
+            // (the check's row sums) and the iteration takes its q from that
+            // A x, so the check adds no second row product.
+            const bool chk = (it + 1) % check_every == 0 || (max_iter > 0 && it + 1 >= max_iter);
+            double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
             for (int ib = 0; ib < m; ib += Gr) {
                 const int i = ib + gr;
                 T q = 0, fi = 0, bi = 0;
-                double l0 = 0.0;
+                double l0 = 0.0, qz = 0.0, qx = 0.0;
                 if (i < m) {
                     const int beg = rp[r0 + i], end = rp[r0 + i + 1];
                     if (lr == 0) {
@@ -332,37 +337,34 @@ k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__
                         bi = b[r0 + i];
                         l0 = lam[r0 + i];
                     }
-                    q = seg_sum<4, T>(beg, end, lr, Lr, cl, va, xs);
+                    if (chk) seg_sum2<4>(beg, end, lr, Lr, cl, va64, zi, xs, qz, qx);
+                    else q = seg_sum<4, T>(beg, end, lr, Lr, cl, va, xs);
                 }
-                q = group_sum_rt(q, Lr);
+                if (chk) {
+                    qz = group_sum_rt(qz, Lr);
+                    qx = group_sum_rt(qx, Lr);
+                    q = (T)qx;
+                } else {
+                    q = group_sum_rt(q, Lr);
+                }
                 if (i < m && lr == 0) {
                     const T e = fi * (bi - q);
                     const double li = l0 - mu * (double)e;
                     lam[r0 + i] = li;
                     us[i] = (T)((double)e - li * inv_mu);
+                    if (chk) {
+                        const double bd = b64[r0 + i];
+                        a[0] += (qz - bd) * (qz - bd);
+                        a[1] += bd * li;
+                        a[2] += (qx - bd) * (qx - bd);
+                    }
                 }
             }
             __syncthreads();
             ++it;
-            if (it % check_every == 0 || (max_iter > 0 && it >= max_iter)) {
-                // FP64 residuals at (z, lambda, delta) with the FP64 values of A
-                double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-                for (int ib = 0; ib < m; ib += Gr) {
-                    const int i = ib + gr;
-                    double qz = 0.0, qx = 0.0;
-                    if (i < m) {
-                        const int beg = rp[r0 + i], end = rp[r0 + i + 1];
-                        seg_sum2<4>(beg, end, lr, Lr, cl, va64, zi, xs, qz, qx);
-                    }
-                    qz = group_sum_rt(qz, Lr);
-                    qx = group_sum_rt(qx, Lr);
-                    if (i < m && lr == 0) {
-                        const double bi = b64[r0 + i];
-                        a[0] += (qz - bi) * (qz - bi);
-                        a[1] += bi * lam[r0 + i];
-                        a[2] += (qx - bi) * (qx - bi);
-                    }
-                }
+            if (chk) {
+                // FP64 residuals at (z, lambda, delta) with the FP64 values of A:
+                // the row sums came with the row pass, the column sums here
                 auto col_res = [&](int j, double atl) {
                     const double r = atl + c64[c0 + j] - delta[c0 + j];
                     a[3] += r * r;
