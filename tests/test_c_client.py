@@ -1,5 +1,7 @@
 """A plain C program against include/uvadmm.h and libuvadmm.so: it builds
-and links on the CPU; on a GPU it solves a small LP to its known optimum."""
+and links on the CPU; on a GPU it solves a small LP to its known optimum,
+reads the run's residual history and solves again on the same handle with
+a new right-hand side."""
 import os
 import subprocess
 
