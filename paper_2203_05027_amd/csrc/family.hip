@@ -203,6 +203,70 @@ k_fam_res_row(int m, int B, const int *__restrict__ rp, const int *__restrict__ 
             part[((size_t)blk * 3 + k) * B + l] = ((s[k][0][lane] + s[k][1][lane]) + s[k][2][lane]) + s[k][3][lane];
 }
 
+// The row pass of a check iteration, on the grid of k_fam_res_row: each
+// row's A z and A x in FP64 (FP64 values of A, the same sums in the same
+// order as k_fam_res_row), the iteration's lambda and u updates from that
+// A x (rounded to the sweep type), and the row partials of the check with
+// the updated lambda -- one pass where the row pass and k_fam_res_row took
+// two.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_fam_row_check(int m, int B, const int *__restrict__ rp, const int *__restrict__ ci,
+                const double *__restrict__ va, const T *__restrict__ X, const T *__restrict__ Z,
+                const T *__restrict__ BV, const double *__restrict__ BV64, const T *__restrict__ fu,
+                double *__restrict__ LAM, T *__restrict__ U, const FInst *__restrict__ inst, double mu,
+                double inv_mu, FShared *sh, double *__restrict__ part)
+{
+    if (sh->active == 0) return;
+    __shared__ double s[3][4][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int blk = blockIdx.x % kResBlocks, l = (blockIdx.x / kResBlocks) * 64 + lane;
+    if (blockIdx.x == 0 && threadIdx.x == 0) sh->iter += 1;
+    const bool run = inst[l].status == UV_STATUS_RUNNING;
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int i = blk * 4 + w; i < m; i += kResBlocks * 4) {
+        const int beg = rp[i], end = rp[i + 1];
+        double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0, x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0;
+        int k = beg;
+        for (; k + 3 < end; k += 4) {
+            const size_t o0 = (size_t)ci[k] * B + l, o1 = (size_t)ci[k + 1] * B + l;
+            const size_t o2 = (size_t)ci[k + 2] * B + l, o3 = (size_t)ci[k + 3] * B + l;
+            const double v0 = va[k], v1 = va[k + 1], v2 = va[k + 2], v3 = va[k + 3];
+            z0 += v0 * (double)Z[o0];
+            z1 += v1 * (double)Z[o1];
+            z2 += v2 * (double)Z[o2];
+            z3 += v3 * (double)Z[o3];
+            x0 += v0 * (double)X[o0];
+            x1 += v1 * (double)X[o1];
+            x2 += v2 * (double)X[o2];
+            x3 += v3 * (double)X[o3];
+        }
+        for (; k < end; ++k) {
+            const size_t o = (size_t)ci[k] * B + l;
+            z0 += va[k] * (double)Z[o];
+            x0 += va[k] * (double)X[o];
+        }
+        const double qz = (z0 + z1) + (z2 + z3), qx = (x0 + x1) + (x2 + x3);
+        const size_t o = (size_t)i * B + l;
+        double li = LAM[o];
+        if (run) {
+            const T e = fu[i] * (BV[o] - (T)qx);
+            li = li - mu * (double)e;
+            LAM[o] = li;
+            U[o] = (T)((double)e - li * inv_mu);
+        }
+        const double bi = BV64[o];
+        a[0] += (qz - bi) * (qz - bi);
+        a[1] += bi * li;
+        a[2] += (qx - bi) * (qx - bi);
+    }
+    for (int k = 0; k < 3; ++k) s[k][w][lane] = a[k];
+    __syncthreads();
+    if (w == 0)
+        for (int k = 0; k < 3; ++k)
+            part[((size_t)blk * 3 + k) * B + l] = ((s[k][0][lane] + s[k][1][lane]) + s[k][2][lane]) + s[k][3][lane];
+}
+
 // Residual partials over columns: ||A'lambda + c - delta||^2, c'z (same
 // grid and order as the row partials).
 template <typename T>
@@ -583,12 +647,14 @@ void fam_iteration_t(uv_family *h, hipStream_t st, bool check)
     k_fam_col<T><<<fam_blocks(h->n, ng), 256, 0, st>>>(
         h->n, h->B, h->cp, h->ri, (const T *)h->vc, (const T *)h->U, (T *)h->X, (T *)h->Z, h->D, (const T *)h->c,
         h->inst, mu, im, h->sh);
-    k_fam_row<T><<<fam_blocks(h->m, ng), 256, 0, st>>>(
-        h->m, h->B, h->rp, h->ci, (const T *)h->va, (const T *)h->X, (const T *)h->BV, (const T *)h->fu, h->LAM,
-        (T *)h->U, h->inst, mu, im, h->sh);
-    if (check) {
-        k_fam_res_row<T><<<kResBlocks * (h->B / 64), 256, 0, st>>>(h->m, h->B, h->rp, h->ci, h->va64, (const T *)h->X,
-                                                     (const T *)h->Z, h->BV64, h->LAM, h->prow);
+    if (!check) {
+        k_fam_row<T><<<fam_blocks(h->m, ng), 256, 0, st>>>(
+            h->m, h->B, h->rp, h->ci, (const T *)h->va, (const T *)h->X, (const T *)h->BV, (const T *)h->fu, h->LAM,
+            (T *)h->U, h->inst, mu, im, h->sh);
+    } else {
+        k_fam_row_check<T><<<kResBlocks * ng, 256, 0, st>>>(
+            h->m, h->B, h->rp, h->ci, h->va64, (const T *)h->X, (const T *)h->Z, (const T *)h->BV, h->BV64,
+            (const T *)h->fu, h->LAM, (T *)h->U, h->inst, mu, im, h->sh, h->prow);
         k_fam_res_col<T><<<kResBlocks * (h->B / 64), 256, 0, st>>>(h->n, h->B, h->cp, h->ri, h->vc64, h->LAM, h->c64, h->D,
                                                      (const T *)h->Z, h->pcol);
         const int ng = kResBlocks / kFold;
