@@ -261,7 +261,8 @@ typedef struct {
 /* The latest min(max, recorded, opts.history) checks of the residual
  * history into out[0..*count-1], oldest first (host buffer of max records);
  * *count = 0 when opts.history was 0.  Residual queries between checks are
- * not recorded. */
+ * not recorded; a new start (solver_set_start, solver_resume) begins a new
+ * history.  The one-call solves keep none. */
 int solver_history(uv_solver *s, int32_t max, uv_history *out, int32_t *count);
 
 /* One call: solver_create, iterations from the zero start until the

@@ -165,15 +165,15 @@ class WarmStart:
         Also returned: "group_iters" (iterations of the B-slot group),
         "busy" (the fraction of slot-iterations that served a member),
         "tail_iters" (group iterations after the last member got a slot),
-        "handed_over" (members finished on the single-problem solver) and
-        "handover_iters" (their iterations there)."""
+        "handed_over" (members finished on the single-problem solver, listed
+        in "handed_members") and "handover_iters" (their iterations there)."""
         torch = self.torch
         N = len(b_all)
         D = self.D
         iters = np.zeros(N, np.int64)
         conv = np.zeros(N, bool)
         tail = self._tail_solver(b_all[0:1][0], eps) if tail_slots > 0 else None
-        handed, handed_iters = 0, 0
+        handed, handed_iters, handed_members = 0, 0, []
         with self._family(eps, max_iter) as F:
             buf = (torch.empty((self.B, D), dtype=torch.float32, device="cuda") if keep is not None else None)
             torch.cuda.synchronize()
@@ -249,6 +249,7 @@ class WarmStart:
                         conv[mem] = ok
                         handed += 1
                         handed_iters += more
+                        handed_members.append(mem)
                         if keep is not None:
                             st = tail.solution()
                             row = np.concatenate([st["z"], st["lambda"]]).astype(np.float32)
@@ -261,7 +262,7 @@ class WarmStart:
             tail.close()
         return {"iters": iters, "converged": conv, "seconds": seconds, "group_iters": group_iters,
                 "busy": busy_slot_iters / max(group_iters * self.B, 1), "tail_iters": tail_iters,
-                "handed_over": handed, "handover_iters": handed_iters}
+                "handed_over": handed, "handover_iters": handed_iters, "handed_members": handed_members}
 
     def _tail_solver(self, b0, eps):
         """The single-problem solver that takes over the last running

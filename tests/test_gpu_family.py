@@ -330,3 +330,37 @@ def test_hand_over_falls_back_to_a_cold_solve(small_family):
         cold = s.residuals()["iter"]
     say(f"hand-over fallback: {more} iterations alone, a fresh cold solve {cold}")
     assert ok and more == 10 + cold
+
+
+def test_stream_hand_over_keeps_solutions():
+    """The solutions the streaming driver keeps ([z ; lambda] rows, the
+    training data of the learned start): members that stopped in the group
+    are bitwise those of the driver without the hand-over; members finished
+    on the single-problem solver are converged points of the same problems,
+    z in the cone, and within the stopping tolerance's reach of the other
+    run's point."""
+    import torch
+    from paper_2203_05027_amd.warmstart import WarmStart
+    fam = I.ParametricFamily(m=300, n=600, k=5, p=8, seed=7)
+    ws = WarmStart(fam, k=8, hidden=(32, 32), B=64, log=say)
+    thetas = np.stack([fam.theta(7000 + i, p=8) for i in range(150)])
+    b_all = np.ascontiguousarray(fam.b_many(thetas))
+    keeps, runs = [], []
+    for tail in (16, 0):
+        keep = torch.zeros((len(thetas), ws.D), dtype=torch.float32, device="cuda")
+        runs.append(ws.solve_stream(b_all, eps=1e-4, max_iter=100_000, keep=keep, tail_slots=tail))
+        keeps.append(keep.cpu().numpy())
+    with_h, without = runs
+    assert with_h["handed_over"] >= 1 and with_h["converged"].all() and without["converged"].all()
+    handed = np.zeros(len(thetas), bool)
+    handed[with_h["handed_members"]] = True
+    n = fam.n
+    assert (keeps[0][:, :n] >= 0).all()
+    # members that stopped in the group: the same iterates, bit for bit
+    assert np.array_equal(keeps[0][~handed], keeps[1][~handed])
+    assert np.array_equal(with_h["iters"][~handed], without["iters"][~handed])
+    # members finished alone: the same iteration continued with another order of FP32 sums
+    scale = np.abs(keeps[1][handed]).max(axis=1)
+    diff = np.abs(keeps[0][handed] - keeps[1][handed]).max(axis=1) / scale
+    say(f"kept rows: {int(handed.sum())} handed over, largest relative difference {diff.max():.2e}")
+    assert diff.max() <= 5e-2, float(diff.max())
