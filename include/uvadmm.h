@@ -138,6 +138,19 @@ typedef struct {
     int32_t history;      /* residual history: the last `history` checks of
                              the iteration are recorded on the device (0 =
                              none; at most 2^24); see solver_history */
+    int32_t full_checks;  /* 0 = a check of the iteration evaluates its
+                             primal half first (the row residuals, which
+                             the row pass forms anyway) and its column half
+                             (A'lambda: the dual residual, c'z, the gap) only
+                             when the primal half passes the stopping test,
+                             since otherwise the check cannot stop the run:
+                             the same stopping iteration, status and
+                             iterates, and a NaN on the dual side alone shows
+                             at the next check whose primal half passes or
+                             whose primal residual is NaN; 1 = every check
+                             evaluates both halves.  Checks are always whole
+                             with a residual history, on the resident path and
+                             in solver_residuals */
 } uv_opts;
 
 /* Stopping tests (Section V): UV_CRIT_KKT stops when kkt <= eps_kkt (the

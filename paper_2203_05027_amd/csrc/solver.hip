@@ -52,6 +52,7 @@ struct DevStatus {
     unsigned long long clock0;  // GPU wall clock at the start
     int done;              // 1 = stop: every sweep kernel returns at once
     int status;            // UV_STATUS_*
+    int skip_col;          // 1: the last check's primal part failed, its column part is skipped
 };
 
 // One record of the residual history (a check of the iteration), as kept on
@@ -107,6 +108,7 @@ k_start(int m, const double *__restrict__ lam, T *__restrict__ u, double inv_mu,
         st->clock0 = wall_clock64();
         st->done = 0;
         st->status = UV_STATUS_RUNNING;
+        st->skip_col = 0;
     }
 }
 
@@ -526,8 +528,9 @@ template <typename T, int L>
 __global__ void __launch_bounds__(kWG)
 k_res_col(int n, const int *__restrict__ cp, const int *__restrict__ ri, const double *__restrict__ vc,
           const double *__restrict__ lam, const double *__restrict__ c, const double *__restrict__ delta,
-          const T *__restrict__ z, const T *__restrict__ x, double *__restrict__ part, int pstride)
+          const T *__restrict__ z, const T *__restrict__ x, double *__restrict__ part, int pstride, const int *skip)
 {
+    if (skip && *skip) return;  // the check's column half is ruled out (uniform)
     const int lane = threadIdx.x & (L - 1);
     const int col = blockIdx.x * (kWG / L) + threadIdx.x / L;
     double acc[3] = {0.0, 0.0, 0.0}, mx[2] = {0.0, 0.0};
@@ -551,8 +554,10 @@ k_res_col(int n, const int *__restrict__ cp, const int *__restrict__ ri, const d
 template <typename T, int S>
 __global__ void __launch_bounds__(kWG)
 k_res_col_slab(int n, const double *__restrict__ P, const double *__restrict__ c, const double *__restrict__ delta,
-               const T *__restrict__ z, const T *__restrict__ x, double *__restrict__ part, int pstride)
+               const T *__restrict__ z, const T *__restrict__ x, double *__restrict__ part, int pstride,
+               const int *skip)
 {
+    if (skip && *skip) return;  // the check's column half is ruled out (uniform)
     const int col = blockIdx.x * kWG + threadIdx.x;
     double acc[3] = {0.0, 0.0, 0.0}, mx[2] = {0.0, 0.0};
     if (col < n) {
@@ -654,8 +659,10 @@ __device__ bool finish_check(const double (&s)[10], const double (&nrm)[4], long
 // status and the stop flag change at the checks of the iteration alone.
 __global__ void __launch_bounds__(kWG)
 k_finalize(int nrow, const double *__restrict__ prow, int ncol, const double *__restrict__ pcol,
-           double eps, double eps_abs, double eps_gap, int crit, int decide, DevStatus *st, HistRing hist)
+           double eps, double eps_abs, double eps_gap, int crit, int decide, int gated, DevStatus *st,
+           HistRing hist)
 {
+    if (decide && gated && st->skip_col) return;  // a check that k_row_gate ruled out (uniform)
     double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, w[4] = {0.0, 0.0, 0.0, 0.0};
     for (int base = threadIdx.x; base < nrow; base += 8 * kWG) {
         double a[5][8];
@@ -700,6 +707,51 @@ k_finalize(int nrow, const double *__restrict__ prow, int ncol, const double *__
     if (decide && st->done) return;
     const double nrm[4] = {st->bnorm2, st->cnorm2, st->binf, st->cinf};
     finish_check(s, nrm, st->iter, eps, eps_abs, eps_gap, crit, decide, st, hist);
+}
+
+// The primal half of a check, before its column half: the row partials
+// summed exactly as k_finalize sums them (the same loop and reduction, so
+// the values agree bit for bit) and the primal part of the stopping test --
+// r_prim <= eps for the KKT test, ||Az-b||_inf <= eps_abs + eps scale_p for
+// the infinity-norm test, ||Ax-b|| < eps_abs for the POGS form.  When it
+// fails and the row sums are finite the check cannot stop the run, so its
+// column half (the A'lambda product, the dual residual, c'z and the gap) is
+// skipped: skip_col = 1, which the column kernels and k_finalize read.  A
+// check replayed after the run stopped is skipped too.
+__global__ void __launch_bounds__(kWG)
+k_row_gate(int nrow, const double *__restrict__ prow, double eps, double eps_abs, int crit, DevStatus *st)
+{
+    double v[3] = {0.0, 0.0, 0.0}, w[2] = {0.0, 0.0};
+    for (int base = threadIdx.x; base < nrow; base += 8 * kWG) {
+        double a[5][8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int i = base + r * kWG;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) a[k][r] = i < nrow ? prow[k * nrow + i] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            v[0] += a[0][r];
+            v[1] += a[1][r];
+            v[2] += a[2][r];
+            w[0] = fmax(w[0], a[3][r]);
+            w[1] = fmax(w[1], a[4][r]);
+        }
+    }
+    double s[5];
+    uv::block_sum_max<3, 2>(v, w, s, 1);
+    if (threadIdx.x != 0) return;
+    if (st->done) {
+        st->skip_col = 1;
+        return;
+    }
+    bool fails;
+    if (crit == 1) fails = !(s[3] <= eps_abs + eps * fmax(s[4], st->binf));
+    else if (crit == 2) fails = !(sqrt(s[2]) < eps_abs);
+    else fails = !(sqrt(s[0]) / (1.0 + sqrt(st->bnorm2)) <= eps);
+    const bool finite = isfinite(s[0]) && isfinite(s[1]) && isfinite(s[2]) && isfinite(s[3]) && isfinite(s[4]);
+    st->skip_col = fails && finite ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1008,6 +1060,7 @@ struct uv_solver {
     int nblk_row_fused = 0;     // row-residual partial blocks written by the check row pass
     bool resident = false;      // iterate with k_resident (the whole problem in one workgroup's LDS)
     bool need_start = false;    // b changed (solver_set_rhs): no iteration before a new start
+    const int *res_skip = nullptr;  // skip flag of the column residual kernels being launched
     ResLayout rlay{};
     int res_lr = 1, res_lc = 1;  // lanes per row and per column of k_resident
     HistRec *hist = nullptr;     // residual history ring (opts.history records)
@@ -1204,7 +1257,8 @@ struct ResColLaunch {
     {
         const unsigned g = blocks_for(s->n, kWG / L);
         k_res_col<T, L><<<g, kWG, 0, st>>>(s->n, s->cp, s->ri, s->vc64, s->lam, s->c64, s->delta,
-                                           (const T *)s->z, (const T *)s->x, s->part_col, s->nblk_rescol);
+                                           (const T *)s->z, (const T *)s->x, s->part_col, s->nblk_rescol,
+                                           s->res_skip);
     }
 };
 
@@ -1290,18 +1344,27 @@ void res_col_slab_launch(uv_solver *s, hipStream_t st)
     const unsigned g = blocks_for(s->n, kWG);
     const bool mixed = s->o.precision == UV_MIXED;
     double *P = mixed ? s->P_res : (double *)s->P_col;
-    seg_chunk_launch<double, S>(s, S * g, st, s->n, s->scp, s->sri, s->svc64, s->lam, P, nullptr);
+    seg_chunk_launch<double, S>(s, S * g, st, s->n, s->scp, s->sri, s->svc64, s->lam, P, s->res_skip);
     if (mixed)
         k_res_col_slab<float, S><<<g, kWG, 0, st>>>(s->n, P, s->c64, s->delta, (const float *)s->z,
-                                                    (const float *)s->x, s->part_col, (int)g);
+                                                    (const float *)s->x, s->part_col, (int)g, s->res_skip);
     else
         k_res_col_slab<double, S><<<g, kWG, 0, st>>>(s->n, P, s->c64, s->delta, (const double *)s->z,
-                                                     (const double *)s->x, s->part_col, (int)g);
+                                                     (const double *)s->x, s->part_col, (int)g, s->res_skip);
 }
 
 void launch_residuals(uv_solver *s, hipStream_t st, bool row_done, bool decide)
 {
     if (!row_done) dispatch_le_res<ResRowLaunch>(s, st, s->L_row);
+    const int nrow = row_done ? s->nblk_row_fused : s->nblk_row;
+    // primal half first: a check of the iteration whose primal part fails
+    // cannot stop the run, and then skips its column half (not with a
+    // residual history, which records every check whole, nor when every
+    // check is asked for whole)
+    const bool gated = decide && s->o.full_checks == 0 && !s->hist;
+    if (gated)
+        k_row_gate<<<1, kWG, 0, st>>>(nrow, s->part_row, s->o.eps_kkt, s->o.eps_abs, s->o.criterion, s->st);
+    s->res_skip = gated ? &s->st->skip_col : nullptr;
     // with column slabs and chunked passes A'lambda goes through the slab copy
     // (FP64 values in both precisions), else the plain column residual pass
     const bool slab = slab_col_check(s);
@@ -1312,11 +1375,11 @@ void launch_residuals(uv_solver *s, hipStream_t st, bool row_done, bool decide)
     } else {
         dispatch_le_res<ResColLaunch>(s, st, s->L_col);
     }
-    const int nrow = row_done ? s->nblk_row_fused : s->nblk_row;
     const int ncol = slab ? (int)blocks_for(s->n, kWG) : s->nblk_rescol;
     k_finalize<<<1, kWG, 0, st>>>(nrow, s->part_row, ncol, s->part_col, s->o.eps_kkt, s->o.eps_abs,
-                                  s->o.eps_gap, s->o.criterion, decide ? 1 : 0, s->st,
+                                  s->o.eps_gap, s->o.criterion, decide ? 1 : 0, gated ? 1 : 0, s->st,
                                   HistRing{s->hist, s->o.history});
+    s->res_skip = nullptr;
 }
 
 // One iteration; with check, the residuals of the new iterate follow it.
@@ -1443,6 +1506,7 @@ int validate(const uv_csr *A, const double *b, const double *c, const uv_cones *
     if (o->slab_kernel < 0 || o->slab_kernel > 3) return UV_EINVAL;
     if (o->resident < 0 || o->resident > 2) return UV_EINVAL;
     if (o->history < 0 || o->history > (1 << 24)) return UV_EINVAL;
+    if (o->full_checks < 0 || o->full_checks > 1) return UV_EINVAL;
     if (A->nnz > 0 && (!A->col_idx || !A->val)) return UV_EINVAL;
     if (!A->row_ptr) return UV_EINVAL;
     if (A->nnz >= ((int64_t)1 << 31)) return UV_ETOOBIG;
@@ -1678,6 +1742,7 @@ void uv_default_opts(uv_opts *o)
     o->eps_gap = 0.0;
     o->resident = 0;
     o->history = 0;
+    o->full_checks = 0;
 }
 
 const char *solver_strerror(int code)

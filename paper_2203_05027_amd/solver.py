@@ -41,7 +41,7 @@ class UvOpts(ctypes.Structure):
                 ("slabs_col", ctypes.c_int32), ("criterion", ctypes.c_int32),
                 ("eps_abs", ctypes.c_double), ("slab_kernel", ctypes.c_int32),
                 ("eps_gap", ctypes.c_double), ("resident", ctypes.c_int32),
-                ("history", ctypes.c_int32)]
+                ("history", ctypes.c_int32), ("full_checks", ctypes.c_int32)]
 
 
 class UvResiduals(ctypes.Structure):
@@ -180,7 +180,7 @@ def _problem(m, n, row_ptr, col_idx, val, b, c, n_orth, soc_sizes):
 
 def _opts(*, mu=1.0, precision="fp64", check_every=10, eps=1e-4, max_iter=0, lanes_row=0, lanes_col=0,
           unroll_row=0, unroll_col=0, slabs_row=0, slabs_col=0, criterion="kkt", eps_abs=0.0, eps_gap=0.0,
-          slab_kernel="auto", resident="auto", history=0, use_graph=True, stream=None):
+          slab_kernel="auto", resident="auto", history=0, full_checks=False, use_graph=True, stream=None):
     o = default_opts()
     o.mu = float(mu)
     o.precision = {"fp64": UV_FP64, "mixed": UV_MIXED}[precision]
@@ -197,6 +197,7 @@ def _opts(*, mu=1.0, precision="fp64", check_every=10, eps=1e-4, max_iter=0, lan
     o.slab_kernel = {"auto": 0, "chunked": 1, "lanes": 2, "chunked4": 3}[slab_kernel]
     o.eps_abs = float(eps_abs)
     o.history = int(history)
+    o.full_checks = 1 if full_checks else 0
     o.use_graph = 1 if use_graph else 0
     return o
 
@@ -231,7 +232,7 @@ class Solver:
                  mu=1.0, precision="fp64", check_every=10, eps=1e-4, max_iter=0,
                  lanes_row=0, lanes_col=0, unroll_row=0, unroll_col=0, slabs_row=0, slabs_col=0,
                  criterion="kkt", eps_abs=0.0, eps_gap=0.0, slab_kernel="auto", resident="auto", history=0,
-                 use_graph=True, stream=None):
+                 full_checks=False, use_graph=True, stream=None):
         L = lib()
         self.m, self.n = int(m), int(n)
         keep, csr, cones, bb, cc = _problem(self.m, self.n, row_ptr, col_idx, val, b, c, n_orth, soc_sizes)
@@ -239,7 +240,7 @@ class Solver:
                   lanes_row=lanes_row, lanes_col=lanes_col, unroll_row=unroll_row, unroll_col=unroll_col,
                   slabs_row=slabs_row, slabs_col=slabs_col, criterion=criterion, eps_abs=eps_abs,
                   eps_gap=eps_gap, slab_kernel=slab_kernel, resident=resident, history=history,
-                  use_graph=use_graph, stream=stream)
+                  full_checks=full_checks, use_graph=use_graph, stream=stream)
         self.precision = precision
         self._history_cap = int(history)
         self.nnz = csr.nnz

@@ -1,0 +1,82 @@
+"""Primal half first: a check whose primal part fails the stopping test
+skips its column half (full_checks = 0, the default), since it cannot stop
+the run.  Against every check evaluated whole (full_checks = 1): the same
+stopping iteration and status, bit for bit the same iterates and final
+residuals, for the three stopping tests, both precisions, with and without
+XCD slabs; residual queries stay whole."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2203_05027_amd import instances as I
+from paper_2203_05027_amd.solver import Solver
+
+pytestmark = pytest.mark.gpu
+
+RES = ("r_prim", "r_dual", "r_gap", "kkt", "pobj", "dobj", "res_ax_b", "prim_inf", "dual_inf", "pobj_x", "gap_x",
+       "iter", "status")
+
+
+def say(msg):
+    sys.__stderr__.write(f"[gpu-test] {msg}\n")
+    sys.__stderr__.flush()
+
+
+_INST = {}
+
+
+def inst():
+    if not _INST:
+        _INST["lp"] = I.lp_instance(1500, 3000, 5, seed=51)
+    return _INST["lp"]
+
+
+CRIT = {"kkt": dict(criterion="kkt", eps=1e-4),
+        "inf": dict(criterion="inf", eps=1e-4, eps_abs=1e-6),
+        "pogs": dict(criterion="pogs", eps_abs=2e-3, eps_gap=2e-2)}
+
+
+def _run(full, precision, slabs, crit):
+    kw = dict(CRIT[crit], precision=precision, check_every=10, resident="never", max_iter=200_000)
+    if slabs > 1:
+        kw.update(slabs_row=slabs, slabs_col=slabs)
+    with Solver.from_instance(inst(), full_checks=full, **kw) as s:
+        while not s.iterate(5000):
+            pass
+        return s.solution(), s.residuals(), s.launch_shape()
+
+
+@pytest.mark.parametrize("crit", ["kkt", "inf", "pogs"])
+@pytest.mark.parametrize("slabs", [1, 2])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_gated_checks_stop_where_whole_checks_stop(precision, slabs, crit):
+    g_sol, g_res, shape = _run(False, precision, slabs, crit)
+    f_sol, f_res, _ = _run(True, precision, slabs, crit)
+    say(f"{precision} slabs {slabs} {crit}: shape {shape}, stop at {g_res['iter']} ({g_res['status']}), "
+        f"kkt {g_res['kkt']:.3e}")
+    assert g_res["status"] == "converged"
+    for k in RES:
+        assert g_res[k] == f_res[k], (k, g_res[k], f_res[k])
+    for k in g_sol:
+        assert np.array_equal(g_sol[k], f_sol[k]), k
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_residual_queries_stay_whole(precision):
+    """Between checks and right after a check whose column half was skipped,
+    a residual query evaluates every residual: the same values as with every
+    check whole."""
+    out = []
+    for full in (False, True):
+        with Solver.from_instance(inst(), eps=1e-4, check_every=10, resident="never", precision=precision,
+                                  full_checks=full) as s:
+            vals = []
+            for k in (30, 5, 15):  # ends on a check, between checks, on a check
+                s.iterate(k)
+                vals.append(s.residuals())
+            out.append(vals)
+    for a, b in zip(*out):
+        assert a["r_prim"] > 1e-4  # these checks' primal halves fail: gated ones skip the column half
+        for k in RES:
+            assert a[k] == b[k], (k, a[k], b[k])
