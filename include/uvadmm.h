@@ -149,8 +149,9 @@ typedef struct {
                              at the next check whose primal half passes or
                              whose primal residual is NaN; 1 = every check
                              evaluates both halves.  Checks are always whole
-                             with a residual history, on the resident path and
-                             in solver_residuals */
+                             with a residual history, on the resident path, in
+                             the family solver and in solver_residuals; the
+                             batched solver gates its checks the same way */
 } uv_opts;
 
 /* Stopping tests (Section V): UV_CRIT_KKT stops when kkt <= eps_kkt (the
@@ -350,9 +351,11 @@ int batch_create(int32_t count, const uv_csr *A, const double *const *b,
  * be NULL) receives the number still running afterwards. */
 int batch_iterate(uv_batch *h, int64_t k, int32_t *n_active);
 
-/* Residuals / status of instance i at its last check (see uv_residuals;
- * the infinity-norm fields, pobj_x and gap_x are not evaluated by the
- * batched solver and read 0).  Returns UV_ENUMERIC (with *r filled) when that instance stopped on a
+/* Residuals / status of instance i at its last whole check (see
+ * uv_residuals; the infinity-norm fields, pobj_x and gap_x are not evaluated
+ * by the batched solver and read 0).  With opts.full_checks = 0 a check whose
+ * r_prim exceeds eps_kkt (it cannot stop the instance) skips its column half
+ * and records nothing; the check that stops an instance is always whole.  Returns UV_ENUMERIC (with *r filled) when that instance stopped on a
  * NaN or Inf. */
 int batch_residuals(uv_batch *h, int32_t i, uv_residuals *r);
 

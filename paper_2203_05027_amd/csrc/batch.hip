@@ -235,11 +235,11 @@ k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__
         const T *__restrict__ c, const double *__restrict__ c64, T *__restrict__ x, T *__restrict__ z,
         T *__restrict__ u, double *__restrict__ lam, double *__restrict__ delta, double mu, double inv_mu,
         double eps, int check_every, long long max_iter, const int *__restrict__ sptr,
-        const lidx_t *__restrict__ sidx, const T *__restrict__ sval, const double *__restrict__ sval64)
+        const lidx_t *__restrict__ sidx, const T *__restrict__ sval, const double *__restrict__ sval64, int gated)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T *xs = reinterpret_cast<T *>(lds_raw);
-    __shared__ int s_q, s_stop;
+    __shared__ int s_q, s_stop, s_skip;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int budget = *budget_p;
     for (;;) {
@@ -362,6 +362,18 @@ k_batch(BInst *__restrict__ inst, const int *__restrict__ order, int nq, int *__
             }
             __syncthreads();
             ++it;
+            if (chk && gated && !(max_iter > 0 && it >= max_iter)) {
+                // primal half first: when r_prim > eps (with finite row sums)
+                // this check cannot stop the instance, and its column half is
+                // skipped (the row sums are reduced as below, bit for bit)
+                double g[3] = {a[0], a[1], a[2]};
+                block_sum_rt<3>(g);
+                if (tid == 0)
+                    s_skip = !(sqrt(g[0]) / (1.0 + sqrt(I->bnorm2)) <= eps) && isfinite(g[0]) && isfinite(g[1]) &&
+                             isfinite(g[2]);
+                __syncthreads();
+                if (s_skip) continue;
+            }
             if (chk) {
                 // FP64 residuals at (z, lambda, delta) with the FP64 values of A:
                 // the row sums came with the row pass, the column sums here
@@ -485,7 +497,7 @@ int batch_launch(uv_batch *h, hipStream_t st, const int *order, int nq)
     h->inst, order, nq, h->queue, h->budget, h->rp, h->cl, (const T *)h->va, h->va64, h->cp, h->rl,          \
         (const T *)h->vc, h->vc64, (const T *)h->b, h->b64, (const T *)h->fu, (const T *)h->c, h->c64,      \
         (T *)h->x, (T *)h->z, (T *)h->u, h->lam, h->delta, mu, im, o.eps_kkt, o.check_every, (long long)o.max_iter, \
-        h->sptr, h->sidx, (const T *)h->sval, h->sval64
+        h->sptr, h->sidx, (const T *)h->sval, h->sval64, o.full_checks == 0 ? 1 : 0
     const int grid = std::max(1, std::min(h->grid, nq));
     if (o.precision == UV_MIXED)
         h->zc ? k_batch<float, true><<<grid, h->threads, h->lds_bytes, st>>>(UV_BATCH_ARGS(float))

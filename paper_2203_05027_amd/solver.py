@@ -366,7 +366,7 @@ class Batch:
     BUCKETS = (0, 128, 512, 2048)  # lower bounds of the size buckets on m
 
     def __init__(self, instances, *, mu=1.0, precision="mixed", check_every=10, eps=1e-4,
-                 max_iter=0, use_graph=True, stream=None):
+                 max_iter=0, full_checks=False, use_graph=True, stream=None):
         L = lib()
         if not hasattr(L, "_batch_bound"):
             _bind_batch(L)
@@ -392,6 +392,7 @@ class Batch:
         o.check_every = int(check_every)
         o.eps_kkt = float(eps)
         o.max_iter = int(max_iter)
+        o.full_checks = 1 if full_checks else 0
         o.hip_stream = stream
         o.use_graph = 1 if use_graph else 0
         self.precision = precision

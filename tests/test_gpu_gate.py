@@ -80,3 +80,25 @@ def test_residual_queries_stay_whole(precision):
         assert a["r_prim"] > 1e-4  # these checks' primal halves fail: gated ones skip the column half
         for k in RES:
             assert a[k] == b[k], (k, a[k], b[k])
+
+
+def test_batched_gated_checks_match_whole_checks():
+    """The batched solver with primal-first checks against every check
+    whole: every instance stops at the same iteration with the same status,
+    bit for bit the same iterates and the same residuals of its stopping
+    check."""
+    from paper_2203_05027_amd.solver import Batch
+    insts = [I.lp_instance(m, 2 * m, 6, seed=60 + q) for q, m in enumerate((60, 90, 150, 240, 400, 700))]
+    out = []
+    for full in (False, True):
+        with Batch(insts, precision="mixed", eps=1e-4, max_iter=200_000, full_checks=full) as b:
+            while b.iterate(5000):
+                pass
+            out.append([(b.solution(i), b.residuals(i)) for i in range(len(insts))])
+    for i, ((s1, r1), (s2, r2)) in enumerate(zip(*out)):
+        say(f"batched instance {i}: stop at {r1['iter']} ({r1['status']})")
+        assert r1["status"] == "converged"
+        for k in ("iter", "status", "kkt", "r_prim", "r_dual", "r_gap", "pobj", "dobj", "res_ax_b"):
+            assert r1[k] == r2[k], (i, k, r1[k], r2[k])
+        for k in s1:
+            assert np.array_equal(s1[k], s2[k]), (i, k)
