@@ -151,7 +151,8 @@ typedef struct {
                              evaluates both halves.  Checks are always whole
                              with a residual history, on the resident path, in
                              the family solver and in solver_residuals; the
-                             batched solver gates its checks the same way */
+                             batched solver and the standard-ADMM baseline
+                             gate their checks the same way */
 } uv_opts;
 
 /* Stopping tests (Section V): UV_CRIT_KKT stops when kkt <= eps_kkt (the

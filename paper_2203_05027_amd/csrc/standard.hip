@@ -49,6 +49,7 @@ struct StdStatus {
     int done;    // 1 = stop: every kernel of an iteration returns at once
     int idle;    // 1 = CG of this iteration has stopped (or done)
     int status;  // UV_STATUS_*
+    int skip_col;  // 1: the check's primal half failed, its column half is skipped
 };
 
 // Sum of nb per-workgroup partials in a fixed order (one workgroup).
@@ -291,8 +292,9 @@ k_std_res_row(int m, const double *__restrict__ P, const double *__restrict__ b,
 template <int S>
 __global__ void __launch_bounds__(kWG)
 k_std_res_col(int n, const double *__restrict__ P, const double *__restrict__ c, const double *__restrict__ delta,
-              const double *__restrict__ z, double mu, double *__restrict__ part, int pstride)
+              const double *__restrict__ z, double mu, double *__restrict__ part, int pstride, const int *skip)
 {
+    if (skip && *skip) return;  // the check's column half is ruled out (uniform)
     const int j = blockIdx.x * kWG + threadIdx.x;
     double v[2] = {0.0, 0.0};
     if (j < n) {
@@ -306,10 +308,34 @@ k_std_res_col(int n, const double *__restrict__ P, const double *__restrict__ c,
     uv::block_sum<2>(v, part + blockIdx.x, pstride);
 }
 
+// The primal half of a check first, as in the UV solver: the row partials
+// summed as k_std_finalize sums them (bit for bit the same values); when
+// r_prim > eps with finite sums the check cannot stop the run and its column
+// half (the A' nu product, its partials and the finalize) is skipped.
+__global__ void __launch_bounds__(kWG)
+k_std_gate(int nr, const double *__restrict__ prow, double eps, StdStatus *st)
+{
+    double v[2] = {0.0, 0.0};
+    for (int i = threadIdx.x; i < nr; i += kWG) {
+        v[0] += prow[i];
+        v[1] += prow[nr + i];
+    }
+    __shared__ double s[2];
+    uv::block_sum<2>(v, s, 1);
+    if (threadIdx.x != 0) return;
+    if (st->done) {
+        st->skip_col = 1;
+        return;
+    }
+    const bool fails = !(sqrt(s[0]) / (1.0 + sqrt(st->bnorm2)) <= eps);
+    st->skip_col = fails && isfinite(s[0]) && isfinite(s[1]) ? 1 : 0;
+}
+
 __global__ void __launch_bounds__(kWG)
 k_std_finalize(int nr, const double *__restrict__ prow, int nc, const double *__restrict__ pcol, double eps,
-               StdStatus *st)
+               StdStatus *st, int gated)
 {
+    if (gated && st->skip_col) return;  // ruled out by k_std_gate (uniform)
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int i = threadIdx.x; i < nr; i += kWG) {
         v[0] += prow[i];
@@ -348,6 +374,7 @@ struct uv_standard {
     int *soc_off = nullptr;  // n_soc + 1 cone boundaries
     double mu = 1.0, eps = 0.0;
     int check_every = 10;
+    bool gated = true;  // checks of the iteration evaluate their primal half first (opts.full_checks = 0)
     int64_t max_iter = 0, host_iter = 0;
     hipStream_t stream = nullptr, cap = nullptr;
     bool own_stream = false;
@@ -427,9 +454,11 @@ void iteration(uv_standard *h, hipStream_t st, bool check)
     if (!check) return;
     prod_row<SR>(h, st, h->x1, nullptr);
     k_std_res_row<SR><<<gm, kWG, 0, st>>>(m, h->P_row, h->b, h->nu, mu, h->part_row, (int)gm);
-    prod_col<SC>(h, st, h->nu, nullptr);
-    k_std_res_col<SC><<<gn, kWG, 0, st>>>(n, h->P_col, h->c, h->delta, h->x1, mu, h->part_col, (int)gn);
-    k_std_finalize<<<1, kWG, 0, st>>>((int)gm, h->part_row, (int)gn, h->part_col, h->eps, h->st);
+    const int *skip = h->gated ? &h->st->skip_col : nullptr;
+    if (h->gated) k_std_gate<<<1, kWG, 0, st>>>((int)gm, h->part_row, h->eps, h->st);
+    prod_col<SC>(h, st, h->nu, skip);
+    k_std_res_col<SC><<<gn, kWG, 0, st>>>(n, h->P_col, h->c, h->delta, h->x1, mu, h->part_col, (int)gn, skip);
+    k_std_finalize<<<1, kWG, 0, st>>>((int)gm, h->part_row, (int)gn, h->part_col, h->eps, h->st, h->gated ? 1 : 0);
 }
 
 template <int SR>
@@ -455,8 +484,9 @@ void check_only(uv_standard *h, hipStream_t st)
     prod_row<SR>(h, st, h->x1, nullptr);
     k_std_res_row<SR><<<gm, kWG, 0, st>>>(h->m, h->P_row, h->b, h->nu, h->mu, h->part_row, (int)gm);
     prod_col<SC>(h, st, h->nu, nullptr);
-    k_std_res_col<SC><<<gn, kWG, 0, st>>>(h->n, h->P_col, h->c, h->delta, h->x1, h->mu, h->part_col, (int)gn);
-    k_std_finalize<<<1, kWG, 0, st>>>((int)gm, h->part_row, (int)gn, h->part_col, h->eps, h->st);
+    k_std_res_col<SC><<<gn, kWG, 0, st>>>(h->n, h->P_col, h->c, h->delta, h->x1, h->mu, h->part_col, (int)gn,
+                                          nullptr);
+    k_std_finalize<<<1, kWG, 0, st>>>((int)gm, h->part_row, (int)gn, h->part_col, h->eps, h->st, 0);
 }
 
 void launch_check(uv_standard *h, hipStream_t st)
@@ -549,6 +579,7 @@ int standard_create(const uv_csr *A, const double *b, const double *c, const uv_
     h->mu = o.mu;
     h->eps = o.eps_kkt;
     h->check_every = o.check_every;
+    h->gated = o.full_checks == 0;
     h->max_iter = o.max_iter;
     h->cg_iters = cg_iters;
     h->S_row = o.slabs_row ? o.slabs_row : pick_slabs_row(8 * (size_t)n);

@@ -720,8 +720,8 @@ class Standard:
     same sparse product kernels as the UV solver."""
 
     def __init__(self, m, n, row_ptr, col_idx, val, b, c, *, n_orth=None, soc_sizes=(), mu=1.0, cg_iters=10,
-                 cg_tol=0.0, check_every=10, eps=1e-4, max_iter=0, slabs_row=0, slabs_col=0, use_graph=True,
-                 stream=None):
+                 cg_tol=0.0, check_every=10, eps=1e-4, max_iter=0, slabs_row=0, slabs_col=0, full_checks=False,
+                 use_graph=True, stream=None):
         L = _bind_standard()
         self.m, self.n = int(m), int(n)
         rp, ci, va, self.nnz = _csr(self.m, row_ptr, col_idx, val)
@@ -733,6 +733,7 @@ class Standard:
         o.max_iter = int(max_iter)
         o.slabs_row = int(slabs_row)
         o.slabs_col = int(slabs_col)
+        o.full_checks = 1 if full_checks else 0
         o.use_graph = 1 if use_graph else 0
         o.hip_stream = stream
         sizes = np.ascontiguousarray(soc_sizes, dtype=np.int32)

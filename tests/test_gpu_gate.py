@@ -102,3 +102,24 @@ def test_batched_gated_checks_match_whole_checks():
             assert r1[k] == r2[k], (i, k, r1[k], r2[k])
         for k in s1:
             assert np.array_equal(s1[k], s2[k]), (i, k)
+
+
+def test_standard_baseline_gated_checks_match_whole_checks():
+    """The standard ADMM + CG baseline gates its checks the same way: the
+    same stopping iteration, iterates and final residuals."""
+    from paper_2203_05027_amd.solver import Standard
+    src = inst()
+    out = []
+    for full in (False, True):
+        with Standard(src["m"], src["n"], src["row_ptr"], src["col_idx"], src["val"], src["b"], src["c"],
+                      cg_iters=3, eps=1e-4, max_iter=100_000, full_checks=full) as s:
+            while not s.iterate(5000):
+                pass
+            out.append((s.solution(), s.residuals()))
+    (s1, r1), (s2, r2) = out
+    say(f"standard: stop at {r1['iter']} ({r1['status']})")
+    assert r1["status"] == "converged"
+    for k in ("iter", "status", "kkt", "r_prim", "r_dual", "r_gap", "pobj", "dobj"):
+        assert r1[k] == r2[k], (k, r1[k], r2[k])
+    for k in s1:
+        assert np.array_equal(s1[k], s2[k]), k
