@@ -123,3 +123,36 @@ def test_standard_baseline_gated_checks_match_whole_checks():
         assert r1[k] == r2[k], (k, r1[k], r2[k])
     for k in s1:
         assert np.array_equal(s1[k], s2[k]), k
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_problems_gated_like_whole(seed):
+    """Drawn LPs and SOCPs (ragged shapes, check intervals 1-12, tolerances
+    1e-2 to 1e-5, the three stopping tests, both precisions): primal-first
+    checks stop where whole checks stop, with the same iterates."""
+    rng = np.random.default_rng(900 + seed)
+    if rng.random() < 0.5:
+        src = I.lp_instance(int(rng.integers(20, 400)), int(rng.integers(450, 900)), 4, seed=int(rng.integers(1e6)))
+    else:
+        src = I.socp_instance(int(rng.integers(20, 60)), 6, seed=int(rng.integers(1e6)))
+    crit = ["kkt", "inf", "pogs"][seed % 3]
+    eps = float(10.0 ** -rng.uniform(2, 5))
+    kw = dict(precision=["fp64", "mixed"][seed % 2], check_every=int(rng.integers(1, 13)), resident="never",
+              max_iter=30_000, criterion=crit, eps=eps)
+    if crit == "inf":
+        kw["eps_abs"] = eps * 1e-2
+    if crit == "pogs":
+        kw.update(eps_abs=eps * 10, eps_gap=eps * 100)
+    out = []
+    for full in (False, True):
+        with Solver.from_instance(src, full_checks=full, **kw) as s:
+            while not s.iterate(4000):
+                pass
+            out.append((s.solution(), s.residuals()))
+    (g, rg), (f, rf) = out
+    say(f"seed {seed}: m={src['m']} n={src['n']} {kw['precision']} {crit} eps {eps:.1e} ce {kw['check_every']}: "
+        f"stop {rg['iter']} ({rg['status']})")
+    for k in RES:
+        assert rg[k] == rf[k], (k, rg[k], rf[k])
+    for k in g:
+        assert np.array_equal(g[k], f[k]), k
