@@ -149,8 +149,8 @@ typedef struct {
                              at the next check whose primal half passes or
                              whose primal residual is NaN; 1 = every check
                              evaluates both halves.  Checks are always whole
-                             with a residual history, on the resident path, in
-                             the family solver and in solver_residuals; the
+                             with a residual history, in the family solver
+                             and in solver_residuals; the resident path, the
                              batched solver and the standard-ADMM baseline
                              gate their checks the same way */
 } uv_opts;

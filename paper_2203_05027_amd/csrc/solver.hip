@@ -848,7 +848,7 @@ __device__ __forceinline__ void res_check(int m, int n, int Lr, int Lc, const in
                                           const double *cvc, const T *xs, const T *zs, const double *ds,
                                           const double *ls, const double *__restrict__ b64,
                                           const double *__restrict__ c64, double (*red)[kResThreads / 64],
-                                          double (&sv)[10])
+                                          double (&sv)[10], const double *gate, int *s_skip)
 {
     constexpr int NT = kResThreads;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -865,6 +865,39 @@ __device__ __forceinline__ void res_check(int m, int n, int Lr, int Lc, const in
             v[6] = fmax(v[6], fabs(rz));
             v[7] = fmax(v[7], fabs(qz));
         }
+    }
+    if (gate) {
+        // primal half first (gate: eps, eps_abs, crit, ||b||^2, ||b||_inf):
+        // the row values folded as below, bit for bit; when the primal part
+        // of the test fails with finite sums the check cannot stop the run
+        // and its column half is skipped (*s_skip = 1, sv left unset)
+        double g[5] = {uv::wave_fold0<false>(v[0]), uv::wave_fold0<false>(v[1]), uv::wave_fold0<false>(v[2]),
+                       uv::wave_fold0<true>(v[6]), uv::wave_fold0<true>(v[7])};
+        if (lane == 0)
+#pragma unroll
+            for (int k = 0; k < 5; ++k) red[k][w] = g[k];
+        __syncthreads();
+        if (w == 0) {
+            double a = 0.0;
+            if (lane < 5) {
+                a = red[lane][0];
+                for (int q = 1; q < NT / 64; ++q) a = lane < 3 ? a + red[lane][q] : fmax(a, red[lane][q]);
+            }
+            double f[5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) f[k] = __shfl(a, k, 64);
+            if (lane == 0) {
+                const int crit = (int)gate[2];
+                bool fails;
+                if (crit == 1) fails = !(f[3] <= gate[1] + gate[0] * fmax(f[4], gate[4]));
+                else if (crit == 2) fails = !(sqrt(f[2]) < gate[1]);
+                else fails = !(sqrt(f[0]) / (1.0 + sqrt(gate[3])) <= gate[0]);
+                *s_skip = fails && isfinite(f[0]) && isfinite(f[1]) && isfinite(f[2]) && isfinite(f[3]) &&
+                          isfinite(f[4]);
+            }
+        }
+        __syncthreads();
+        if (*s_skip) return;
     }
     for (int j = gc; j < n; j += NT / Lc) {
         const double a = lds_dot<double>(cps[j], cps[j + 1], lc, Lc, ris, cvc, ls);
@@ -916,11 +949,11 @@ k_resident(int m, int n, ResLayout L, int Lr, int Lc, const int *__restrict__ rp
            const double *__restrict__ c64, const T *__restrict__ fu, T *__restrict__ x, T *__restrict__ z,
            T *__restrict__ u, double *__restrict__ lam, double *__restrict__ delta, double mu, long long iters,
            int eval_only, int check_every, double eps, double eps_abs, double eps_gap, int crit, DevStatus *st,
-           HistRing hist)
+           HistRing hist, int gated)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ double red[10][kResThreads / 64];
-    __shared__ int stop;
+    __shared__ int stop, skip;
     if (!eval_only && st->done) return;
     constexpr int NT = kResThreads;
     const int tid = threadIdx.x;
@@ -951,12 +984,13 @@ k_resident(int m, int n, ResLayout L, int Lr, int Lc, const int *__restrict__ rp
     __syncthreads();
     const long long it0 = st->iter;
     const double nrm[4] = {st->bnorm2, st->cnorm2, st->binf, st->cinf};
+    const double gate[5] = {eps, eps_abs, (double)crit, nrm[0], nrm[2]};
     // FP64 values of A for the checks: the staged ones in FP64, global ones in the mixed form
     const double *cva = sizeof(T) == sizeof(double) ? (const double *)vas : va64;
     const double *cvc = sizeof(T) == sizeof(double) ? (const double *)vcs : vc64;
     if (eval_only) {
         double sv[10];
-        res_check<T>(m, n, Lr, Lc, rps, cis, cps, ris, cva, cvc, xs, zs, ds, ls, b64, c64, red, sv);
+        res_check<T>(m, n, Lr, Lc, rps, cis, cps, ris, cva, cvc, xs, zs, ds, ls, b64, c64, red, sv, nullptr, &skip);
         if (tid == 0) finish_check(sv, nrm, it0, eps, eps_abs, eps_gap, crit, 0, st, hist);
         return;
     }
@@ -995,7 +1029,9 @@ k_resident(int m, int n, ResLayout L, int Lr, int Lc, const int *__restrict__ rp
         if (--to_check != 0) continue;
         to_check = check_every;
         double sv[10];
-        res_check<T>(m, n, Lr, Lc, rps, cis, cps, ris, cva, cvc, xs, zs, ds, ls, b64, c64, red, sv);
+        res_check<T>(m, n, Lr, Lc, rps, cis, cps, ris, cva, cvc, xs, zs, ds, ls, b64, c64, red, sv,
+                     gated ? gate : nullptr, &skip);
+        if (gated && skip) continue;
         if (tid == 0) {
             st->iter = itn;
             stop = finish_check(sv, nrm, itn, eps, eps_abs, eps_gap, crit, 1, st, hist) ? 1 : 0;
@@ -1424,6 +1460,7 @@ struct ResArgs {
     bool mixed;
     double mu, eps, eps_abs, eps_gap;
     int check_every, crit;
+    int gated;  // checks primal half first (no history, opts.full_checks = 0)
 };
 
 // Up to `iters` iterations on the resident path in launches of at most 2^16
@@ -1438,7 +1475,8 @@ void resident_launch(const ResArgs &a, hipStream_t st, int64_t iters, bool eval_
 #define UV_RES_ARGS(T)                                                                                         \
     a.m, a.n, a.L, a.Lr, a.Lc, a.rp, a.ci, (const T *)a.va, a.cp, a.ri, (const T *)a.vc, a.va64, a.vc64,         \
         (const T *)a.b, a.b64, (const T *)a.c, a.c64, (const T *)a.fu, (T *)a.x, (T *)a.z, (T *)a.u, a.lam,        \
-        a.delta, a.mu, q, eval_only ? 1 : 0, a.check_every, a.eps, a.eps_abs, a.eps_gap, a.crit, a.st, a.hist
+        a.delta, a.mu, q, eval_only ? 1 : 0, a.check_every, a.eps, a.eps_abs, a.eps_gap, a.crit, a.st, a.hist,  \
+        a.gated
         if (a.mixed) k_resident<float><<<1, kResThreads, a.L.bytes, st>>>(UV_RES_ARGS(float));
         else k_resident<double><<<1, kResThreads, a.L.bytes, st>>>(UV_RES_ARGS(double));
 #undef UV_RES_ARGS
@@ -1474,6 +1512,7 @@ ResArgs res_args(const uv_solver *s)
     a.delta = s->delta;
     a.st = s->st;
     a.hist = HistRing{s->hist, s->o.history};
+    a.gated = s->o.full_checks == 0 && !s->hist ? 1 : 0;
     a.mixed = s->o.precision == UV_MIXED;
     a.mu = s->o.mu;
     a.eps = s->o.eps_kkt;
@@ -2268,6 +2307,7 @@ int solver_solve_noalloc(const uv_csr *A, const double *b, const double *c, cons
     a.delta = d.delta;
     a.st = d.st;
     a.hist = HistRing{nullptr, 0};
+    a.gated = o.full_checks == 0 ? 1 : 0;
     a.mixed = mixed;
     a.mu = o.mu;
     a.eps = o.eps_kkt;

@@ -156,3 +156,31 @@ def test_random_problems_gated_like_whole(seed):
         assert rg[k] == rf[k], (k, rg[k], rf[k])
     for k in g:
         assert np.array_equal(g[k], f[k]), k
+
+
+@pytest.mark.parametrize("crit", ["kkt", "inf", "pogs"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_resident_gated_checks_match_whole_checks(precision, crit):
+    """The resident path (the whole problem in one CU's LDS) gates its
+    checks inside the launch: the same stopping iteration, iterates and
+    final residuals as every check whole; so does the no-allocation solve."""
+    from paper_2203_05027_amd.solver import solve
+    src = I.lp_instance(300, 700, 5, seed=53)
+    kw = dict(CRIT[crit], precision=precision, check_every=10, max_iter=200_000)
+    out = []
+    for full in (False, True):
+        with Solver.from_instance(src, resident="required", full_checks=full, **kw) as s:
+            while not s.iterate(5000):
+                pass
+            out.append((s.solution(), s.residuals()))
+    (g, rg), (f, rf) = out
+    say(f"resident {precision} {crit}: stop at {rg['iter']} ({rg['status']})")
+    assert rg["status"] == "converged"
+    for k in RES:
+        assert rg[k] == rf[k], (k, rg[k], rf[k])
+    for k in g:
+        assert np.array_equal(g[k], f[k]), k
+    rc, sol, res = solve(src, 200_000, noalloc=True, **kw)
+    assert res["iter"] == rg["iter"] and res["kkt"] == rg["kkt"]
+    for k in g:
+        assert np.array_equal(sol[k], g[k]), k
