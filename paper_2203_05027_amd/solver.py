@@ -63,6 +63,17 @@ class UvHistory(ctypes.Structure):
                 ("res_ax_b", ctypes.c_double), ("gap_x", ctypes.c_double)]
 
 
+def _struct_dtype(cls):
+    """numpy view of a ctypes Structure of doubles and integers."""
+    fmt = {ctypes.c_double: "<f8", ctypes.c_int64: "<i8", ctypes.c_int32: "<i4"}
+    names = [k for k, _ in cls._fields_]
+    return np.dtype({"names": names, "formats": [fmt[t] for _, t in cls._fields_],
+                     "offsets": [getattr(cls, k).offset for k in names], "itemsize": ctypes.sizeof(cls)})
+
+
+_RES_DTYPE = _struct_dtype(UvResiduals)
+
+
 class UvError(RuntimeError):
     def __init__(self, code: int, where: str):
         self.code = code
@@ -601,6 +612,17 @@ class Family:
             d["status"] = STATUS.get(d["status"], d["status"])
             out.append(d)
         return out
+
+    def status_iters(self):
+        """(status codes, iteration counts) of the nb members as numpy
+        arrays (0 running, 1 converged, 2 max_iter, 3 numeric): residuals()
+        without building a dict per member, for drivers that poll often."""
+        arr = (UvResiduals * max(self.nb, 1))()
+        rc = lib().family_residuals(self._h, arr)
+        if rc != UV_ENUMERIC:
+            _check(rc, "family_residuals")
+        a = np.frombuffer(arr, dtype=_RES_DTYPE, count=self.nb)
+        return a["status"].copy(), a["iter"].copy()
 
     def solution(self) -> dict:
         nb, n, m = self.nb, self.n, self.m

@@ -188,7 +188,7 @@ class WarmStart:
             group_iters, tail_iters, busy_slot_iters = 0, 0, 0
             while True:
                 F.iterate(chunk)
-                res = F.residuals()
+                stat, its = F.status_iters()  # 0 running, 1 converged, 2 max_iter, 3 numeric
                 group_iters += chunk
                 if nxt >= N and not retry:
                     tail_iters += chunk
@@ -198,13 +198,12 @@ class WarmStart:
                     if mem is None:
                         free.append(sl)
                         continue
-                    r = res[sl]
-                    if r["status"] == "running":
+                    if stat[sl] == 0:
                         continue
                     stopped.append(sl)
-                    iters[mem] += r["iter"]
-                    busy_slot_iters += r["iter"]
-                    ok = r["status"] == "converged"
+                    iters[mem] += its[sl]
+                    busy_slot_iters += int(its[sl])
+                    ok = stat[sl] == 1
                     if not ok and warm[sl]:
                         retry.append(mem)            # the cold fallback
                     else:
@@ -241,7 +240,7 @@ class WarmStart:
                 if tail is not None and not entered and nxt >= N and not retry and len(running) <= tail_slots:
                     for sl in running:  # the last few continue alone
                         mem = owner[sl]
-                        done_here = res[sl]["iter"]
+                        done_here = int(its[sl])
                         busy_slot_iters += done_here
                         ok, more = self._finish_alone(tail, F, sl, b_all[mem:mem + 1][0], eps,
                                                       max_iter - done_here, warm[sl], max_iter)
