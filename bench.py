@@ -34,14 +34,20 @@ SWEEP_SOURCES = ("solver.hip", "common.hpp", "setup.hpp", "spmv.hpp")
 
 
 def sources_digest() -> str:
-    """Digest of the single-problem solver's kernel sources; a traffic
-    measurement is only used while the kernels are the ones it was taken on."""
+    """Digest of the single-problem solver's kernel sources, comments and
+    blank space left out; a traffic measurement is only used while the
+    kernels are the ones it was taken on."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in (os.path.join(ROOT, "paper_2203_05027_amd", "csrc", name) for name in SWEEP_SOURCES):
-        with open(f, "rb") as fh:
-            h.update(os.path.basename(f).encode())
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)   # block comments
+        text = re.sub(r"//[^\n]*", " ", text)                  # line comments
+        text = " ".join(text.split())
+        h.update(os.path.basename(f).encode())
+        h.update(text.encode())
     return h.hexdigest()[:16]
 
 

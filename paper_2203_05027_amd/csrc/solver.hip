@@ -936,10 +936,12 @@ __device__ __forceinline__ void res_check(int m, int n, int Lr, int Lc, const in
 // A x, the lambda and u updates) and a barrier, with the FP64 residual
 // check of the other paths every check_every iterations (FP64 values of A:
 // the staged ones in FP64, from global memory in the mixed form; then a
-// fixed-order workgroup reduction) and its stop decision; the state goes
-// back to global memory at the end.  Same per-entry arithmetic as the sweep
-// kernels.  eval_only: no iteration, the residuals of the current state are
-// recorded without a stop decision (a residual query).
+// fixed-order workgroup reduction) and its stop decision; with gated the
+// check's column half is skipped when its primal half fails the stopping
+// test (res_check); the state goes back to global memory at the end.  Same
+// per-entry arithmetic as the sweep kernels.  eval_only: no iteration, the
+// residuals of the current state are recorded without a stop decision (a
+// residual query).
 template <typename T>
 __global__ void __launch_bounds__(kResThreads)
 k_resident(int m, int n, ResLayout L, int Lr, int Lc, const int *__restrict__ rp, const int *__restrict__ ci,
