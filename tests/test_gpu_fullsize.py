@@ -4,7 +4,8 @@ the 1e5-cone SOCP after 200 iterations from the zero start, every entry of
 x, z, delta and lambda against the FP64 oracle at 1e-9 of the vector's
 largest entry; the mixed form's error against the same oracle, stated per
 result; and the mixed form's iteration count to a 1e-4 KKT residual against
-the FP64 solver's on the LP."""
+the FP64 solver's on the LP; and the default primal-first checks against
+every check whole on the LP, to 1e-4."""
 import sys
 
 import numpy as np
@@ -120,3 +121,21 @@ def test_mixed_reaches_1e4_with_the_fp64_iteration_count():
         assert out[prec]["status"] == "converged"
         assert abs(out[prec]["pobj"] - inst["p_star"]) <= 2e-3 * abs(inst["p_star"])
     assert abs(out["mixed"]["iter"] - out["fp64"]["iter"]) <= 10
+
+
+def test_gated_checks_at_full_size():
+    """The 1e6 x 2e6 LP to a 1e-4 KKT residual in FP64, checks primal half
+    first (the default) against every check whole: the same stopping
+    iteration, final residuals and iterates, bit for bit."""
+    inst = I.config_instance("lp_large")
+    out = []
+    for full in (False, True):
+        with Solver.from_instance(inst, eps=1e-4, check_every=10, full_checks=full) as s:
+            assert s.iterate(40_000)
+            out.append((s.residuals(), s.solution()))
+    (rg, g), (rf, f) = out
+    say(f"lp_large gated vs whole checks: stop at {rg['iter']} / {rf['iter']}, kkt {rg['kkt']:.3e}")
+    for k in RES + ("iter", "status", "pobj_x", "gap_x"):
+        assert rg[k] == rf[k], (k, rg[k], rf[k])
+    for k in KEYS:
+        assert np.array_equal(g[k], f[k]), k
