@@ -346,3 +346,24 @@ def test_ctypes_structs_match_the_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+@pytest.mark.parametrize("field,value", [("full_checks", 2), ("full_checks", -1), ("history", -1),
+                                         ("history", (1 << 24) + 1), ("resident", 3), ("criterion", 3)])
+def test_rejects_out_of_range_options(field, value):
+    """Options the Python keywords cannot express, set on the C struct: the
+    library validates them before any device work."""
+    a = GOOD
+    rp = np.ascontiguousarray(a["rp"], dtype=np.int64)
+    ci = np.ascontiguousarray(a["ci"], dtype=np.int32)
+    va = np.ascontiguousarray(a["va"], dtype=np.float64)
+    b = np.ascontiguousarray(a["b"], dtype=np.float64)
+    c = np.ascontiguousarray(a["c"], dtype=np.float64)
+    csr = S.UvCsr(a["m"], a["n"], 3, S._ptr(rp), S._ptr(ci), S._ptr(va))
+    cones = S.UvCones(3, 0, None)
+    o = S.default_opts()
+    setattr(o, field, value)
+    h = ctypes.c_void_p()
+    rc = S.lib().solver_create(ctypes.byref(csr), S._ptr(b), S._ptr(c), ctypes.byref(cones), ctypes.byref(o),
+                               ctypes.byref(h))
+    assert rc == S.UV_EINVAL and not h.value
