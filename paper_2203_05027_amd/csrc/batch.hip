@@ -634,7 +634,7 @@ int batch_create(int32_t count, const uv_csr *A, const double *const *b, const d
     uv_default_opts(&o);
     if (opts) o = *opts;
     if (!(o.mu > 0.0) || !std::isfinite(o.mu) || o.check_every < 1 || !(o.eps_kkt >= 0.0) || o.max_iter < 0 ||
-        (o.precision != UV_FP64 && o.precision != UV_MIXED))
+        (o.precision != UV_FP64 && o.precision != UV_MIXED) || o.full_checks < 0 || o.full_checks > 1)
         return UV_EINVAL;
     const size_t ts = o.precision == UV_MIXED ? 4 : 8;
     int64_t M = 0, N = 0, NNZ = 0;

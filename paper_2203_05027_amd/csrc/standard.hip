@@ -538,6 +538,7 @@ int standard_create(const uv_csr *A, const double *b, const double *c, const uv_
     if (!A || !b || !c || !A->row_ptr || A->m < 1 || A->n < 1 || A->nnz < 0) return UV_EINVAL;
     if (!(o.mu > 0.0) || !std::isfinite(o.mu) || o.precision != UV_FP64) return UV_EINVAL;
     if (o.check_every < 1 || !(o.eps_kkt >= 0.0) || o.max_iter < 0) return UV_EINVAL;
+    if (o.full_checks < 0 || o.full_checks > 1) return UV_EINVAL;
     if (cg_iters < 0 || !(cg_tol >= 0.0) || !std::isfinite(cg_tol)) return UV_EINVAL;
     if (o.slabs_row != 0 && o.slabs_row != 1 && o.slabs_row != 2 && o.slabs_row != 4) return UV_EINVAL;
     if (o.slabs_col != 0 && o.slabs_col != 1 && o.slabs_col != 2 && o.slabs_col != 4) return UV_EINVAL;

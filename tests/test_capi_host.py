@@ -367,3 +367,34 @@ def test_rejects_out_of_range_options(field, value):
     rc = S.lib().solver_create(ctypes.byref(csr), S._ptr(b), S._ptr(c), ctypes.byref(cones), ctypes.byref(o),
                                ctypes.byref(h))
     assert rc == S.UV_EINVAL and not h.value
+
+
+def test_batch_and_baseline_reject_out_of_range_full_checks():
+    a = GOOD
+    rp = np.ascontiguousarray(a["rp"], dtype=np.int64)
+    ci = np.ascontiguousarray(a["ci"], dtype=np.int32)
+    va = np.ascontiguousarray(a["va"], dtype=np.float64)
+    b = np.ascontiguousarray(a["b"], dtype=np.float64)
+    c = np.ascontiguousarray(a["c"], dtype=np.float64)
+    csr = S.UvCsr(a["m"], a["n"], 3, S._ptr(rp), S._ptr(ci), S._ptr(va))
+    o = S.default_opts()
+    o.full_checks = 2
+    L = S.lib()
+    S._bind_batch(L)
+    h = ctypes.c_void_p()
+    csrs = (S.UvCsr * 1)(csr)
+    bp = (ctypes.c_void_p * 1)(b.ctypes.data)
+    cp = (ctypes.c_void_p * 1)(c.ctypes.data)
+    assert L.batch_create(1, csrs, bp, cp, ctypes.byref(o), ctypes.byref(h)) == S.UV_EINVAL and not h.value
+    Ls = S._bind_standard()
+    cones = S.UvCones(3, 0, None)
+    rc = Ls.standard_create(ctypes.byref(csr), S._ptr(b), S._ptr(c), ctypes.byref(cones), ctypes.byref(o), 2, 0.0,
+                            ctypes.byref(h))
+    assert rc == S.UV_EINVAL and not h.value
+    # the same arguments with full_checks = 1 pass validation (and then need a device)
+    o.full_checks = 1
+    rc = Ls.standard_create(ctypes.byref(csr), S._ptr(b), S._ptr(c), ctypes.byref(cones), ctypes.byref(o), 2, 0.0,
+                            ctypes.byref(h))
+    assert rc != S.UV_EINVAL
+    if rc == S.UV_OK:
+        Ls.standard_destroy(h)
