@@ -598,7 +598,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--history", default=None,
-                    help="write every residual check of the time-to-1e-4 runs to this JSONL file")
+                    help="write every residual check of the time-to-1e-4 runs to this JSONL file (a run that "
+                         "keeps a history evaluates every check whole, so its time is the whole-check one)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-ttk", action="store_true",
                     help="skip the time-to-1e-4 runs (with --workload lp_batched: the sweep alone)")
